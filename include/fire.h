@@ -1,0 +1,270 @@
+/*
+ * fire.h -- C ABI of the MI355X (gfx950) library for the stochastic
+ * cellular-automaton fire model of Denham & Laneri (arXiv 1701.03549).
+ *
+ * The library runs thousands of seeded fire simulations at once on one GPU,
+ * scores each simulated burn map against a reference map (Eq. 2), and
+ * provides the device-side operators of the parameter search that those
+ * scores drive (genetic algorithm, ignition scan, ensemble statistics).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Lattice: W x H cells, row 0 is north, x grows east; cell (x, y) has
+ *   linear index y*W + x. Cells outside the lattice are non-burnable.
+ *   1 <= W, H <= 4096.
+ * Directions d from a burning source to a target, with compass angle 45*d:
+ *   d = 0 N (0,-1), 1 NE (+1,-1), 2 E (+1,0), 3 SE (+1,+1),
+ *       4 S (0,+1), 5 SW (-1,+1), 6 W (-1,0),  7 NW (-1,-1).
+ * Packed burn maps: uint32 words, row-major, ceil(W/32) words per row;
+ *   cell (x, y) is bit x%32 of word y*ceil(W/32) + x/32; padding bits 0.
+ * Threshold tables: uint32 T[(y*W + x)*8 + d] for the directed edge from
+ *   source (x, y) in direction d; a coin r succeeds iff T == 0xFFFFFFFF or
+ *   r < T (so T/2^32 is the spread probability, Eq. 1, quantised by
+ *   round-half-even of p*2^32, saturating at 0xFFFFFFFF); T = 0 when the
+ *   target is outside the lattice or non-burnable.
+ * Coins: word (d % 4) of Philox4x32-10 (Salmon et al., SC'11; the
+ *   generator the paper's CUDA-implementation section names) with counter
+ *   (sim_index, step, y*W + x, d / 4) and key (seed low 32, seed high 32).
+ * Memory: "host" pointers are ordinary CPU memory, "device" pointers are
+ *   GPU memory of the context's device (e.g. a torch tensor's data_ptr()).
+ *   The caller owns every buffer it passes; landscapes and targets are
+ *   copied into context-owned device memory at load time.
+ * Streams: `stream` is a hipStream_t (NULL = the null stream). Device work
+ *   is enqueued on it and ordered with the caller's other work there;
+ *   device buffers passed in must stay alive until that work completes.
+ * Errors: every call returns a fire_status; nothing throws or aborts across
+ *   the ABI. Argument checks run before any device work is enqueued, and a
+ *   failing call leaves its outputs untouched. fire_last_error() describes
+ *   the last failure of a context. Asynchronous device errors surface as
+ *   FIRE_E_DEVICE at the next fire_sync().
+ * Threads: a context is not thread-safe; use one per host thread.
+ */
+#ifndef FIRE_H_
+#define FIRE_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fire_ctx fire_ctx; /* opaque */
+
+typedef enum {
+  FIRE_OK = 0,
+  FIRE_E_INVALID = -1,     /* bad argument or unknown id                 */
+  FIRE_E_OOM = -2,         /* device or host allocation failed           */
+  FIRE_E_DEVICE = -3,      /* HIP runtime / kernel error                 */
+  FIRE_E_UNSUPPORTED = -4  /* valid request this build cannot serve      */
+} fire_status;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`; *out receives the handle. */
+fire_status fire_ctx_create(int device, fire_ctx **out);
+/* Destroy a context and free every device object it owns (waits for the
+ * device first). NULL is ignored. */
+void fire_ctx_destroy(fire_ctx *ctx);
+/* Text of the last failure on this context ("" if none). Owned by the
+ * context, valid until its next call. */
+const char *fire_last_error(const fire_ctx *ctx);
+/* Wait for `stream` and report any asynchronous device error, including
+ * descriptors rejected by device-side validation in fire_run_dev(). */
+fire_status fire_sync(fire_ctx *ctx, void *stream);
+/* Library version string, e.g. "1.0.0 gfx950". */
+const char *fire_version(void);
+
+/* ---- landscapes and reference maps (Methods, "Forest Fire Spread
+ *      Simulation": vegetation, slope, aspect and wind rasters; Eq. 2's
+ *      reference map A) ---------------------------------------------- */
+
+typedef struct {
+  int32_t width, height;     /* W, H                                     */
+  float cell_m;              /* cell size in metres (informational)      */
+  const uint8_t *veg;        /* [H][W] 0 = non-burnable, else burnable   */
+  const float *elev_m;       /* [H][W] elevation; decides sigma's gate   */
+  const float *slope_deg;    /* [H][W] slope in degrees                  */
+  const float *aspect_deg;   /* [H][W] compass degrees the slope faces   */
+  const float *wind_to_deg;  /* [H][W] compass degrees wind blows toward */
+  uint8_t forest_class;      /* I_f = (veg == forest_class); 0 -> 1      */
+  int32_t on_device;         /* 0: host pointers, 1: device pointers     */
+} fire_landscape_desc;
+
+/* Copy a landscape into the context and precompute its per-cell record
+ * (raw covariate inputs, the 8-bit "target higher than source" mask, the
+ * aspect covariate in binary64 and the packed non-burnable map).
+ * FIRE_E_INVALID on W or H outside [1, 4096], NULL layers or a non-finite
+ * value. Synchronous. *out_id receives a small non-negative id. */
+fire_status fire_landscape_load(fire_ctx *ctx, const fire_landscape_desc *desc,
+                                int32_t *out_id);
+fire_status fire_landscape_free(fire_ctx *ctx, int32_t landscape_id);
+
+/* Copy a packed reference burn map (host pointer, H*ceil(W/32) words) for
+ * landscape `landscape_id`. Padding bits are ignored. FIRE_E_INVALID when
+ * the map is empty (Eq. 2 divides by |A|). Synchronous. */
+fire_status fire_target_load(fire_ctx *ctx, int32_t landscape_id,
+                             const uint32_t *bits, int32_t *out_target_id);
+fire_status fire_target_free(fire_ctx *ctx, int32_t target_id);
+
+/* ---- Eq. 1 thresholds ------------------------------------------------- */
+
+/* Threshold table of landscape `landscape_id` under parameters beta[5]
+ * (host, finite) into out_T (device, W*H*8 uint32, layout above), in
+ * binary64: x = b0 + b1*I_f + b2*psi + b3*omega + b4*sigma summed left to
+ * right without contraction, p = 1/(1+exp(-x)), with the covariates of the
+ * target cell (psi = cos(aspect - 315 deg) if slope > 5 deg else 0;
+ * omega = cos(wind_to - 45*d deg); sigma = slope/100 if the target is
+ * strictly higher than the source else 0). Stream-ordered. */
+fire_status fire_thresholds(fire_ctx *ctx, int32_t landscape_id,
+                            const double beta[5], uint32_t *out_T,
+                            void *stream);
+
+/* ---- simulations (Methods: propagation rules; Eq. 2 fitness) ---------- */
+
+typedef struct {
+  int32_t landscape_id;
+  int32_t target_id;     /* -1: no reference map, fitness = NaN          */
+  int32_t ign_x, ign_y;  /* ignition cell, inside the lattice            */
+  uint32_t param_index;  /* row of betas[] (and of thresholds_override)  */
+  uint32_t sim_index;    /* Philox counter word 0                        */
+  uint32_t max_steps;    /* step cap; 0xFFFFFFFF = run to extinction     */
+} fire_sim;              /* 28 bytes */
+
+typedef struct {
+  uint32_t burnt;   /* |A*|: burnt cells including the ignition          */
+  uint32_t steps;   /* CA steps executed                                 */
+  uint64_t trials;  /* coin draws: (burning source, unburnt burnable
+                       in-lattice target) pairs over all steps           */
+  double fitness;   /* Eq. 2: (|A| + |A*| - 2|A n A*|) / |A|, NaN
+                       without target                                    */
+} fire_result;      /* 24 bytes */
+
+/* Run n_sims independent simulations. Each one: if the ignition cell is
+ * non-burnable it burns nothing (burnt = steps = trials = 0, fitness 1.0
+ * with a target). Otherwise the ignition burns at step 0; at every step
+ * each cell that ignited at the previous step tries once, with its own
+ * coin, to ignite each unburnt burnable neighbour, and a target ignites if
+ * any of those coins succeeds; it stops when no cell ignited or after
+ * max_steps steps.
+ *   betas  host [n_params][5] binary64, finite
+ *   sims   host [n_sims] descriptors (checked on the host)
+ *   seed   Philox key
+ *   thresholds_override  NULL, or device [n_params][W*H*8] tables to use
+ *          instead of Eq. 1 (every sim must then use one landscape)
+ *   out    device [n_sims] results, written in sims[] order
+ *   out_maps  NULL, or device [n_sims][map_words] packed maps; sim i's
+ *          map starts at out_maps + i*map_words
+ *   map_words  words reserved per map; must be >= H*ceil(W/32) of every
+ *          sim's landscape when out_maps != NULL
+ * Results do not depend on the schedule (threads, queue sizes, threshold
+ * mode) or on the order in which simulations run. Stream-ordered. */
+fire_status fire_run(fire_ctx *ctx, const double *betas, int32_t n_params,
+                     const fire_sim *sims, int32_t n_sims, uint64_t seed,
+                     const uint32_t *thresholds_override, fire_result *out,
+                     uint32_t *out_maps, int64_t map_words, void *stream);
+
+/* As fire_run, with betas and sims already in device memory (no host
+ * staging; usable under stream capture). Descriptors are checked on the
+ * device: an invalid one yields {0, 0xFFFFFFFF, 0, NaN} and makes the next
+ * fire_sync() return FIRE_E_INVALID. */
+fire_status fire_run_dev(fire_ctx *ctx, const double *betas_dev,
+                         int32_t n_params, const fire_sim *sims_dev,
+                         int32_t n_sims, uint64_t seed,
+                         const uint32_t *thresholds_override,
+                         fire_result *out, uint32_t *out_maps,
+                         int64_t map_words, void *stream);
+
+/* ---- schedule (autotuner hooks) --------------------------------------- */
+
+typedef struct {
+  int32_t threads;       /* workgroup size: 64, 128, 256, 512 or 1024     */
+  int32_t queue_cap;     /* frontier entries kept in LDS per queue (>=64) */
+  int32_t table_mode;    /* 1: precomputed threshold table per parameter,
+                            0: thresholds evaluated per trial             */
+  int32_t wg_per_cu;     /* persistent workgroups per compute unit (>=1)  */
+} fire_schedule;
+
+/* Fix the schedule used by later fire_run/fire_run_dev calls; NULL
+ * restores the built-in choice. FIRE_E_INVALID when a field is out of
+ * range or the LDS budget cannot hold it. */
+fire_status fire_set_schedule(fire_ctx *ctx, const fire_schedule *s);
+/* The schedule the next run on landscapes of up to `max_cells` cells and
+ * `n_params` parameter vectors would use. */
+fire_status fire_get_schedule(fire_ctx *ctx, int64_t max_cells,
+                              int32_t n_params, fire_schedule *out);
+
+/* ---- genetic algorithm (Appendix B) ----------------------------------- */
+
+typedef struct {
+  int32_t elite;         /* individuals copied unchanged (e.g. 2)         */
+  double pm0;            /* mutation probability at generation 0          */
+  double mut_h;          /* mutation step half-width                      */
+  double lo, hi;         /* gene box, mutated genes are clamped to it     */
+  uint32_t generations;  /* p_m(g) = pm0 * (1 - g / generations)          */
+} fire_ga_cfg;
+
+/* One generation in place on the device. pop: device [P][G] binary64,
+ * replaced by the next population; fit: device [P][R] Eq. 2 values of the
+ * current population; mean_fit: NULL or device [P], receives the mean
+ * fitness (sum in replicate order / R). Fitness of an individual is its
+ * mean; the `elite` best (ties by index) are kept; every other slot i is
+ * the winner of a 2-tournament drawn from Philox counter (gen, i, 0, 0)
+ * under key ga_seed (indices (out0*P)>>32 and (out1*P)>>32, lower fitness
+ * wins, tie to lower index); non-elite slots elite+2k, elite+2k+1 swap
+ * genes [c, G) with c = 1 + ((out0*(G-1))>>32), counter (gen, k, 1, 0);
+ * gene j of non-elite slot i mutates iff out0*2^-32 < p_m(gen), counter
+ * (gen, i, 2, j), by mut_h*(2*out1*2^-32 - 1), clamped to [lo, hi].
+ * 1 <= P <= 1024, 2 <= G <= 16, R >= 1. Stream-ordered. */
+fire_status fire_ga_step(fire_ctx *ctx, double *pop, const double *fit,
+                         double *mean_fit, int32_t P, int32_t G, int32_t R,
+                         const fire_ga_cfg *cfg, uint32_t gen,
+                         uint64_t ga_seed, void *stream);
+
+/* A whole GA calibration on one landscape and reference map (5 genes, the
+ * betas): for g in [0, generations): evaluate every individual by R
+ * simulations (sim_index = (g*P + i)*R + r, ignition (ign_x, ign_y),
+ * run to extinction), then fire_ga_step with gen = g. One generation is
+ * captured once as a HIP graph and replayed.
+ *   pop0      host [P][5] initial population
+ *   hist_pop  device [generations][P][5]: population evaluated at g
+ *   hist_fit  device [generations][P][R]: its Eq. 2 values
+ * Stream-ordered; FIRE_E_UNSUPPORTED if graph capture fails. */
+fire_status fire_ga_run(fire_ctx *ctx, int32_t landscape_id,
+                        int32_t target_id, int32_t ign_x, int32_t ign_y,
+                        const double *pop0, int32_t P, int32_t R,
+                        const fire_ga_cfg *cfg, uint64_t sim_seed,
+                        uint64_t ga_seed, double *hist_pop, double *hist_fit,
+                        void *stream);
+
+/* ---- ensemble statistics (Methods rules; Appendix D) ------------------ */
+
+/* Accepted-ensemble statistics over N individuals with G parameters each
+ * (device params [N][G]) evaluated by R simulations (device deltas [N][R]):
+ * a simulation is accepted iff its fitness < cutoff; out_best (device,
+ * int32[1]) = individual of the minimum single fitness (first on ties);
+ * out_n (device, int32[1]) = accepted simulations; out_mean and out_sd
+ * (device [G]) = mean and standard deviation (n-1 denominator, 0 if n<2)
+ * of the parameters over the accepted simulations (each accepted
+ * replicate counts its individual once). Stream-ordered. */
+fire_status fire_ensemble(fire_ctx *ctx, const double *params,
+                          const double *deltas, int32_t N, int32_t G,
+                          int32_t R, double cutoff, int32_t *out_best,
+                          int32_t *out_n, double *out_mean, double *out_sd,
+                          void *stream);
+
+/* Ignition-scan reduction (Methods: ignition points; cutoff rule of the
+ * CUDA-implementation section) over device deltas [n_cand][R]: per
+ * candidate the mean, standard deviation (n-1) and acceptance rate
+ * #(delta < cutoff)/R, and a map acceptance/sum(acceptance), or, when no
+ * replicate is accepted anywhere, exp(-(mean - min mean)/tau) normalised
+ * to 1. All outputs device [n_cand] binary64. Stream-ordered. */
+fire_status fire_scan_reduce(fire_ctx *ctx, const double *deltas,
+                             int32_t n_cand, int32_t R, double cutoff,
+                             double tau, double *out_mean, double *out_sd,
+                             double *out_accept, double *out_post,
+                             void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIRE_H_ */
