@@ -1,0 +1,839 @@
+// Host side of the C ABI declared in include/fire.h: contexts, landscape and
+// reference-map storage, argument checks, schedule selection and the launch
+// sequences of the simulation, GA, ensemble and scan entry points.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fire.h"
+#include "fire_internal.h"
+
+using namespace firegpu;
+
+namespace {
+
+struct LandscapeHost {
+  bool live = false;
+  int W = 0, H = 0, stride = 0;
+  uint8_t forest = 1;
+  uint4 *rec = nullptr;
+  double *psi = nullptr;
+  uint32_t *blocked = nullptr;
+};
+
+struct TargetHost {
+  bool live = false;
+  int landscape_id = -1;
+  uint32_t n_ref = 0;
+  uint32_t *bits = nullptr;
+};
+
+}  // namespace
+
+struct fire_ctx {
+  int device = 0;
+  int num_cu = 256;
+  size_t max_lds = 65536;
+  std::string err;
+  std::vector<LandscapeHost> ls;
+  std::vector<TargetHost> tg;
+  LandscapeDev *d_ls = nullptr;
+  int d_ls_cap = 0;
+  TargetDev *d_tg = nullptr;
+  int d_tg_cap = 0;
+  uint32_t *d_work = nullptr;   // [0] sim counter, [1] error flag
+  uint32_t *d_ovf = nullptr;
+  size_t ovf_words = 0;
+  uint32_t *d_tables = nullptr;
+  size_t tables_words = 0;
+  // staging of host descriptors for fire_run
+  void *h_stage = nullptr;
+  void *d_stage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
+  // fixed schedule (autotuner) or built-in choice
+  bool sched_fixed = false;
+  fire_schedule sched{};
+  // GA scratch
+  double *d_ga = nullptr;
+  size_t ga_bytes = 0;
+};
+
+namespace {
+
+fire_status fail(fire_ctx *c, fire_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIP_OR_FAIL(ctx, expr)                                             \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? FIRE_E_OOM            \
+                                                   : FIRE_E_DEVICE,        \
+                  "%s: %s", #expr, hipGetErrorString(e_));                \
+  } while (0)
+
+hipError_t ensure(void **p, size_t *have, size_t want) {
+  if (*have >= want && *p) return hipSuccess;
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipMalloc(p, want);
+  if (e == hipSuccess) *have = want;
+  return e;
+}
+
+fire_status sync_tables(fire_ctx *c) {
+  // mirror the landscape and target tables on the device
+  int nl = (int)c->ls.size(), nt = (int)c->tg.size();
+  std::vector<LandscapeDev> hl(nl > 0 ? nl : 1);
+  for (int i = 0; i < nl; ++i) {
+    const LandscapeHost &L = c->ls[i];
+    LandscapeDev d{};
+    d.W = L.W; d.H = L.H; d.stride = L.stride; d.valid = L.live ? 1 : 0;
+    d.rec = L.rec; d.psi = L.psi; d.blocked = L.blocked;
+    d.forest_class = L.forest;
+    hl[i] = d;
+  }
+  std::vector<TargetDev> ht(nt > 0 ? nt : 1);
+  for (int i = 0; i < nt; ++i) {
+    const TargetHost &T = c->tg[i];
+    TargetDev d{};
+    d.landscape_id = T.landscape_id; d.valid = T.live ? 1 : 0;
+    d.n_ref = T.n_ref; d.bits = T.bits;
+    ht[i] = d;
+  }
+  if (nl > c->d_ls_cap || !c->d_ls) {
+    int cap = nl < 16 ? 16 : nl * 2;
+    if (c->d_ls) HIP_OR_FAIL(c, hipFree(c->d_ls));
+    c->d_ls = nullptr;
+    HIP_OR_FAIL(c, hipMalloc(&c->d_ls, sizeof(LandscapeDev) * cap));
+    c->d_ls_cap = cap;
+  }
+  if (nt > c->d_tg_cap || !c->d_tg) {
+    int cap = nt < 16 ? 16 : nt * 2;
+    if (c->d_tg) HIP_OR_FAIL(c, hipFree(c->d_tg));
+    c->d_tg = nullptr;
+    HIP_OR_FAIL(c, hipMalloc(&c->d_tg, sizeof(TargetDev) * cap));
+    c->d_tg_cap = cap;
+  }
+  HIP_OR_FAIL(c, hipDeviceSynchronize());
+  if (nl > 0)
+    HIP_OR_FAIL(c, hipMemcpy(c->d_ls, hl.data(), sizeof(LandscapeDev) * nl,
+                             hipMemcpyHostToDevice));
+  if (nt > 0)
+    HIP_OR_FAIL(c, hipMemcpy(c->d_tg, ht.data(), sizeof(TargetDev) * nt,
+                             hipMemcpyHostToDevice));
+  return FIRE_OK;
+}
+
+bool valid_threads(int t) {
+  return t == 64 || t == 128 || t == 256 || t == 512 || t == 1024;
+}
+
+size_t lds_bytes_for(int bitset_words, int queue_cap) {
+  return sizeof(uint32_t) * ((size_t)bitset_words + 2 * (size_t)queue_cap + 8);
+}
+
+// Built-in schedule for landscapes of up to max_cells cells: threads grow
+// with the lattice; the LDS queues take what the bitset leaves of a budget
+// chosen so that several workgroups share a compute unit.
+fire_schedule default_schedule(const fire_ctx *c, int64_t max_cells,
+                               int bitset_words, int32_t n_params) {
+  fire_schedule s{};
+  s.threads = max_cells <= 16384 ? 64 : (max_cells <= 65536 ? 128 : 256);
+  s.table_mode = n_params <= 8 ? 1 : 0;
+  size_t budget = c->max_lds;  // per CU
+  int per_cu = 1;
+  for (int k = 8; k >= 1; --k) {
+    size_t slot = budget / k;
+    if (slot >= lds_bytes_for(bitset_words, 256) && slot <= c->max_lds) {
+      per_cu = k;
+      break;
+    }
+  }
+  size_t slot = budget / per_cu;
+  if (slot > c->max_lds) slot = c->max_lds;
+  int qcap = (int)((slot / sizeof(uint32_t) - bitset_words - 8) / 2);
+  if (qcap > 16384) qcap = 16384;
+  if (qcap < 64) qcap = 64;
+  s.queue_cap = qcap;
+  s.wg_per_cu = per_cu;
+  return s;
+}
+
+struct RunPlan {
+  fire_schedule s;
+  int bitset_words;
+  int64_t max_cells;
+  size_t lds;
+  int grid;
+};
+
+fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells,
+                     int32_t n_params, int32_t n_sims, bool table_allowed,
+                     RunPlan *out) {
+  fire_schedule s = c->sched_fixed
+                        ? c->sched
+                        : default_schedule(c, max_cells, bitset_words, n_params);
+  if (!table_allowed) s.table_mode = 0;
+  size_t lds = lds_bytes_for(bitset_words, s.queue_cap);
+  if (lds > c->max_lds)
+    return fail(c, FIRE_E_UNSUPPORTED,
+                "LDS needed (%zu B: %d bitset words + 2x%d queue entries) "
+                "exceeds the device limit of %zu B",
+                lds, bitset_words, s.queue_cap, c->max_lds);
+  int per_cu_lds = (int)(c->max_lds / lds);
+  int per_cu = s.wg_per_cu < per_cu_lds ? s.wg_per_cu : per_cu_lds;
+  if (per_cu < 1) per_cu = 1;
+  int64_t grid = (int64_t)per_cu * c->num_cu;
+  if (grid > n_sims) grid = n_sims;
+  if (grid < 1) grid = 1;
+  out->s = s;
+  out->bitset_words = bitset_words;
+  out->max_cells = max_cells;
+  out->lds = lds;
+  out->grid = (int)grid;
+  return FIRE_OK;
+}
+
+fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
+                       int32_t n_params, const fire_sim *sims_dev,
+                       int32_t n_sims, uint64_t seed, const uint32_t *tables,
+                       int64_t table_stride, int32_t table_ls,
+                       fire_result *out, uint32_t *out_maps,
+                       int64_t map_words, hipStream_t st) {
+  int64_t ovf_cap = p.max_cells - p.s.queue_cap;
+  if (ovf_cap < 1) ovf_cap = 1;
+  size_t ovf_need = (size_t)p.grid * 2 * (size_t)ovf_cap * sizeof(uint32_t);
+  if (ovf_need > c->ovf_words * sizeof(uint32_t)) {
+    HIP_OR_FAIL(c, hipDeviceSynchronize());
+    size_t have = c->ovf_words * sizeof(uint32_t);
+    HIP_OR_FAIL(c, ensure((void **)&c->d_ovf, &have, ovf_need));
+    c->ovf_words = have / sizeof(uint32_t);
+  }
+  SimArgs a{};
+  a.ls = c->d_ls; a.n_ls = (int32_t)c->ls.size();
+  a.tg = c->d_tg; a.n_tg = (int32_t)c->tg.size();
+  a.betas = betas_dev; a.n_params = n_params;
+  a.sims = sims_dev; a.n_sims = n_sims;
+  a.key0 = (uint32_t)seed; a.key1 = (uint32_t)(seed >> 32);
+  a.tables = tables; a.table_stride = table_stride; a.table_ls = table_ls;
+  a.out = out; a.maps = out_maps; a.map_words = map_words;
+  a.work = c->d_work; a.error_flag = c->d_work + 1;
+  a.ovf = c->d_ovf; a.ovf_cap = ovf_cap;
+  a.queue_cap = p.s.queue_cap; a.bitset_words = p.bitset_words;
+  HIP_OR_FAIL(c, launch_fill_u32(c->d_work, 0u, 1, st));
+  HIP_OR_FAIL(c, launch_sim(a, p.s.threads, tables != nullptr, p.grid, p.lds, st));
+  return FIRE_OK;
+}
+
+bool finite_all(const float *p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *fire_version(void) { return "1.0.0 gfx950"; }
+
+fire_status fire_ctx_create(int device, fire_ctx **out) {
+  if (!out) return FIRE_E_INVALID;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+    return FIRE_E_INVALID;
+  fire_ctx *c = new (std::nothrow) fire_ctx();
+  if (!c) return FIRE_E_OOM;
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return FIRE_E_DEVICE;
+  }
+  c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                            device) == hipSuccess && lds > 0)
+    c->max_lds = (size_t)lds;
+  else
+    c->max_lds = prop.sharedMemPerBlock;
+  // raising the dynamic-LDS ceiling is advisory on this platform
+  if (set_sim_lds_limit(c->max_lds) != hipSuccess) (void)hipGetLastError();
+  if (hipMalloc(&c->d_work, 2 * sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(c->d_work, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
+      hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    fire_ctx_destroy(c);
+    return FIRE_E_DEVICE;
+  }
+  *out = c;
+  return FIRE_OK;
+}
+
+void fire_ctx_destroy(fire_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto &L : c->ls) {
+    if (L.rec) (void)hipFree(L.rec);
+    if (L.psi) (void)hipFree(L.psi);
+    if (L.blocked) (void)hipFree(L.blocked);
+  }
+  for (auto &T : c->tg)
+    if (T.bits) (void)hipFree(T.bits);
+  if (c->d_ls) (void)hipFree(c->d_ls);
+  if (c->d_tg) (void)hipFree(c->d_tg);
+  if (c->d_work) (void)hipFree(c->d_work);
+  if (c->d_ovf) (void)hipFree(c->d_ovf);
+  if (c->d_tables) (void)hipFree(c->d_tables);
+  if (c->d_stage) (void)hipFree(c->d_stage);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->d_ga) (void)hipFree(c->d_ga);
+  if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  delete c;
+}
+
+const char *fire_last_error(const fire_ctx *c) {
+  return c ? c->err.c_str() : "null context";
+}
+
+fire_status fire_sync(fire_ctx *c, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, hipStreamSynchronize((hipStream_t)stream));
+  uint32_t flag = 0;
+  HIP_OR_FAIL(c, hipMemcpy(&flag, c->d_work + 1, sizeof flag, hipMemcpyDeviceToHost));
+  if (flag) {
+    uint32_t zero = 0;
+    HIP_OR_FAIL(c, hipMemcpy(c->d_work + 1, &zero, sizeof zero, hipMemcpyHostToDevice));
+    return fail(c, FIRE_E_INVALID,
+                "a simulation descriptor was rejected on the device "
+                "(bad id, ignition outside the lattice, map or table mismatch)");
+  }
+  return FIRE_OK;
+}
+
+fire_status fire_landscape_load(fire_ctx *c, const fire_landscape_desc *d,
+                                int32_t *out_id) {
+  if (!c) return FIRE_E_INVALID;
+  if (!d || !out_id) return fail(c, FIRE_E_INVALID, "null argument");
+  if (d->width < 1 || d->height < 1 || d->width > kMaxDim || d->height > kMaxDim)
+    return fail(c, FIRE_E_INVALID, "lattice %dx%d outside [1, %d]", d->width,
+                d->height, kMaxDim);
+  if (!d->veg || !d->elev_m || !d->slope_deg || !d->aspect_deg || !d->wind_to_deg)
+    return fail(c, FIRE_E_INVALID, "null landscape layer");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  const int W = d->width, H = d->height, stride = (W + 31) / 32;
+  const int64_t n = (int64_t)W * H;
+  // host copies for validation (and staging when the input is on the host)
+  std::vector<uint8_t> veg(n);
+  std::vector<float> layers[4];
+  const float *src[4] = {d->elev_m, d->slope_deg, d->aspect_deg, d->wind_to_deg};
+  hipMemcpyKind kind = d->on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+  HIP_OR_FAIL(c, hipMemcpy(veg.data(), d->veg, n, kind));
+  for (int k = 0; k < 4; ++k) {
+    layers[k].resize(n);
+    HIP_OR_FAIL(c, hipMemcpy(layers[k].data(), src[k], n * sizeof(float), kind));
+    if (!finite_all(layers[k].data(), n))
+      return fail(c, FIRE_E_INVALID, "non-finite value in landscape layer %d", k);
+  }
+  LandscapeHost L;
+  L.W = W; L.H = H; L.stride = stride;
+  L.forest = d->forest_class ? d->forest_class : 1;
+  uint8_t *d_veg = nullptr;
+  float *d_f = nullptr;
+  hipError_t e = hipMalloc(&L.rec, sizeof(uint4) * n);
+  if (e == hipSuccess) e = hipMalloc(&L.psi, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&L.blocked, sizeof(uint32_t) * H * stride);
+  if (e == hipSuccess) e = hipMalloc(&d_veg, n);
+  if (e == hipSuccess) e = hipMalloc(&d_f, sizeof(float) * 4 * n);
+  if (e == hipSuccess) e = hipMemcpy(d_veg, veg.data(), n, hipMemcpyHostToDevice);
+  for (int k = 0; k < 4 && e == hipSuccess; ++k)
+    e = hipMemcpy(d_f + k * n, layers[k].data(), n * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = launch_preprocess(d_veg, d_f, d_f + n, d_f + 2 * n, d_f + 3 * n, W, H,
+                          stride, L.rec, L.psi, L.blocked, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (d_veg) (void)hipFree(d_veg);
+  if (d_f) (void)hipFree(d_f);
+  if (e != hipSuccess) {
+    if (L.rec) (void)hipFree(L.rec);
+    if (L.psi) (void)hipFree(L.psi);
+    if (L.blocked) (void)hipFree(L.blocked);
+    return fail(c, e == hipErrorOutOfMemory ? FIRE_E_OOM : FIRE_E_DEVICE,
+                "landscape upload: %s", hipGetErrorString(e));
+  }
+  L.live = true;
+  int id = -1;
+  for (size_t i = 0; i < c->ls.size(); ++i)
+    if (!c->ls[i].live) { id = (int)i; break; }
+  if (id < 0) { id = (int)c->ls.size(); c->ls.push_back(L); }
+  else c->ls[id] = L;
+  fire_status st = sync_tables(c);
+  if (st != FIRE_OK) return st;
+  *out_id = id;
+  return FIRE_OK;
+}
+
+fire_status fire_landscape_free(fire_ctx *c, int32_t id) {
+  if (!c) return FIRE_E_INVALID;
+  if (id < 0 || id >= (int)c->ls.size() || !c->ls[id].live)
+    return fail(c, FIRE_E_INVALID, "unknown landscape id %d", id);
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, hipDeviceSynchronize());
+  LandscapeHost &L = c->ls[id];
+  (void)hipFree(L.rec); (void)hipFree(L.psi); (void)hipFree(L.blocked);
+  L = LandscapeHost();
+  for (auto &T : c->tg)
+    if (T.live && T.landscape_id == id) {
+      (void)hipFree(T.bits);
+      T = TargetHost();
+    }
+  return sync_tables(c);
+}
+
+fire_status fire_target_load(fire_ctx *c, int32_t lid, const uint32_t *bits,
+                             int32_t *out_id) {
+  if (!c) return FIRE_E_INVALID;
+  if (!bits || !out_id) return fail(c, FIRE_E_INVALID, "null argument");
+  if (lid < 0 || lid >= (int)c->ls.size() || !c->ls[lid].live)
+    return fail(c, FIRE_E_INVALID, "unknown landscape id %d", lid);
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  const LandscapeHost &L = c->ls[lid];
+  const int64_t nw = (int64_t)L.H * L.stride;
+  std::vector<uint32_t> b(bits, bits + nw);
+  const uint32_t tail = (L.W % 32) ? ((1u << (L.W % 32)) - 1u) : 0xFFFFFFFFu;
+  uint64_t count = 0;
+  for (int y = 0; y < L.H; ++y) {
+    b[(int64_t)y * L.stride + L.stride - 1] &= tail;  // clear padding bits
+    for (int w = 0; w < L.stride; ++w) count += __builtin_popcount(b[(int64_t)y * L.stride + w]);
+  }
+  if (count == 0) return fail(c, FIRE_E_INVALID, "empty reference map (Eq. 2 divides by |A|)");
+  TargetHost T;
+  T.landscape_id = lid;
+  T.n_ref = (uint32_t)count;
+  HIP_OR_FAIL(c, hipMalloc(&T.bits, sizeof(uint32_t) * nw));
+  hipError_t e = hipMemcpy(T.bits, b.data(), sizeof(uint32_t) * nw, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(T.bits);
+    return fail(c, FIRE_E_DEVICE, "target upload: %s", hipGetErrorString(e));
+  }
+  T.live = true;
+  int id = -1;
+  for (size_t i = 0; i < c->tg.size(); ++i)
+    if (!c->tg[i].live) { id = (int)i; break; }
+  if (id < 0) { id = (int)c->tg.size(); c->tg.push_back(T); }
+  else c->tg[id] = T;
+  fire_status st = sync_tables(c);
+  if (st != FIRE_OK) return st;
+  *out_id = id;
+  return FIRE_OK;
+}
+
+fire_status fire_target_free(fire_ctx *c, int32_t id) {
+  if (!c) return FIRE_E_INVALID;
+  if (id < 0 || id >= (int)c->tg.size() || !c->tg[id].live)
+    return fail(c, FIRE_E_INVALID, "unknown target id %d", id);
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, hipDeviceSynchronize());
+  (void)hipFree(c->tg[id].bits);
+  c->tg[id] = TargetHost();
+  return sync_tables(c);
+}
+
+fire_status fire_thresholds(fire_ctx *c, int32_t lid, const double beta[5],
+                            uint32_t *out_T, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (!beta || !out_T) return fail(c, FIRE_E_INVALID, "null argument");
+  if (lid < 0 || lid >= (int)c->ls.size() || !c->ls[lid].live)
+    return fail(c, FIRE_E_INVALID, "unknown landscape id %d", lid);
+  for (int i = 0; i < 5; ++i)
+    if (!std::isfinite(beta[i])) return fail(c, FIRE_E_INVALID, "non-finite beta");
+  if (((uintptr_t)out_T) % 16 != 0)
+    return fail(c, FIRE_E_INVALID, "out_T must be 16-byte aligned");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  // parameters staged through the context's small device buffer
+  size_t have = c->ga_bytes;
+  HIP_OR_FAIL(c, hipStreamSynchronize(st));
+  HIP_OR_FAIL(c, ensure((void **)&c->d_ga, &have, 4096));
+  c->ga_bytes = have;
+  HIP_OR_FAIL(c, hipMemcpy(c->d_ga, beta, 5 * sizeof(double), hipMemcpyHostToDevice));
+  const LandscapeHost &L = c->ls[lid];
+  HIP_OR_FAIL(c, launch_thresholds(c->d_ls + lid, L.W, L.H, c->d_ga, L.forest, out_T, st));
+  return FIRE_OK;
+}
+
+static fire_status check_sims_host(fire_ctx *c, const fire_sim *sims, int32_t n,
+                                   int32_t n_params, int *bitset_words,
+                                   int64_t *max_cells, int *one_ls,
+                                   int64_t map_words, bool maps) {
+  int bw = 0;
+  int64_t mc = 1;
+  int ls_seen = -2;
+  for (int32_t i = 0; i < n; ++i) {
+    const fire_sim &s = sims[i];
+    if (s.landscape_id < 0 || s.landscape_id >= (int)c->ls.size() ||
+        !c->ls[s.landscape_id].live)
+      return fail(c, FIRE_E_INVALID, "sim %d: unknown landscape id %d", i, s.landscape_id);
+    const LandscapeHost &L = c->ls[s.landscape_id];
+    if (s.target_id != -1) {
+      if (s.target_id < 0 || s.target_id >= (int)c->tg.size() || !c->tg[s.target_id].live)
+        return fail(c, FIRE_E_INVALID, "sim %d: unknown target id %d", i, s.target_id);
+      if (c->tg[s.target_id].landscape_id != s.landscape_id)
+        return fail(c, FIRE_E_INVALID, "sim %d: target %d belongs to another landscape", i,
+                    s.target_id);
+    }
+    if (s.ign_x < 0 || s.ign_x >= L.W || s.ign_y < 0 || s.ign_y >= L.H)
+      return fail(c, FIRE_E_INVALID, "sim %d: ignition (%d, %d) outside the %dx%d lattice", i,
+                  s.ign_x, s.ign_y, L.W, L.H);
+    if (s.param_index >= (uint32_t)n_params)
+      return fail(c, FIRE_E_INVALID, "sim %d: param_index %u >= n_params %d", i,
+                  s.param_index, n_params);
+    const int words = L.H * L.stride;
+    if (maps && words > map_words)
+      return fail(c, FIRE_E_INVALID, "sim %d: map needs %d words > map_words %lld", i, words,
+                  (long long)map_words);
+    if (words > bw) bw = words;
+    if ((int64_t)L.W * L.H > mc) mc = (int64_t)L.W * L.H;
+    if (ls_seen == -2) ls_seen = s.landscape_id;
+    else if (ls_seen != s.landscape_id) ls_seen = -1;
+  }
+  *bitset_words = bw;
+  *max_cells = mc;
+  *one_ls = ls_seen;
+  return FIRE_OK;
+}
+
+// Table-mode thresholds: one table per parameter vector into context
+// scratch, computed on the stream right before the simulations.
+static fire_status build_tables(fire_ctx *c, int lid, const double *betas_dev,
+                                int32_t n_params, hipStream_t st,
+                                const uint32_t **tables, int64_t *stride) {
+  const LandscapeHost &L = c->ls[lid];
+  const int64_t per = (int64_t)L.W * L.H * 8;
+  const size_t need = sizeof(uint32_t) * (size_t)per * n_params;
+  if (need > c->tables_words * sizeof(uint32_t)) {
+    HIP_OR_FAIL(c, hipStreamSynchronize(st));
+    HIP_OR_FAIL(c, hipDeviceSynchronize());
+    size_t have = c->tables_words * sizeof(uint32_t);
+    HIP_OR_FAIL(c, ensure((void **)&c->d_tables, &have, need));
+    c->tables_words = have / sizeof(uint32_t);
+  }
+  for (int32_t p = 0; p < n_params; ++p)
+    HIP_OR_FAIL(c, launch_thresholds(c->d_ls + lid, L.W, L.H, betas_dev + 5 * p,
+                                     L.forest, c->d_tables + per * p, st));
+  *tables = c->d_tables;
+  *stride = per;
+  return FIRE_OK;
+}
+
+fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
+                     const fire_sim *sims, int32_t n_sims, uint64_t seed,
+                     const uint32_t *override_T, fire_result *out,
+                     uint32_t *out_maps, int64_t map_words, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (n_sims < 0 || n_params < 1 || !betas || (n_sims > 0 && (!sims || !out)))
+    return fail(c, FIRE_E_INVALID, "bad sizes or null pointers");
+  for (int64_t i = 0; i < (int64_t)n_params * 5; ++i)
+    if (!std::isfinite(betas[i])) return fail(c, FIRE_E_INVALID, "non-finite beta %lld", (long long)i);
+  if (n_sims == 0) return FIRE_OK;
+  int bw = 0, one_ls = -1;
+  int64_t mc = 1;
+  fire_status st0 = check_sims_host(c, sims, n_sims, n_params, &bw, &mc, &one_ls, map_words,
+                                    out_maps != nullptr);
+  if (st0 != FIRE_OK) return st0;
+  if (override_T && one_ls < 0)
+    return fail(c, FIRE_E_INVALID, "thresholds_override needs every sim on one landscape");
+  if (override_T && ((uintptr_t)override_T) % 16 != 0)
+    return fail(c, FIRE_E_INVALID, "thresholds_override must be 16-byte aligned");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  RunPlan plan;
+  fire_status ps = plan_run(c, bw, mc, n_params, n_sims, one_ls >= 0, &plan);
+  if (ps != FIRE_OK) return ps;
+  // stage descriptors and parameters
+  const size_t bbytes = sizeof(double) * 5 * (size_t)n_params;
+  const size_t boff = (sizeof(fire_sim) * (size_t)n_sims + 255) / 256 * 256;
+  const size_t need = boff + bbytes;
+  if (c->stage_pending) {
+    HIP_OR_FAIL(c, hipEventSynchronize(c->stage_done));
+    c->stage_pending = false;
+  }
+  if (need > c->stage_bytes) {
+    HIP_OR_FAIL(c, hipDeviceSynchronize());
+    if (c->h_stage) HIP_OR_FAIL(c, hipHostFree(c->h_stage));
+    if (c->d_stage) HIP_OR_FAIL(c, hipFree(c->d_stage));
+    c->h_stage = c->d_stage = nullptr;
+    c->stage_bytes = 0;
+    size_t sz = need * 2;
+    HIP_OR_FAIL(c, hipHostMalloc(&c->h_stage, sz, hipHostMallocDefault));
+    HIP_OR_FAIL(c, hipMalloc(&c->d_stage, sz));
+    c->stage_bytes = sz;
+  }
+  memcpy(c->h_stage, sims, sizeof(fire_sim) * (size_t)n_sims);
+  memcpy((char *)c->h_stage + boff, betas, bbytes);
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_stage, c->h_stage, need, hipMemcpyHostToDevice, st));
+  HIP_OR_FAIL(c, hipEventRecord(c->stage_done, st));
+  c->stage_pending = true;
+  const fire_sim *d_sims = (const fire_sim *)c->d_stage;
+  const double *d_betas = (const double *)((char *)c->d_stage + boff);
+  const uint32_t *tables = override_T;
+  int64_t tstride = 0;
+  if (override_T) {
+    tstride = mc * 8;
+  } else if (plan.s.table_mode) {
+    fire_status tsx = build_tables(c, one_ls, d_betas, n_params, st, &tables, &tstride);
+    if (tsx != FIRE_OK) return tsx;
+  }
+  return launch_run(c, plan, d_betas, n_params, d_sims, n_sims, seed, tables, tstride,
+                    tables ? one_ls : -1, out, out_maps, map_words, st);
+}
+
+fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
+                         const fire_sim *sims_dev, int32_t n_sims, uint64_t seed,
+                         const uint32_t *override_T, fire_result *out,
+                         uint32_t *out_maps, int64_t map_words, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (n_sims < 0 || n_params < 1 || !betas_dev || (n_sims > 0 && (!sims_dev || !out)))
+    return fail(c, FIRE_E_INVALID, "bad sizes or null pointers");
+  if (n_sims == 0) return FIRE_OK;
+  // sized for every loaded landscape (the descriptors stay on the device)
+  int bw = 0, nlive = 0, lid = -1;
+  int64_t mc = 1;
+  for (size_t i = 0; i < c->ls.size(); ++i) {
+    const LandscapeHost &L = c->ls[i];
+    if (!L.live) continue;
+    ++nlive;
+    lid = (int)i;
+    if (L.H * L.stride > bw) bw = L.H * L.stride;
+    if ((int64_t)L.W * L.H > mc) mc = (int64_t)L.W * L.H;
+  }
+  if (nlive == 0) return fail(c, FIRE_E_INVALID, "no landscape loaded");
+  if (override_T && nlive != 1)
+    return fail(c, FIRE_E_INVALID, "thresholds_override needs exactly one loaded landscape");
+  if (override_T && ((uintptr_t)override_T) % 16 != 0)
+    return fail(c, FIRE_E_INVALID, "thresholds_override must be 16-byte aligned");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  RunPlan plan;
+  fire_status ps = plan_run(c, bw, mc, n_params, n_sims, nlive == 1, &plan);
+  if (ps != FIRE_OK) return ps;
+  const uint32_t *tables = override_T;
+  int64_t tstride = 0;
+  if (override_T) {
+    tstride = mc * 8;
+  } else if (plan.s.table_mode) {
+    fire_status tsx = build_tables(c, lid, betas_dev, n_params, st, &tables, &tstride);
+    if (tsx != FIRE_OK) return tsx;
+  }
+  return launch_run(c, plan, betas_dev, n_params, sims_dev, n_sims, seed, tables, tstride,
+                    tables ? lid : -1, out, out_maps, map_words, st);
+}
+
+fire_status fire_set_schedule(fire_ctx *c, const fire_schedule *s) {
+  if (!c) return FIRE_E_INVALID;
+  if (!s) {
+    c->sched_fixed = false;
+    return FIRE_OK;
+  }
+  if (!valid_threads(s->threads) || s->queue_cap < 64 || s->wg_per_cu < 1 ||
+      s->wg_per_cu > 32 || (s->table_mode != 0 && s->table_mode != 1))
+    return fail(c, FIRE_E_INVALID, "schedule field out of range");
+  if (lds_bytes_for(0, s->queue_cap) > c->max_lds)
+    return fail(c, FIRE_E_INVALID, "queue_cap %d does not fit LDS", s->queue_cap);
+  c->sched = *s;
+  c->sched_fixed = true;
+  return FIRE_OK;
+}
+
+fire_status fire_get_schedule(fire_ctx *c, int64_t max_cells, int32_t n_params,
+                              fire_schedule *out) {
+  if (!c) return FIRE_E_INVALID;
+  if (!out || max_cells < 1) return fail(c, FIRE_E_INVALID, "bad arguments");
+  if (c->sched_fixed) {
+    *out = c->sched;
+    return FIRE_OK;
+  }
+  // bitset words of a square-ish lattice of max_cells cells
+  int64_t side = (int64_t)std::ceil(std::sqrt((double)max_cells));
+  int bw = (int)(side * ((side + 31) / 32));
+  *out = default_schedule(c, max_cells, bw, n_params);
+  return FIRE_OK;
+}
+
+fire_status fire_ga_step(fire_ctx *c, double *pop, const double *fit, double *mean_fit,
+                         int32_t P, int32_t G, int32_t R, const fire_ga_cfg *cfg,
+                         uint32_t gen, uint64_t ga_seed, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (!pop || !fit || !cfg) return fail(c, FIRE_E_INVALID, "null argument");
+  if (P < 1 || P > 1024 || G < 2 || G > 16 || R < 1 || cfg->elite < 0 || cfg->elite > P ||
+      cfg->generations < 1 || !(cfg->lo <= cfg->hi))
+    return fail(c, FIRE_E_INVALID, "GA sizes or configuration out of range");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, launch_ga_step(pop, fit, mean_fit, P, G, R, cfg->elite, cfg->pm0, cfg->mut_h,
+                                cfg->lo, cfg->hi, gen, nullptr, cfg->generations,
+                                (uint32_t)ga_seed, (uint32_t)(ga_seed >> 32),
+                                (hipStream_t)stream));
+  return FIRE_OK;
+}
+
+fire_status fire_ga_run(fire_ctx *c, int32_t lid, int32_t tid, int32_t ign_x, int32_t ign_y,
+                        const double *pop0, int32_t P, int32_t R, const fire_ga_cfg *cfg,
+                        uint64_t sim_seed, uint64_t ga_seed, double *hist_pop,
+                        double *hist_fit, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (!pop0 || !cfg || !hist_pop || !hist_fit) return fail(c, FIRE_E_INVALID, "null argument");
+  const int G = 5;
+  if (P < 1 || P > 1024 || R < 1 || (int64_t)P * R > (1 << 24) || cfg->elite < 0 ||
+      cfg->elite > P || cfg->generations < 1 || !(cfg->lo <= cfg->hi))
+    return fail(c, FIRE_E_INVALID, "GA sizes or configuration out of range");
+  if (lid < 0 || lid >= (int)c->ls.size() || !c->ls[lid].live)
+    return fail(c, FIRE_E_INVALID, "unknown landscape id %d", lid);
+  if (tid < 0 || tid >= (int)c->tg.size() || !c->tg[tid].live || c->tg[tid].landscape_id != lid)
+    return fail(c, FIRE_E_INVALID, "unknown target id %d for landscape %d", tid, lid);
+  const LandscapeHost &L = c->ls[lid];
+  if (ign_x < 0 || ign_x >= L.W || ign_y < 0 || ign_y >= L.H)
+    return fail(c, FIRE_E_INVALID, "ignition outside the lattice");
+  for (int i = 0; i < P * G; ++i)
+    if (!std::isfinite(pop0[i])) return fail(c, FIRE_E_INVALID, "non-finite initial population");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t user = (hipStream_t)stream;
+  const int n = P * R;
+  // scratch: pop [P*G] | fit [n] | results [n] | sims [n] | gen counter
+  const size_t o_pop = 0;
+  const size_t o_fit = o_pop + sizeof(double) * P * G;
+  const size_t o_res = (o_fit + sizeof(double) * n + 255) / 256 * 256;
+  const size_t o_sims = (o_res + sizeof(fire_result) * n + 255) / 256 * 256;
+  const size_t o_gen = (o_sims + sizeof(fire_sim) * n + 255) / 256 * 256;
+  const size_t need = o_gen + 256;
+  HIP_OR_FAIL(c, hipDeviceSynchronize());
+  size_t have = c->ga_bytes;
+  HIP_OR_FAIL(c, ensure((void **)&c->d_ga, &have, need));
+  c->ga_bytes = have;
+  char *base = (char *)c->d_ga;
+  double *d_pop = (double *)(base + o_pop);
+  double *d_fit = (double *)(base + o_fit);
+  fire_result *d_res = (fire_result *)(base + o_res);
+  fire_sim *d_sims = (fire_sim *)(base + o_sims);
+  uint32_t *d_gen = (uint32_t *)(base + o_gen);
+  std::vector<fire_sim> hs(n);
+  for (int i = 0; i < P; ++i)
+    for (int r = 0; r < R; ++r) {
+      fire_sim s{};
+      s.landscape_id = lid; s.target_id = tid; s.ign_x = ign_x; s.ign_y = ign_y;
+      s.param_index = (uint32_t)i; s.sim_index = 0; s.max_steps = 0xFFFFFFFFu;
+      hs[i * R + r] = s;
+    }
+  HIP_OR_FAIL(c, hipMemcpy(d_sims, hs.data(), sizeof(fire_sim) * n, hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, hipMemcpy(d_pop, pop0, sizeof(double) * P * G, hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, launch_fill_u32(d_gen, 0u, 1, user));
+  // plan the simulation launch for this landscape only (on-the-fly thresholds,
+  // since the parameters change every generation)
+  RunPlan plan;
+  fire_status ps = plan_run(c, L.H * L.stride, (int64_t)L.W * L.H, P, n, false, &plan);
+  if (ps != FIRE_OK) return ps;
+  int64_t ovf_cap = plan.max_cells - plan.s.queue_cap;
+  if (ovf_cap < 1) ovf_cap = 1;
+  size_t ovf_need = (size_t)plan.grid * 2 * (size_t)ovf_cap * sizeof(uint32_t);
+  if (ovf_need > c->ovf_words * sizeof(uint32_t)) {
+    size_t h2 = c->ovf_words * sizeof(uint32_t);
+    HIP_OR_FAIL(c, ensure((void **)&c->d_ovf, &h2, ovf_need));
+    c->ovf_words = h2 / sizeof(uint32_t);
+  }
+  SimArgs a{};
+  a.ls = c->d_ls; a.n_ls = (int32_t)c->ls.size();
+  a.tg = c->d_tg; a.n_tg = (int32_t)c->tg.size();
+  a.betas = d_pop; a.n_params = P;
+  a.sims = d_sims; a.n_sims = n;
+  a.key0 = (uint32_t)sim_seed; a.key1 = (uint32_t)(sim_seed >> 32);
+  a.tables = nullptr; a.table_stride = 0; a.table_ls = -1;
+  a.out = d_res; a.maps = nullptr; a.map_words = 0;
+  a.work = c->d_work; a.error_flag = c->d_work + 1;
+  a.ovf = c->d_ovf; a.ovf_cap = ovf_cap;
+  a.queue_cap = plan.s.queue_cap; a.bitset_words = plan.bitset_words;
+
+  // capture one generation
+  hipStream_t cap = nullptr;
+  HIP_OR_FAIL(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) e = launch_ga_prepare(d_gen, d_sims, P, R, c->d_work, d_pop, G, hist_pop, cap);
+  if (e == hipSuccess) e = launch_sim(a, plan.s.threads, false, plan.grid, plan.lds, cap);
+  if (e == hipSuccess) e = launch_ga_gather(d_gen, d_res, P, R, d_fit, hist_fit, cap);
+  if (e == hipSuccess)
+    e = launch_ga_step(d_pop, d_fit, nullptr, P, G, R, cfg->elite, cfg->pm0, cfg->mut_h, cfg->lo,
+                       cfg->hi, 0u, d_gen, cfg->generations, (uint32_t)ga_seed,
+                       (uint32_t)(ga_seed >> 32), cap);
+  hipError_t e2 = hipStreamEndCapture(cap, &graph);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    return fail(c, FIRE_E_UNSUPPORTED, "GA graph capture failed: %s", hipGetErrorString(e));
+  }
+  for (uint32_t g = 0; g < cfg->generations && e == hipSuccess; ++g)
+    e = hipGraphLaunch(exec, user);
+  hipError_t e3 = hipStreamSynchronize(user);
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap);
+  if (e == hipSuccess) e = e3;
+  if (e != hipSuccess) return fail(c, FIRE_E_DEVICE, "GA graph launch: %s", hipGetErrorString(e));
+  return FIRE_OK;
+}
+
+fire_status fire_ensemble(fire_ctx *c, const double *params, const double *deltas, int32_t N,
+                          int32_t G, int32_t R, double cutoff, int32_t *out_best,
+                          int32_t *out_n, double *out_mean, double *out_sd, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (!params || !deltas || !out_best || !out_n || !out_mean || !out_sd)
+    return fail(c, FIRE_E_INVALID, "null argument");
+  if (N < 1 || G < 1 || R < 1 || (int64_t)N * R > (1LL << 30))
+    return fail(c, FIRE_E_INVALID, "ensemble sizes out of range");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, launch_ensemble(params, deltas, N, G, R, cutoff, out_best, out_n, out_mean,
+                                 out_sd, (hipStream_t)stream));
+  return FIRE_OK;
+}
+
+fire_status fire_scan_reduce(fire_ctx *c, const double *deltas, int32_t n_cand, int32_t R,
+                             double cutoff, double tau, double *out_mean, double *out_sd,
+                             double *out_accept, double *out_post, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (!deltas || !out_mean || !out_sd || !out_accept || !out_post)
+    return fail(c, FIRE_E_INVALID, "null argument");
+  if (n_cand < 1 || R < 1 || !(tau > 0.0))
+    return fail(c, FIRE_E_INVALID, "scan sizes out of range or tau <= 0");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, launch_scan_reduce(deltas, n_cand, R, cutoff, tau, out_mean, out_sd,
+                                    out_accept, out_post, (hipStream_t)stream));
+  return FIRE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Internal declarations shared by the host ABI layer and the kernel file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fire.h"
+
+namespace firegpu {
+
+constexpr int kMaxDim = 4096;          // 12-bit x and y in frontier entries
+constexpr uint32_t kSaturated = 0xFFFFFFFFu;
+
+// Device-side landscape entry (one per loaded landscape id).
+struct LandscapeDev {
+  int32_t W, H, stride, valid;  // stride = ceil(W/32) words per bitset row
+  const uint4 *rec;             // [H*W] {slope f32, aspect f32, wind f32,
+                                //        veg | up_mask << 8}
+  const double *psi;            // [H*W] aspect covariate (binary64)
+  const uint32_t *blocked;      // [H*stride] 1 = non-burnable or padding
+  uint32_t forest_class;
+  uint32_t pad0;
+};
+
+struct TargetDev {
+  int32_t landscape_id, valid;
+  uint32_t n_ref, pad0;
+  const uint32_t *bits;  // [H*stride]
+};
+
+struct SimArgs {
+  const LandscapeDev *ls;
+  int32_t n_ls;
+  const TargetDev *tg;
+  int32_t n_tg;
+  const double *betas;
+  int32_t n_params;
+  const fire_sim *sims;
+  int32_t n_sims;
+  uint32_t key0, key1;
+  const uint32_t *tables;  // NULL or [n_params][table_stride]
+  int64_t table_stride;
+  int32_t table_ls;        // landscape the tables belong to
+  fire_result *out;
+  uint32_t *maps;
+  int64_t map_words;
+  uint32_t *work;          // work-stealing counter (zeroed before launch)
+  uint32_t *error_flag;    // set to 1 on an invalid descriptor
+  uint32_t *ovf;           // per workgroup: 2 * ovf_cap frontier entries
+  int64_t ovf_cap;
+  int32_t queue_cap;       // frontier entries per queue held in LDS
+  int32_t bitset_words;    // LDS words reserved for the burn bitset
+};
+
+// Launchers (fire_kernels.hip). Each returns the hipError_t of its launch.
+hipError_t launch_preprocess(const uint8_t *veg, const float *elev,
+                             const float *slope, const float *aspect,
+                             const float *wind, int W, int H, int stride,
+                             uint4 *rec, double *psi, uint32_t *blocked,
+                             hipStream_t s);
+hipError_t launch_thresholds(const LandscapeDev *ls_dev_entry, int W, int H,
+                             const double *beta_dev, uint32_t forest,
+                             uint32_t *out, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_sim(const SimArgs &a, int threads, bool table, int grid,
+                      size_t lds_bytes, hipStream_t s);
+hipError_t set_sim_lds_limit(size_t bytes);
+hipError_t launch_ga_step(double *pop, const double *fit, double *mean_fit,
+                          int P, int G, int R, int elite, double pm0,
+                          double h, double lo, double hi, uint32_t gen,
+                          uint32_t *gen_ptr, uint32_t generations,
+                          uint32_t key0, uint32_t key1, hipStream_t s);
+hipError_t launch_ga_prepare(const uint32_t *gen_ptr, fire_sim *sims, int P,
+                             int R, uint32_t *work, const double *pop, int G,
+                             double *hist_pop, hipStream_t s);
+hipError_t launch_ga_gather(const uint32_t *gen_ptr, const fire_result *res,
+                            int P, int R, double *fit, double *hist_fit,
+                            hipStream_t s);
+hipError_t launch_ensemble(const double *params, const double *deltas, int N,
+                           int G, int R, double cutoff, int32_t *out_best,
+                           int32_t *out_n, double *out_mean, double *out_sd,
+                           hipStream_t s);
+hipError_t launch_scan_reduce(const double *deltas, int n_cand, int R,
+                              double cutoff, double tau, double *out_mean,
+                              double *out_sd, double *out_accept,
+                              double *out_post, hipStream_t s);
+
+}  // namespace firegpu

@@ -1,0 +1,294 @@
+"""Python binding of the C ABI in include/fire.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libfiregpu.so`` built in this
+package directory; PyTorch provides device memory and streams. There is no
+fallback: if the library is missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # imported before the library so one HIP runtime serves both
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfiregpu.so")
+
+SIM_DTYPE = np.dtype([("landscape_id", "<i4"), ("target_id", "<i4"), ("ign_x", "<i4"),
+                      ("ign_y", "<i4"), ("param_index", "<u4"), ("sim_index", "<u4"),
+                      ("max_steps", "<u4")])
+RESULT_DTYPE = np.dtype([("burnt", "<u4"), ("steps", "<u4"), ("trials", "<u8"),
+                         ("fitness", "<f8")])
+assert SIM_DTYPE.itemsize == 28 and RESULT_DTYPE.itemsize == 24
+RUN_TO_EXTINCTION = 0xFFFFFFFF
+
+STATUS = {0: "FIRE_OK", -1: "FIRE_E_INVALID", -2: "FIRE_E_OOM", -3: "FIRE_E_DEVICE",
+          -4: "FIRE_E_UNSUPPORTED"}
+
+EXPORTS = ["fire_ctx_create", "fire_ctx_destroy", "fire_last_error", "fire_sync", "fire_version",
+           "fire_landscape_load", "fire_landscape_free", "fire_target_load", "fire_target_free",
+           "fire_thresholds", "fire_run", "fire_run_dev", "fire_set_schedule",
+           "fire_get_schedule", "fire_ga_step", "fire_ga_run", "fire_ensemble",
+           "fire_scan_reduce"]
+
+
+class FireError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class LandscapeDesc(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("cell_m", ctypes.c_float),
+                ("veg", ctypes.c_void_p), ("elev_m", ctypes.c_void_p),
+                ("slope_deg", ctypes.c_void_p), ("aspect_deg", ctypes.c_void_p),
+                ("wind_to_deg", ctypes.c_void_p), ("forest_class", ctypes.c_uint8),
+                ("on_device", ctypes.c_int32)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
+                ("table_mode", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class GACfg(ctypes.Structure):
+    _fields_ = [("elite", ctypes.c_int32), ("pm0", ctypes.c_double), ("mut_h", ctypes.c_double),
+                ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("generations", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfiregpu.so (no GPU calls); raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with `python -m paper_1701_03549_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, u32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
+                                   ctypes.c_int64, ctypes.c_uint64, ctypes.c_double)
+    sig = {
+        "fire_ctx_create": (i32, [ctypes.c_int, ctypes.POINTER(vp)]),
+        "fire_ctx_destroy": (None, [vp]),
+        "fire_last_error": (ctypes.c_char_p, [vp]),
+        "fire_sync": (i32, [vp, vp]),
+        "fire_version": (ctypes.c_char_p, []),
+        "fire_landscape_load": (i32, [vp, ctypes.POINTER(LandscapeDesc), ctypes.POINTER(i32)]),
+        "fire_landscape_free": (i32, [vp, i32]),
+        "fire_target_load": (i32, [vp, i32, vp, ctypes.POINTER(i32)]),
+        "fire_target_free": (i32, [vp, i32]),
+        "fire_thresholds": (i32, [vp, i32, vp, vp, vp]),
+        "fire_run": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
+        "fire_run_dev": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
+        "fire_set_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
+        "fire_get_schedule": (i32, [vp, i64, i32, ctypes.POINTER(Schedule)]),
+        "fire_ga_step": (i32, [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(GACfg), u32, u64, vp]),
+        "fire_ga_run": (i32, [vp, i32, i32, i32, i32, vp, i32, i32, ctypes.POINTER(GACfg), u64,
+                              u64, vp, vp, vp]),
+        "fire_ensemble": (i32, [vp, vp, vp, i32, i32, i32, dbl, vp, vp, vp, vp, vp]),
+        "fire_scan_reduce": (i32, [vp, vp, i32, i32, dbl, dbl, vp, vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return int(torch.cuda.current_stream().cuda_stream)
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def results_to_numpy(res: torch.Tensor) -> np.ndarray:
+    """Device result buffer (uint8 [n, 24]) -> numpy structured array."""
+    return res.cpu().numpy().reshape(-1).view(RESULT_DTYPE)
+
+
+def make_sims(n, landscape_id=0, target_id=-1, ign=(0, 0), param_index=0, sim_index=None,
+              max_steps=RUN_TO_EXTINCTION) -> np.ndarray:
+    s = np.zeros(n, dtype=SIM_DTYPE)
+    s["landscape_id"] = landscape_id
+    s["target_id"] = target_id
+    s["ign_x"] = np.asarray(ign)[..., 0] if np.ndim(ign) > 1 else ign[0]
+    s["ign_y"] = np.asarray(ign)[..., 1] if np.ndim(ign) > 1 else ign[1]
+    s["param_index"] = param_index
+    s["sim_index"] = np.arange(n, dtype=np.uint32) if sim_index is None else sim_index
+    s["max_steps"] = max_steps
+    return s
+
+
+class FireGPU:
+    """A library context on one GPU (wraps fire_ctx)."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the fire library has no CPU path")
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        h = ctypes.c_void_p()
+        st = self.lib.fire_ctx_create(device, ctypes.byref(h))
+        if st != 0:
+            raise FireError(st, "fire_ctx_create failed")
+        self.ctx = h
+        self.dims = {}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.fire_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise FireError(st, self.lib.fire_last_error(self.ctx).decode())
+
+    def sync(self, stream=None):
+        self._check(self.lib.fire_sync(self.ctx, _stream(stream)))
+
+    # -- landscapes and targets ---------------------------------------------
+    def load_landscape(self, ls: dict, forest_class: int = 1) -> int:
+        veg = np.ascontiguousarray(ls["veg"], dtype=np.uint8)
+        H, W = veg.shape
+        f = [np.ascontiguousarray(ls[k], dtype=np.float32)
+             for k in ("elev_m", "slope_deg", "aspect_deg", "wind_to_deg")]
+        d = LandscapeDesc(W, H, float(ls.get("cell_m", 30.0)), veg.ctypes.data, f[0].ctypes.data,
+                          f[1].ctypes.data, f[2].ctypes.data, f[3].ctypes.data, forest_class, 0)
+        out = ctypes.c_int32()
+        self._check(self.lib.fire_landscape_load(self.ctx, ctypes.byref(d), ctypes.byref(out)))
+        self.dims[out.value] = (W, H)
+        return out.value
+
+    def free_landscape(self, lid: int):
+        self._check(self.lib.fire_landscape_free(self.ctx, lid))
+        self.dims.pop(lid, None)
+
+    def load_target(self, lid: int, bits: np.ndarray) -> int:
+        b = np.ascontiguousarray(bits, dtype=np.uint32)
+        W, H = self.dims[lid]
+        assert b.shape == (H, (W + 31) // 32)
+        out = ctypes.c_int32()
+        self._check(self.lib.fire_target_load(self.ctx, lid, b.ctypes.data, ctypes.byref(out)))
+        return out.value
+
+    def free_target(self, tid: int):
+        self._check(self.lib.fire_target_free(self.ctx, tid))
+
+    # -- Eq. 1 ---------------------------------------------------------------
+    def thresholds(self, lid: int, beta, stream=None) -> torch.Tensor:
+        W, H = self.dims[lid]
+        b = (ctypes.c_double * 5)(*[float(v) for v in beta])
+        out = torch.empty((H, W, 8), dtype=torch.int32, device=self.device)
+        self._check(self.lib.fire_thresholds(self.ctx, lid, b, _ptr(out), _stream(stream)))
+        return out
+
+    # -- simulations ---------------------------------------------------------
+    def map_words(self, sims: np.ndarray) -> int:
+        ids = np.unique(sims["landscape_id"])
+        return max(self.dims[int(i)][1] * ((self.dims[int(i)][0] + 31) // 32) for i in ids)
+
+    def run(self, betas, sims: np.ndarray, seed: int, override: torch.Tensor | None = None,
+            want_maps: bool = False, stream=None):
+        """fire_run with host parameters/descriptors; returns (results uint8[n,24], maps)."""
+        b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64).reshape(-1, 5))
+        s = np.ascontiguousarray(sims, dtype=SIM_DTYPE)
+        n = len(s)
+        res = torch.empty((max(n, 1), 24), dtype=torch.uint8, device=self.device)
+        maps, mw = None, 0
+        if want_maps and n:
+            mw = self.map_words(s)
+            maps = torch.empty((n, mw), dtype=torch.int32, device=self.device)
+        self._check(self.lib.fire_run(self.ctx, b.ctypes.data, len(b), s.ctypes.data, n,
+                                      int(seed) & (2 ** 64 - 1), _ptr(override), _ptr(res),
+                                      _ptr(maps), mw, _stream(stream)))
+        return res[:n], maps
+
+    def run_dev(self, betas_dev: torch.Tensor, sims_dev: torch.Tensor, n_sims: int, seed: int,
+                out: torch.Tensor, maps: torch.Tensor | None = None, map_words: int = 0,
+                override: torch.Tensor | None = None, stream=None):
+        """fire_run_dev: every buffer already on the device (no host staging)."""
+        n_params = betas_dev.numel() // 5
+        self._check(self.lib.fire_run_dev(self.ctx, _ptr(betas_dev), n_params, _ptr(sims_dev),
+                                          n_sims, int(seed) & (2 ** 64 - 1), _ptr(override),
+                                          _ptr(out), _ptr(maps), map_words, _stream(stream)))
+
+    # -- schedule ------------------------------------------------------------
+    def set_schedule(self, threads=None, queue_cap=None, table_mode=None, wg_per_cu=None,
+                     reset=False):
+        if reset:
+            self._check(self.lib.fire_set_schedule(self.ctx, None))
+            return
+        s = Schedule(int(threads), int(queue_cap), int(table_mode), int(wg_per_cu))
+        self._check(self.lib.fire_set_schedule(self.ctx, ctypes.byref(s)))
+
+    def get_schedule(self, max_cells: int, n_params: int = 1) -> dict:
+        s = Schedule()
+        self._check(self.lib.fire_get_schedule(self.ctx, int(max_cells), int(n_params),
+                                               ctypes.byref(s)))
+        return s.as_dict()
+
+    # -- GA, ensemble, scan --------------------------------------------------
+    @staticmethod
+    def ga_cfg(elite=2, pm0=0.2, mut_h=1.0, lo=-30.0, hi=30.0, generations=50) -> GACfg:
+        return GACfg(elite, pm0, mut_h, lo, hi, generations)
+
+    def ga_step(self, pop: torch.Tensor, fit: torch.Tensor, cfg: GACfg, gen: int, ga_seed: int,
+                mean_fit: torch.Tensor | None = None, stream=None):
+        P, G = pop.shape
+        R = fit.shape[1]
+        self._check(self.lib.fire_ga_step(self.ctx, _ptr(pop), _ptr(fit), _ptr(mean_fit), P, G, R,
+                                          ctypes.byref(cfg), int(gen), int(ga_seed) & (2 ** 64 - 1),
+                                          _stream(stream)))
+
+    def ga_run(self, lid: int, tid: int, ign, pop0: np.ndarray, R: int, cfg: GACfg,
+               sim_seed: int, ga_seed: int, stream=None):
+        p0 = np.ascontiguousarray(pop0, dtype=np.float64)
+        P = p0.shape[0]
+        gens = int(cfg.generations)
+        hist_pop = torch.empty((gens, P, 5), dtype=torch.float64, device=self.device)
+        hist_fit = torch.empty((gens, P, R), dtype=torch.float64, device=self.device)
+        self._check(self.lib.fire_ga_run(self.ctx, lid, tid, int(ign[0]), int(ign[1]),
+                                         p0.ctypes.data, P, R, ctypes.byref(cfg),
+                                         int(sim_seed) & (2 ** 64 - 1),
+                                         int(ga_seed) & (2 ** 64 - 1), _ptr(hist_pop),
+                                         _ptr(hist_fit), _stream(stream)))
+        return hist_pop, hist_fit
+
+    def ensemble(self, params: torch.Tensor, deltas: torch.Tensor, cutoff: float, stream=None):
+        N, G = params.shape
+        R = deltas.numel() // N
+        best = torch.empty(1, dtype=torch.int32, device=self.device)
+        n = torch.empty(1, dtype=torch.int32, device=self.device)
+        mean = torch.empty(G, dtype=torch.float64, device=self.device)
+        sd = torch.empty(G, dtype=torch.float64, device=self.device)
+        self._check(self.lib.fire_ensemble(self.ctx, _ptr(params), _ptr(deltas), N, G, R,
+                                           float(cutoff), _ptr(best), _ptr(n), _ptr(mean),
+                                           _ptr(sd), _stream(stream)))
+        return {"best_individual": best, "n_accepted": n, "mean": mean, "sd": sd}
+
+    def scan_reduce(self, deltas: torch.Tensor, cutoff: float, tau: float = 0.1, stream=None):
+        C, R = deltas.shape
+        outs = [torch.empty(C, dtype=torch.float64, device=self.device) for _ in range(4)]
+        self._check(self.lib.fire_scan_reduce(self.ctx, _ptr(deltas), C, R, float(cutoff),
+                                              float(tau), *[_ptr(o) for o in outs],
+                                              _stream(stream)))
+        return dict(zip(("mean", "sd", "accept", "posterior"), outs))

@@ -156,3 +156,14 @@ def unpack_bits(bits: np.ndarray, W: int) -> np.ndarray:
     shifts = np.arange(32, dtype=np.uint32)
     full = ((b[:, :, None] >> shifts[None, None, :]) & 1).astype(bool).reshape(H, wpr * 32)
     return full[:, :W]
+
+
+def nearest_burnable(veg: np.ndarray, x: int, y: int):
+    """The burnable cell closest (Euclidean, ties by row then column) to (x, y);
+    the workloads' "ignition at the centre" uses this so that a non-burnable
+    blob at the exact centre does not leave every replicate empty."""
+    v = np.asarray(veg)
+    ys, xs = np.nonzero(v != 0)
+    d2 = (xs - x) ** 2 + (ys - y) ** 2
+    k = np.lexsort((xs, ys, d2))[0]
+    return int(xs[k]), int(ys[k])

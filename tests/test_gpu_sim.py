@@ -1,0 +1,252 @@
+"""GPU parity of the simulation path against the CPU oracle (through the C ABI).
+
+Bar: burn maps, burnt counts, step counts and trial counts bit-exact; Eq. 2
+fitness bit-exact (one IEEE division of the same integers); Eq. 1 thresholds
+within one unit of the oracle's (exp and cos differ by an ulp between libms).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import BETA_STAR, SEED, TARGET_SEED, compare_with_oracle, oracle_target, say
+from paper_1701_03549_amd import synth
+
+pytestmark = pytest.mark.gpu
+U32 = 0xFFFFFFFF
+BETA_SUB_64 = (-0.9, -0.5, 0.3, 0.8, 1.0)  # contained fires on the 64x64 landscape
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    from paper_1701_03549_amd import fire
+    assert torch.cuda.is_available()
+    ctx = fire.FireGPU(0)
+    yield ctx
+    ctx.close()
+
+
+def _np_maps(maps):
+    return None if maps is None else maps.cpu().numpy().view(np.uint32)
+
+
+def _res(res):
+    from paper_1701_03549_amd import fire
+    return fire.results_to_numpy(res)
+
+
+@pytest.mark.parametrize("W,H,seed", [(64, 64, 101), (37, 23, 5), (100, 67, 6), (512, 512, 102)])
+def test_thresholds_within_one_unit(g, W, H, seed):
+    say(f"thresholds {W}x{H}")
+    ls = synth.make_landscape(W, H, seed)
+    lid = g.load_landscape(ls)
+    for beta in [(0, 0, 0, 0, 0), BETA_STAR, (-5, -10, 5, 18.1, -5), (2.5, -7.0, 11.0, -3.3, 25.0)]:
+        Tg = g.thresholds(lid, beta).cpu().numpy().view(np.uint32).astype(np.int64)
+        To = oracle.thresholds(ls, beta).astype(np.int64)
+        d = np.abs(Tg - To)
+        assert d.max() <= 1, beta
+        assert np.mean(d > 0) < 1e-3, beta
+    g.free_landscape(lid)
+
+
+def test_config1_plain_64(g):
+    """64x64, landscape seed 101, ignition at the centre, 200 replicates to
+    extinction, with beta = 0 and a subcritical vector; maps and counts."""
+    from paper_1701_03549_amd import fire
+    W = H = 64
+    ls = synth.make_landscape(W, H, 101)
+    centre = synth.nearest_burnable(ls["veg"], 32, 32)
+    betas = np.array([(0, 0, 0, 0, 0), BETA_SUB_64], dtype=np.float64)
+    ref, _ = oracle_target(ls, betas[1], centre, lo=0.02, hi=0.5)
+    lid = g.load_landscape(ls)
+    tid = g.load_target(lid, ref)
+    T = [oracle.thresholds(ls, b) for b in betas]
+    for p in range(2):
+        say(f"config1 param {p}")
+        sims = fire.make_sims(200, lid, tid, centre, param_index=p)
+        res, maps = g.run(betas, sims, SEED, want_maps=True)
+        g.sync()
+        compare_with_oracle(ls, T, _res(res), _np_maps(maps), sims, SEED, ref_bits=ref)
+    g.free_landscape(lid)
+
+
+@pytest.mark.parametrize("mode", ["table", "onthefly", "override"])
+def test_threshold_modes_and_schedules(g, mode):
+    """Table mode, per-trial thresholds and oracle-injected tables all give the
+    oracle's results; several schedules including tiny LDS queues that force
+    the global spill path."""
+    import torch
+    from paper_1701_03549_amd import fire
+    W, H = 100, 67
+    ls = synth.make_landscape(W, H, 6)
+    beta = np.array([(-0.4, -0.3, 0.2, 0.8, 1.0), (0.3, 0.0, 0.0, 0.0, 0.0)])
+    ref, _ = oracle_target(ls, beta[0], (50, 33), lo=0.01)
+    lid = g.load_landscape(ls)
+    tid = g.load_target(lid, ref)
+    T = [oracle.thresholds(ls, b) for b in beta]
+    override = None
+    if mode == "override":
+        override = torch.from_numpy(np.stack(T).view(np.int32).copy()).cuda()
+    sims = fire.make_sims(48, lid, tid, (50, 33), param_index=np.arange(48) % 2)
+    for threads, qcap, wg in [(64, 64, 4), (256, 64, 2), (1024, 128, 1), (128, 4096, 8)]:
+        say(f"modes {mode} threads={threads} qcap={qcap}")
+        g.set_schedule(threads, qcap, 1 if mode == "table" else 0, wg)
+        res, maps = g.run(beta, sims, SEED, override=override, want_maps=True)
+        g.sync()
+        compare_with_oracle(ls, T, _res(res), _np_maps(maps), sims, SEED, ref_bits=ref)
+    g.set_schedule(reset=True)
+    g.free_landscape(lid)
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (1, 40), (33, 1), (2, 2), (31, 33), (65, 7)])
+def test_ragged_and_degenerate_lattices(g, W, H):
+    from paper_1701_03549_amd import fire
+    say(f"ragged {W}x{H}")
+    ls = synth.random_small_landscape(W, H, seed=W * 100 + H, p_blocked=0.1)
+    ls["veg"][0, 0] = 2
+    beta = np.array([(0.8, -0.2, 0.3, 0.5, 1.0)])
+    T = [oracle.thresholds(ls, beta[0])]
+    lid = g.load_landscape(ls)
+    n = 40
+    rng = np.random.default_rng(W * H)
+    ign = np.stack([rng.integers(0, W, n), rng.integers(0, H, n)], axis=1)
+    sims = fire.make_sims(n, lid, -1, ign)
+    res, maps = g.run(beta, sims, SEED, want_maps=True)
+    g.sync()
+    r = _res(res)
+    compare_with_oracle(ls, T, r, _np_maps(maps), sims, SEED)
+    assert np.all(np.isnan(r["fitness"]))
+    g.free_landscape(lid)
+
+
+def test_edge_cases(g):
+    from paper_1701_03549_amd import fire
+    W, H = 48, 40
+    ls = synth.make_landscape(W, H, 8)
+    ys, xs = np.nonzero(ls["veg"] == 0)
+    blocked_ign = (int(xs[0]), int(ys[0]))
+    betas = np.array([(-1000, 0, 0, 0, 0), (1000, 0, 0, 0, 0), (0.2, 0.1, 0.1, 0.5, 0.5)])
+    T = [oracle.thresholds(ls, b) for b in betas]
+    c = synth.nearest_burnable(ls["veg"], 24, 20)
+    ref, _ = oracle_target(ls, betas[2], c, lo=0.01)
+    lid = g.load_landscape(ls)
+    tid = g.load_target(lid, ref)
+    sims = np.concatenate([
+        fire.make_sims(3, lid, tid, c, param_index=0),                       # p = 0
+        fire.make_sims(4, lid, tid, c, param_index=1,
+                       max_steps=np.array([0, 1, 5, U32], dtype=np.uint32)),  # p = 1, caps
+        fire.make_sims(3, lid, tid, blocked_ign, param_index=2),             # non-burnable ign
+        fire.make_sims(4, lid, tid, (0, 0), param_index=2),                  # corner
+        fire.make_sims(4, lid, -1, (W - 1, H - 1), param_index=2,
+                       max_steps=np.array([0, 1, 2, 3], dtype=np.uint32)),
+    ])
+    say("edge cases")
+    res, maps = g.run(betas, sims, SEED, want_maps=True)
+    g.sync()
+    r = _res(res)
+    compare_with_oracle(ls, T, r, _np_maps(maps), sims, SEED, ref_bits=None)
+    assert np.all(r["burnt"][:3] == 1)
+    assert tuple(r["burnt"][7:10]) == (0, 0, 0) and np.all(r["fitness"][7:10] == 1.0)
+    assert r["steps"][3] == 0 and r["burnt"][3] == 1
+    # empty batch, bad arguments, empty target
+    res0, _ = g.run(betas, sims[:0], SEED)
+    with pytest.raises(fire.FireError):
+        bad = sims[:1].copy()
+        bad["ign_x"] = W
+        g.run(betas, bad, SEED)
+    with pytest.raises(fire.FireError):
+        bad = sims[:1].copy()
+        bad["param_index"] = 3
+        g.run(betas, bad, SEED)
+    with pytest.raises(fire.FireError):
+        g.load_target(lid, np.zeros_like(ref))
+    with pytest.raises(fire.FireError):
+        g.run(np.array([(np.nan, 0, 0, 0, 0)]), sims[:1], SEED)
+    g.free_landscape(lid)
+
+
+def test_device_descriptor_validation(g):
+    import torch
+    from paper_1701_03549_amd import fire
+    ls = synth.make_landscape(32, 32, 9)
+    lid = g.load_landscape(ls)
+    sims = fire.make_sims(4, lid, -1, (16, 16))
+    sims["ign_y"][2] = 99  # outside the lattice
+    say("device validation")
+    d_sims = torch.from_numpy(sims.view(np.uint8).copy()).cuda()
+    d_betas = torch.tensor([[0.1, 0, 0, 0, 0]], dtype=torch.float64, device="cuda")
+    out = torch.empty((4, 24), dtype=torch.uint8, device="cuda")
+    g.run_dev(d_betas, d_sims, 4, SEED, out)
+    with pytest.raises(fire.FireError):
+        g.sync()
+    r = fire.results_to_numpy(out)
+    assert r["steps"][2] == U32 and np.isnan(r["fitness"][2])
+    assert r["burnt"][0] >= 1
+    g.sync()  # the error flag was consumed
+    g.free_landscape(lid)
+
+
+def test_config2_512_sampled(g):
+    """512x512 at the calibration vector, 1280 replicates in one launch with
+    the default schedule (the benchmark's launch); 24 sampled simulations
+    recomputed by the oracle, and properties on all of them."""
+    import torch
+    from paper_1701_03549_amd import fire
+    W = H = 512
+    ls = synth.make_landscape(W, H, 102)
+    centre = synth.nearest_burnable(ls["veg"], 256, 256)
+    ref, _ = oracle_target(ls, BETA_STAR, centre, lo=0.01, hi=0.15)
+    T = [oracle.thresholds(ls, BETA_STAR)]
+    lid = g.load_landscape(ls)
+    tid = g.load_target(lid, ref)
+    n = 1280
+    sims = fire.make_sims(n, lid, tid, centre)
+    say("config2 512^2 x 1280")
+    d_sims = torch.from_numpy(sims.view(np.uint8).copy()).cuda()
+    d_betas = torch.tensor([BETA_STAR], dtype=torch.float64, device="cuda")
+    out = torch.empty((n, 24), dtype=torch.uint8, device="cuda")
+    mw = H * (W // 32)
+    maps = torch.empty((n, mw), dtype=torch.int32, device="cuda")
+    g.run_dev(d_betas, d_sims, n, SEED, out, maps, mw)
+    g.sync()
+    r = fire.results_to_numpy(out)
+    m = maps.cpu().numpy().view(np.uint32)
+    sample = list(range(0, n, n // 24))[:24]
+    compare_with_oracle(ls, T, r, m, sims, SEED, ref_bits=ref, idx=sample)
+    pop = np.array([int(np.unpackbits(m[i].view(np.uint8)).sum()) for i in range(n)])
+    assert np.array_equal(pop, r["burnt"])
+    assert np.all(r["burnt"] >= 1) and np.all(r["trials"] >= r["burnt"] - 1)
+    g.free_landscape(lid)
+
+
+def test_mixed_landscapes_one_launch(g):
+    """Uneven batch: four landscapes of different sizes and per-simulation
+    parameter vectors drawn from the search box, in one launch."""
+    from paper_1701_03549_amd import fire
+    sizes = [(128, 128, 101), (256, 256, 102), (96, 160, 103), (200, 120, 104)]
+    lss = [synth.make_landscape(W, H, s) for W, H, s in sizes]
+    lids = [g.load_landscape(ls) for ls in lss]
+    rng = np.random.default_rng(77)
+    n = 64
+    betas = rng.uniform(-3, 3, size=(n, 5))
+    betas[:, 0] -= 1.0
+    which = np.arange(n) % 4
+    centres = [synth.nearest_burnable(ls["veg"], W // 2, H // 2)
+               for ls, (W, H, _) in zip(lss, sizes)]
+    sims = np.concatenate([fire.make_sims(1, lids[w], -1, centres[w],
+                                          param_index=i, sim_index=1000 + i)
+                           for i, w in enumerate(which)])
+    say("mixed landscapes")
+    res, maps = g.run(betas, sims, SEED, want_maps=True)
+    g.sync()
+    r = _res(res)
+    m = _np_maps(maps)
+    for i in range(0, n, 3):
+        w = which[i]
+        ls = lss[w]
+        T = {int(i): oracle.thresholds(ls, betas[i])}
+        sd = sims[i:i + 1].copy()
+        sd["param_index"] = 0
+        compare_with_oracle(ls, [T[int(i)]], r[i:i + 1], m[i:i + 1], sd, SEED)
+    for lid in lids:
+        g.free_landscape(lid)
