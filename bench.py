@@ -1,0 +1,238 @@
+"""Benchmark: fire simulations/s and neighbour-trials/s at 512x512 on one GPU.
+
+One step = one pass of the simulation hot path over the calibration batch:
+the Eq. 1 threshold table of the calibration vector, then 1280 seeded
+replicate simulations (ignition at the centre, run to extinction) on a
+512x512 synthetic landscape with the Eq. 2 fitness against a reference map
+fused in. Inputs (landscape, reference map, descriptors, parameters) are
+resident on the device before timing starts.
+
+Also reported: the simulation kernel's achieved algorithmic bandwidth against
+the HBM peak, the CPU oracle timed on the host cores on the same batch, and
+(unless --no-ga) the wall time of a whole GA calibration (64 individuals x 20
+replicates x 50 generations) as a captured-graph batched run versus plain
+one-simulation-per-launch evaluation with a host synchronisation after each.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fire simulations/sec + neighbour-trials/sec at 512², GA wall-time batched vs plain"
+HBM_PEAK_GBS = 8000.0
+BETA_STAR = (-1.15, -0.5, 0.3, 0.8, 1.0)
+SIM_SEED = 0x5EED0001
+TARGET_SEED = 0x7A26E7
+GA_SEED = 0x6A00001
+W = H = 512
+LANDSCAPE_SEED = 102
+N_SIMS = 1280
+PROFILE_PMC = os.path.join(ROOT, "profiles", "sim_kernel_512x512_1280_pmc.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1701_03549_amd", "csrc", "fire_kernels.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def reference_fire(g, ls, lid, centre):
+    """Reference map: the first replicate under the reference seed whose burnt
+    fraction lies in [1%, 15%] and that does not touch the lattice border,
+    simulated by the library at the calibration vector."""
+    from paper_1701_03549_amd import fire
+    n = 256
+    sims = fire.make_sims(n, lid, -1, centre)
+    res, maps = g.run(np.array([BETA_STAR]), sims, TARGET_SEED, want_maps=True)
+    g.sync()
+    r = fire.results_to_numpy(res)
+    m = maps.cpu().numpy().view(np.uint32).reshape(n, H, -1)
+    for k in range(n):
+        frac = r["burnt"][k] / (W * H)
+        mk = m[k]
+        border = mk[0].any() or mk[-1].any() or (mk[:, 0] & 1).any() or ((mk[:, -1] >> 31) & 1).any()
+        if 0.01 <= frac <= 0.15 and not border:
+            return mk.copy(), k
+    raise RuntimeError("no contained reference fire among the first 256 replicates")
+
+
+def cpu_baseline(ls, centre, ref, threads, budget_s=12.0):
+    """The oracle (plain C, binary64) on the same batch, on host threads."""
+    import oracle
+    sims = [dict(param=0, ign=centre, sim_index=i) for i in range(N_SIMS)]
+    t0 = time.perf_counter()
+    done = 0
+    trials = 0
+    while True:
+        T = oracle.thresholds(ls, BETA_STAR)
+        out = oracle.run_batch(ls["veg"], [T], sims, SIM_SEED, ref_bits=ref, threads=threads)
+        done += len(out)
+        trials += sum(o["trials"] for o in out)
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "sims/s", "cores": threads, "kind": "oracle",
+            "trials_per_s": trials / dt,
+            "sample": f"{done // N_SIMS} pass(es) over the full batch ({N_SIMS} replicates at "
+                      f"512x512, thresholds + simulation + Eq. 2), {dt:.1f} s"}
+
+
+def pmc_traffic(sim_ms):
+    if not os.path.exists(PROFILE_PMC):
+        return None
+    with open(PROFILE_PMC) as f:
+        p = json.load(f)
+    if p.get("kernel_source_sha") != kernel_sha():
+        return None
+    return p.get("hbm_bytes_per_launch")
+
+
+def run_ga(g, lid, tid, centre, plain: bool):
+    """Batched (graph-captured) GA and, optionally, the plain per-simulation
+    GA; returns wall times and a bit-identity check of the two histories."""
+    import torch
+    from paper_1701_03549_amd import ga
+    rng = np.random.default_rng(2024)
+    pop0 = rng.uniform(-30.0, 30.0, size=(64, 5))
+    out = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hb = ga.run_batched(g, lid, tid, centre, pop0, R=20, generations=50, sim_seed=SIM_SEED,
+                        ga_seed=GA_SEED)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    out["batched_s"] = tb
+    out["batched_sims_per_s"] = 64 * 20 * 50 / tb
+    log(f"batched GA: {tb:.2f} s")
+    est = ga.recovered(g, hb, cutoff=0.3)
+    out["recovered"] = est
+    if plain:
+        t0 = time.perf_counter()
+        hp = ga.run_plain(g, lid, tid, centre, pop0, R=20, generations=50, sim_seed=SIM_SEED,
+                          ga_seed=GA_SEED,
+                          progress=lambda k: log(f"plain GA generation {k} done") if k % 5 == 0
+                          else None)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        out["plain_s"] = tp
+        out["plain_sims_per_s"] = 64 * 20 * 50 / tp
+        out["speedup"] = tp / tb
+        out["identical_trajectory"] = bool(torch.equal(hb[0], hp[0]) and torch.equal(hb[1], hp[1]))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ga", action="store_true", help="skip the GA wall-time comparison")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain GA run")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only; simulations are independent, so N "
+              "GPUs would each run their own share of the batch (see the sharding design). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1701_03549_amd import fire, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    g = fire.FireGPU(0)
+    ls = synth.make_landscape(W, H, LANDSCAPE_SEED)
+    centre = synth.nearest_burnable(ls["veg"], W // 2, H // 2)
+    lid = g.load_landscape(ls)
+    ref, ref_k = reference_fire(g, ls, lid, centre)
+    tid = g.load_target(lid, ref)
+    log(f"reference fire: replicate {ref_k}, {int(np.unpackbits(ref.view(np.uint8)).sum())} cells")
+
+    sims = fire.make_sims(N_SIMS, lid, tid, centre)
+    d_sims = torch.from_numpy(sims.view(np.uint8).copy()).cuda()
+    d_beta = torch.tensor([BETA_STAR], dtype=torch.float64, device="cuda")
+    out = torch.empty((N_SIMS, 24), dtype=torch.uint8, device="cuda")
+    table = torch.empty((H, W, 8), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    sched = g.get_schedule(W * H, 1)
+
+    def step(ev=None):
+        g.thresholds(lid, BETA_STAR, out=table, stream=stream)
+        if ev is not None:
+            ev[0].record(stream)
+        g.run_dev(d_beta, d_sims, N_SIMS, SIM_SEED, out, override=table, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    g.sync()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.sync()
+    sim_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    r = fire.results_to_numpy(out)
+    trials = int(r["trials"].sum())
+    burnt = int(r["burnt"].sum())
+    ms_per_step = dt / args.steps * 1e3
+    sims_per_s = N_SIMS * args.steps / dt
+    trials_per_s = trials * args.steps / dt
+    alg_bytes = 4 * trials + 8 * burnt + 24 * N_SIMS
+    achieved = alg_bytes / (sim_ms * 1e-3) / 1e9
+    log(f"{ms_per_step:.3f} ms/step, sim kernel {sim_ms:.3f} ms, {sims_per_s:.0f} sims/s, "
+        f"{trials_per_s:.3e} trials/s, mean burnt {burnt / N_SIMS:.1f}, mean trials "
+        f"{trials / N_SIMS:.1f}")
+
+    result = {
+        "metric": METRIC, "value": sims_per_s, "unit": "sims/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "calibration batch: 512x512 synthetic landscape (seed 102), "
+                               "1280 replicates at the calibration vector, ignition at the "
+                               "centre, run to extinction, Eq. 2 vs a contained reference fire",
+                   "lattice": [W, H], "sims_per_step": N_SIMS, "beta": list(BETA_STAR),
+                   "ignition": list(centre), "schedule": sched, "threshold_mode": "table"},
+        "trials_per_s": trials_per_s,
+        "mean_burnt": burnt / N_SIMS, "mean_trials": trials / N_SIMS,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(sim_ms),
+                     "kernel": "sim_kernel", "kernel_ms": sim_ms,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"CPU oracle baseline on {threads} threads ...")
+        result["cpu_baseline"] = cpu_baseline(ls, centre, ref, threads)
+    if not args.no_ga:
+        log("GA calibration runs ...")
+        result["ga"] = run_ga(g, lid, tid, centre, plain=not args.no_plain)
+    g.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

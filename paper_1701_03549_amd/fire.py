@@ -194,10 +194,14 @@ class FireGPU:
         self._check(self.lib.fire_target_free(self.ctx, tid))
 
     # -- Eq. 1 ---------------------------------------------------------------
-    def thresholds(self, lid: int, beta, stream=None) -> torch.Tensor:
+    def thresholds(self, lid: int, beta, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+        """Eq. 1 table [H][W][8] (int32 storage of the uint32 thresholds)."""
         W, H = self.dims[lid]
         b = (ctypes.c_double * 5)(*[float(v) for v in beta])
-        out = torch.empty((H, W, 8), dtype=torch.int32, device=self.device)
+        if out is None:
+            out = torch.empty((H, W, 8), dtype=torch.int32, device=self.device)
+        assert out.numel() == H * W * 8 and out.is_contiguous()
         self._check(self.lib.fire_thresholds(self.ctx, lid, b, _ptr(out), _stream(stream)))
         return out
 
