@@ -142,6 +142,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ga", action="store_true", help="skip the GA wall-time comparison")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain GA run")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain elementwise copy of 256 MiB (read) + 256 MiB (write) "
+                         "three times, to scale the profiler's HBM byte counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -180,6 +183,14 @@ def main():
         if ev is not None:
             ev[1].record(stream)
 
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x torch.neg over 268435456 B in, 268435456 B out")
+        del a, b
     for _ in range(args.warmup):
         step()
     g.sync()

@@ -149,7 +149,7 @@ bool valid_threads(int t) {
 }
 
 size_t lds_bytes_for(int bitset_words, int queue_cap) {
-  return sizeof(uint32_t) * ((size_t)bitset_words + 2 * (size_t)queue_cap + 8);
+  return sizeof(uint32_t) * ((size_t)bitset_words + 2 * (size_t)queue_cap + 16);
 }
 
 // Built-in schedule for landscapes of up to max_cells cells: threads grow
@@ -158,7 +158,7 @@ size_t lds_bytes_for(int bitset_words, int queue_cap) {
 fire_schedule default_schedule(const fire_ctx *c, int64_t max_cells,
                                int bitset_words, int32_t n_params) {
   fire_schedule s{};
-  s.threads = max_cells <= 16384 ? 64 : (max_cells <= 65536 ? 128 : 256);
+  s.threads = max_cells <= 4096 ? 64 : (max_cells <= 16384 ? 128 : 256);
   s.table_mode = n_params <= 8 ? 1 : 0;
   size_t budget = c->max_lds;  // per CU
   int per_cu = 1;
@@ -171,7 +171,7 @@ fire_schedule default_schedule(const fire_ctx *c, int64_t max_cells,
   }
   size_t slot = budget / per_cu;
   if (slot > c->max_lds) slot = c->max_lds;
-  int qcap = (int)((slot / sizeof(uint32_t) - bitset_words - 8) / 2);
+  int qcap = (int)((slot / sizeof(uint32_t) - bitset_words - 16) / 2);
   if (qcap > 16384) qcap = 16384;
   if (qcap < 64) qcap = 64;
   s.queue_cap = qcap;

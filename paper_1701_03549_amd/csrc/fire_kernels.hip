@@ -37,10 +37,10 @@ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1,
                                            uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0;
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo2 = 0xCD9E8D57u * c2;
-    const uint32_t hi2 = __umulhi(0xCD9E8D57u, c2);
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p2 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo2 = (uint32_t)p2, hi2 = (uint32_t)(p2 >> 32);
     c0 = hi2 ^ c1 ^ k0;
     c1 = lo2;
     c2 = hi0 ^ c3 ^ k1;
@@ -171,52 +171,66 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
 //   * the cells that ignited at the previous step form the frontier queue,
 //     entries x | y << 12 (the top byte is scratch), held in LDS up to
 //     queue_cap entries and in a per-workgroup global spill area beyond;
-//   * each step runs in two phases separated by barriers. Phase 1 reads the
-//     bitset only (so eligibility is judged against the burn state at the
-//     start of the step), draws the coins of the eligible edges of every
-//     frontier cell and stores the mask of successful directions in the
-//     entry's top byte. Phase 2 sets the bits of the successful targets with
-//     atomic ORs; the lane whose OR flipped a bit owns that new cell and
-//     appends it to the next frontier (wave ballot prefix sums give the
-//     offsets, one LDS atomic per wave reserves the space), counting it and
-//     its overlap with the reference map for Eq. 2.
+//   * work is spread one lane per directed edge (frontier cell, direction),
+//     so a small front still fills a wave and every lane's dependent chain
+//     is one bitset read, one 4-byte threshold and one Philox call;
+//   * each step runs in two phases separated by barriers. Phase 1 only
+//     reads the bitset, so eligibility is judged against the burn state at
+//     the start of the step; it draws the coins of the eligible edges and a
+//     wave ballot gathers each cell's 8 outcomes into the entry's top byte.
+//     Phase 2 sets the bits of the successful targets with atomic ORs; the
+//     lane whose OR flipped a bit owns that new cell and appends it to the
+//     next frontier (ballot + prefix count, one LDS atomic per wave).
 // Every coin is a pure function of (sim_index, step, source cell, direction)
 // and ignition is an OR, so the burnt set, step count, trial count and
 // fitness do not depend on thread order or on the schedule.
 // ---------------------------------------------------------------------------
 
-template <int BLOCK>
-__device__ __forceinline__ uint32_t q_get(const uint32_t *lq, const uint32_t *gq,
-                                          uint32_t cap, uint32_t i) {
-  return i < cap ? lq[i] : gq[i - cap];
+typedef const __attribute__((address_space(1))) uint32_t gmem_cu32;
+typedef __attribute__((address_space(1))) uint32_t gmem_u32;
+typedef const __attribute__((address_space(1))) double gmem_cf64;
+
+__device__ __forceinline__ uint4 load_rec(const uint4 *base, int64_t t) {
+  gmem_cu32 *q = (gmem_cu32 *)(base + t);
+  return make_uint4(q[0], q[1], q[2], q[3]);
 }
 
-template <int BLOCK>
-__device__ __forceinline__ void q_put(uint32_t *lq, uint32_t *gq, uint32_t cap,
-                                      uint32_t i, uint32_t v) {
-  if (i < cap) lq[i] = v;
-  else gq[i - cap] = v;
-}
+// Offsets of direction d, packed 2 bits per direction (value + 1).
+__device__ __forceinline__ int dir_dx(int d) { return ((425 >> (2 * d)) & 3) - 1; }
+__device__ __forceinline__ int dir_dy(int d) { return ((6800 >> (2 * d)) & 3) - 1; }
 
 __device__ __forceinline__ uint32_t lane_prefix(uint64_t ballot) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
 }
 
-enum CtlSlot { kSim = 0, kLen0 = 1, kTrials = 4, kNew = 5, kInter = 6, kCtlWords = 8 };
+enum CtlSlot { kSim = 0, kLen0 = 1, kTrials = 4, kNew = 5, kInter = 6, kRowLo = 7, kRowHi = 8,
+               kCtlWords = 16 };
+
+// register-resident rounds of the small-front step (fronts of up to
+// kRegRounds * BLOCK / 8 cells)
+constexpr int kRegRounds = 2;
 
 template <int BLOCK, bool TABLE>
 __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
   extern __shared__ uint32_t lds[];
-  uint32_t *const bits = lds;
-  uint32_t *qa = lds + a.bitset_words;
-  uint32_t *qb = qa + a.queue_cap;
-  uint32_t *const ctl = qb + a.queue_cap;
-  uint32_t *ga = a.ovf + (int64_t)blockIdx.x * 2 * a.ovf_cap;
-  uint32_t *gb = ga + a.ovf_cap;
+  const int bw = a.bitset_words;
   const uint32_t cap = (uint32_t)a.queue_cap;
+  uint32_t *const bits = lds;
+  uint32_t *const ctl = lds + bw + 2 * cap;
+  gmem_u32 *const spill_base = (gmem_u32 *)(a.ovf + (int64_t)blockIdx.x * 2 * a.ovf_cap);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+
+  // frontier queue q (0 or 1), entry i
+  auto q_load = [&](uint32_t q, uint32_t i) -> uint32_t {
+    if (i < cap) return lds[bw + q * cap + i];
+    return spill_base[(int64_t)q * a.ovf_cap + (i - cap)];
+  };
+  auto q_store = [&](uint32_t q, uint32_t i, uint32_t v) {
+    if (i < cap) lds[bw + q * cap + i] = v;
+    else spill_base[(int64_t)q * a.ovf_cap + (i - cap)] = v;
+  };
 
   for (;;) {
     if (tid == 0) ctl[kSim] = atomicAdd(a.work, 1u);
@@ -262,8 +276,8 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     const int W = L.W, H = L.H, stride = L.stride;
     const int words = H * stride;
     const int ix = sd.ign_x, iy = sd.ign_y;
-    const bool burnable =
-        ((L.blocked[iy * stride + (ix >> 5)] >> (ix & 31)) & 1u) == 0;
+    gmem_cu32 *const blocked = (gmem_cu32 *)L.blocked;
+    const bool burnable = ((blocked[iy * stride + (ix >> 5)] >> (ix & 31)) & 1u) == 0;
     if (!burnable) {
       // a non-burnable ignition burns nothing
       if (tid == 0) {
@@ -281,144 +295,182 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     }
 
     // -- init: bitset = non-burnable map, ignition burnt -------------------
-    for (int w = tid; w < words; w += BLOCK) bits[w] = L.blocked[w];
+    for (int w = tid; w < words; w += BLOCK) bits[w] = blocked[w];
     if (tid == 0) {
-      ctl[kLen0 + 0] = 0; ctl[kLen0 + 1] = 0; ctl[kLen0 + 2] = 0;
+      ctl[kLen0 + 0] = 1; ctl[kLen0 + 1] = 0; ctl[kLen0 + 2] = 0;
       ctl[kTrials] = 0; ctl[kNew] = 0; ctl[kInter] = 0;
+      ctl[kRowLo] = (uint32_t)iy; ctl[kRowHi] = (uint32_t)iy;
     }
     __syncthreads();
     if (tid == 0) {
       bits[iy * stride + (ix >> 5)] |= 1u << (ix & 31);
-      q_put<BLOCK>(qa, ga, cap, 0, (uint32_t)ix | ((uint32_t)iy << 12));
+      q_store(0, 0, (uint32_t)ix | ((uint32_t)iy << 12));
     }
     double beta[5];
-    const double *bp = a.betas + (int64_t)sd.param_index * 5;
+    if (!TABLE) {
+      const double *bp = a.betas + (int64_t)sd.param_index * 5;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) beta[i] = bp[i];
-    const uint32_t *table =
-        TABLE ? a.tables + (int64_t)sd.param_index * a.table_stride : nullptr;
-    const uint32_t *tbits = has_target ? tg.bits : nullptr;
+      for (int i = 0; i < 5; ++i) beta[i] = bp[i];
+    }
+    gmem_cu32 *const table =
+        TABLE ? (gmem_cu32 *)(a.tables + (int64_t)sd.param_index * a.table_stride) : nullptr;
     __syncthreads();
 
-    uint32_t *cur = qa, *nxt = qb, *gcur = ga, *gnxt = gb;
-    uint32_t n_cur = 1, step = 0;
-    uint32_t my_trials = 0, my_new = 0, my_inter = 0;
+    uint32_t cq = 0, step = 0;
+    uint32_t my_trials = 0, my_new = 0;
+    uint32_t row_lo = (uint32_t)iy, row_hi = (uint32_t)iy;
     const uint32_t max_steps = sd.max_steps;
+    const uint32_t sim_index = sd.sim_index;
+    // frontier length of step k lives in ctl[kLen0 + k % 3]
+    int slot = 0;
 
-    while (n_cur != 0 && step < max_steps) {
-      const int nslot = kLen0 + (int)((step + 1) % 3);
-      if (tid == 0) ctl[nslot] = 0;
+    // Phase 1 for one directed edge j of the current frontier: whether the
+    // edge is tried (target inside, burnable, unburnt at step start) and
+    // whether its coin succeeds.
+    auto edge_outcome = [&](uint32_t e, int d, bool &tried, int &tx, int &ty) -> bool {
+      const int x = (int)(e & 0xFFFu), y = (int)((e >> 12) & 0xFFFu);
+      const uint32_t s_lin = (uint32_t)(y * W + x);
+      uint32_t thr = 0;
+      if (TABLE) thr = table[(int64_t)s_lin * 8 + d];
+      tx = x + dir_dx(d);
+      ty = y + dir_dy(d);
+      const bool inside = (unsigned)tx < (unsigned)W && (unsigned)ty < (unsigned)H;
+      const int cx = inside ? tx : x, cy = inside ? ty : y;
+      const uint32_t word = bits[cy * stride + (cx >> 5)];
+      tried = inside && ((word >> (cx & 31)) & 1u) == 0;
+      const Words4 r = philox10(sim_index, step, s_lin, (uint32_t)(d >> 2), a.key0, a.key1);
+      const int k = d & 3;
+      const uint32_t coin = k == 0 ? r.v[0] : k == 1 ? r.v[1] : k == 2 ? r.v[2] : r.v[3];
+      if (!tried) return false;
+      if (!TABLE) {
+        const int64_t t = (int64_t)ty * W + tx;
+        thr = edge_threshold(beta, load_rec(L.rec, t), ((gmem_cf64 *)L.psi)[t], d,
+                             L.forest_class);
+      }
+      return thr == kSaturated || coin < thr;
+    };
 
-      // -- phase 1: eligibility against the step-start state, coins -------
-      for (uint32_t i = tid; i < n_cur; i += BLOCK) {
-        const uint32_t e = q_get<BLOCK>(cur, gcur, cap, i);
-        const int x = (int)(e & 0xFFFu), y = (int)((e >> 12) & 0xFFFu);
-        uint32_t elig = 0;
+    for (;; ++step) {
+      // the frontier length and this lane's first entry are read together
+      const uint32_t n_cur = ctl[kLen0 + slot];
+      const uint32_t e_first = lds[bw + cq * cap + min((uint32_t)tid >> 3, cap - 1)];
+      if (n_cur == 0 || step >= max_steps) break;
+      const int nslot = slot == 2 ? 0 : slot + 1;
+      if (tid == 0) ctl[kLen0 + nslot] = 0;
+      const uint32_t n_edges = 8 * n_cur;
+
+      if (n_edges <= (uint32_t)(kRegRounds * BLOCK) && n_edges <= cap) {
+        // -- small front: outcomes stay in registers between the phases,
+        //    and both queues live in LDS ---------------------------------
+        bool hit[kRegRounds];
+        int htx[kRegRounds], hty[kRegRounds];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
-          const int tx = x + kDx[d], ty = y + kDy[d];
-          if (tx >= 0 && tx < W && ty >= 0 && ty < H &&
-              ((bits[ty * stride + (tx >> 5)] >> (tx & 31)) & 1u) == 0)
-            elig |= 1u << d;
+        for (int rr = 0; rr < kRegRounds; ++rr) {
+          hit[rr] = false;
+          htx[rr] = 0;
+          hty[rr] = 0;
+          const uint32_t j = (uint32_t)(tid + rr * BLOCK);
+          if (rr * BLOCK < (int)n_edges && j < n_edges) {
+            const uint32_t e = rr == 0 ? e_first : lds[bw + cq * cap + (j >> 3)];
+            bool tried;
+            hit[rr] = edge_outcome(e, (int)(j & 7u), tried, htx[rr], hty[rr]);
+            my_trials += tried ? 1u : 0u;
+          }
         }
-        if (elig == 0) continue;
-        my_trials += __popc(elig);
-        const uint32_t s_lin = (uint32_t)(y * W + x);
-        uint32_t succ = 0;
+        __syncthreads();
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
-          const uint32_t m = (elig >> (4 * g)) & 0xFu;
-          if (m == 0) continue;
-          const Words4 r = philox10(sd.sim_index, step, s_lin, (uint32_t)g,
-                                    a.key0, a.key1);
-          uint32_t thr[4];
-          if (TABLE) {
-            const uint4 t4 =
-                reinterpret_cast<const uint4 *>(table + (int64_t)s_lin * 8)[g];
-            thr[0] = t4.x; thr[1] = t4.y; thr[2] = t4.z; thr[3] = t4.w;
-          } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              thr[k] = 0;
-              if ((m >> k) & 1u) {
-                const int d = 4 * g + k;
-                const int64_t t = (int64_t)(y + kDy[d]) * W + (x + kDx[d]);
-                thr[k] = edge_threshold(beta, L.rec[t], L.psi[t], d,
-                                        L.forest_class);
-              }
+        for (int rr = 0; rr < kRegRounds; ++rr) {
+          if (rr * BLOCK >= (int)n_edges) break;
+          bool fresh = false;
+          if (hit[rr]) {
+            const uint32_t bit = 1u << (htx[rr] & 31);
+            fresh = (atomicOr(&bits[hty[rr] * stride + (htx[rr] >> 5)], bit) & bit) == 0;
+          }
+          const uint64_t bal = __ballot(fresh);
+          if (bal != 0) {
+            uint32_t wbase = 0;
+            if (lane == 0) wbase = atomicAdd(&ctl[kLen0 + nslot], (uint32_t)__popcll(bal));
+            wbase = __builtin_amdgcn_readfirstlane(wbase);
+            if (fresh) {
+              lds[bw + (cq ^ 1u) * cap + wbase + lane_prefix(bal)] =
+                  (uint32_t)htx[rr] | ((uint32_t)hty[rr] << 12);
+              ++my_new;
+              row_lo = min(row_lo, (uint32_t)hty[rr]);
+              row_hi = max(row_hi, (uint32_t)hty[rr]);
             }
           }
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const bool hit = ((m >> k) & 1u) &&
-                             (thr[k] == kSaturated || r.v[k] < thr[k]);
-            succ |= (hit ? 1u : 0u) << (4 * g + k);
+        }
+      } else {
+        // -- general front: outcomes gathered into each entry's top byte;
+        //    queues spill to global memory past queue_cap ----------------
+        for (uint32_t j = tid; j < n_edges; j += BLOCK) {
+          const uint32_t e = q_load(cq, j >> 3);
+          bool tried;
+          int tx, ty;
+          const bool hit = edge_outcome(e, (int)(j & 7u), tried, tx, ty);
+          my_trials += tried ? 1u : 0u;
+          const uint64_t bal = __ballot(hit);
+          const uint32_t m8 = (uint32_t)(bal >> (lane & 56)) & 0xFFu;
+          if ((j & 7u) == 0 && m8 != 0) q_store(cq, j >> 3, e | (m8 << 24));
+        }
+        __syncthreads();
+        for (uint32_t base = 0; base < n_edges; base += BLOCK) {
+          const uint32_t j = base + (uint32_t)tid;
+          bool fresh = false;
+          int tx = 0, ty = 0;
+          if (j < n_edges) {
+            const uint32_t e = q_load(cq, j >> 3);
+            const int d = (int)(j & 7u);
+            if ((e >> (24 + d)) & 1u) {
+              tx = (int)(e & 0xFFFu) + dir_dx(d);
+              ty = (int)((e >> 12) & 0xFFFu) + dir_dy(d);
+              const uint32_t bit = 1u << (tx & 31);
+              fresh = (atomicOr(&bits[ty * stride + (tx >> 5)], bit) & bit) == 0;
+            }
           }
-        }
-        if (succ != 0) q_put<BLOCK>(cur, gcur, cap, i, e | (succ << 24));
-      }
-      __syncthreads();
-
-      // -- phase 2: apply ignitions, compact the next frontier --------------
-      for (uint32_t base = 0; base < n_cur; base += BLOCK) {
-        const uint32_t i = base + (uint32_t)tid;
-        const uint32_t e = i < n_cur ? q_get<BLOCK>(cur, gcur, cap, i) : 0u;
-        uint32_t succ = e >> 24;
-        const int x = (int)(e & 0xFFFu), y = (int)((e >> 12) & 0xFFFu);
-        uint32_t newm = 0;
-        while (succ) {
-          const int d = __ffs(succ) - 1;
-          succ &= succ - 1;
-          const int tx = x + kDx[d], ty = y + kDy[d];
-          const uint32_t bit = 1u << (tx & 31);
-          const uint32_t old = atomicOr(&bits[ty * stride + (tx >> 5)], bit);
-          if ((old & bit) == 0) newm |= 1u << d;
-        }
-        const uint32_t cnt = __popc(newm);
-        uint32_t excl = 0, total = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const uint64_t bal = __ballot((cnt >> b) & 1u);
-          excl += lane_prefix(bal) << b;
-          total += (uint32_t)__popcll(bal) << b;
-        }
-        if (total != 0) {
-          uint32_t wbase = 0;
-          if (lane == 0) wbase = atomicAdd(&ctl[nslot], total);
-          wbase = __builtin_amdgcn_readfirstlane(wbase);
-          uint32_t pos = wbase + excl;
-          while (newm) {
-            const int d = __ffs(newm) - 1;
-            newm &= newm - 1;
-            const int tx = x + kDx[d], ty = y + kDy[d];
-            q_put<BLOCK>(nxt, gnxt, cap, pos++, (uint32_t)tx | ((uint32_t)ty << 12));
-            ++my_new;
-            if (tbits != nullptr)
-              my_inter += (tbits[ty * stride + (tx >> 5)] >> (tx & 31)) & 1u;
+          const uint64_t bal = __ballot(fresh);
+          if (bal != 0) {
+            uint32_t wbase = 0;
+            if (lane == 0) wbase = atomicAdd(&ctl[kLen0 + nslot], (uint32_t)__popcll(bal));
+            wbase = __builtin_amdgcn_readfirstlane(wbase);
+            if (fresh) {
+              q_store(cq ^ 1u, wbase + lane_prefix(bal), (uint32_t)tx | ((uint32_t)ty << 12));
+              ++my_new;
+              row_lo = min(row_lo, (uint32_t)ty);
+              row_hi = max(row_hi, (uint32_t)ty);
+            }
           }
         }
       }
       __syncthreads();
-      n_cur = ctl[nslot];
-      uint32_t *t0 = cur; cur = nxt; nxt = t0;
-      uint32_t *t1 = gcur; gcur = gnxt; gnxt = t1;
-      ++step;
+      slot = nslot;
+      cq ^= 1u;
     }
 
-    // -- result: counts, Eq. 2, optional map --------------------------------
+    // -- result: counts, Eq. 2 over the rows the fire reached, map ---------
     if (my_trials) atomicAdd(&ctl[kTrials], my_trials);
-    if (my_new) atomicAdd(&ctl[kNew], my_new);
-    if (my_inter) atomicAdd(&ctl[kInter], my_inter);
+    if (my_new) {
+      atomicAdd(&ctl[kNew], my_new);
+      atomicMin(&ctl[kRowLo], row_lo);
+      atomicMax(&ctl[kRowHi], row_hi);
+    }
     __syncthreads();
+    if (has_target) {
+      // |A n A*| = popcount(burnt & reference) over the burnt rows
+      gmem_cu32 *const ref = (gmem_cu32 *)tg.bits;
+      const int w0 = (int)ctl[kRowLo] * stride, w1 = ((int)ctl[kRowHi] + 1) * stride;
+      uint32_t inter = 0;
+      for (int w = w0 + tid; w < w1; w += BLOCK) inter += __popc(bits[w] & ~blocked[w] & ref[w]);
+      if (inter) atomicAdd(&ctl[kInter], inter);
+      __syncthreads();
+    }
     if (tid == 0) {
       fire_result r;
       r.burnt = 1u + ctl[kNew];
       r.steps = step;
       r.trials = ctl[kTrials];
       if (has_target) {
-        const uint32_t ign_in_ref = (tbits[iy * stride + (ix >> 5)] >> (ix & 31)) & 1u;
-        const int64_t inter = (int64_t)ign_in_ref + ctl[kInter];
-        const int64_t num = (int64_t)tg.n_ref + r.burnt - 2 * inter;
+        const int64_t num = (int64_t)tg.n_ref + r.burnt - 2 * (int64_t)ctl[kInter];
         r.fitness = (double)num / (double)tg.n_ref;
       } else {
         r.fitness = __builtin_nan("");
@@ -427,7 +479,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     }
     if (a.maps != nullptr) {
       uint32_t *m = a.maps + (int64_t)sim * a.map_words;
-      for (int w = tid; w < words; w += BLOCK) m[w] = bits[w] & ~L.blocked[w];
+      for (int w = tid; w < words; w += BLOCK) m[w] = bits[w] & ~blocked[w];
     }
     __syncthreads();
   }
