@@ -156,8 +156,14 @@ typedef struct {
  *          map starts at out_maps + i*map_words
  *   map_words  words reserved per map; must be >= H*ceil(W/32) of every
  *          sim's landscape when out_maps != NULL
- * Results do not depend on the schedule (threads, queue sizes, threshold
- * mode) or on the order in which simulations run. Stream-ordered. */
+ * Simulations are grouped by landscape (by size when more than 8
+ * landscapes are used) and each group runs as its own persistent launch
+ * with LDS sized for it; groups run concurrently on internal streams
+ * forked from and joined back to `stream` (capturable). Results do not
+ * depend on the schedule (threads, queue sizes, threshold mode), the
+ * grouping or the order in which simulations run. Stream-ordered; calls
+ * on one context must not overlap on different streams (they share
+ * staging and scratch buffers). */
 fire_status fire_run(fire_ctx *ctx, const double *betas, int32_t n_params,
                      const fire_sim *sims, int32_t n_sims, uint64_t seed,
                      const uint32_t *thresholds_override, fire_result *out,
@@ -188,6 +194,12 @@ typedef struct {
  * restores the built-in choice. FIRE_E_INVALID when a field is out of
  * range or the LDS budget cannot hold it. */
 fire_status fire_set_schedule(fire_ctx *ctx, const fire_schedule *s);
+/* Schedule for one size class: runs whose landscapes have between
+ * 2^(b-1)+1 and 2^b cells, b = ceil(log2(max_cells)), use `s` unless a
+ * fixed schedule is set. NULL removes the class entry. Used by the
+ * autotuner. */
+fire_status fire_set_class_schedule(fire_ctx *ctx, int64_t max_cells,
+                                    const fire_schedule *s);
 /* The schedule the next run on landscapes of up to `max_cells` cells and
  * `n_params` parameter vectors would use. */
 fire_status fire_get_schedule(fire_ctx *ctx, int64_t max_cells,

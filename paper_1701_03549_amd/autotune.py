@@ -1,0 +1,147 @@
+"""Schedule autotuner for the simulation kernel.
+
+For a representative batch on one landscape size class it times every
+candidate schedule (threads per workgroup, workgroups per compute unit,
+LDS queue capacity, threshold table vs per-trial evaluation) with HIP
+events on the launch stream, checks that every schedule returns bit-identical
+results (they must: results do not depend on the schedule), and keeps the
+fastest. Choices are cached per GPU architecture and size class in a JSON
+file and applied through fire_set_class_schedule.
+
+    python -m paper_1701_03549_amd.autotune            # tune the built-in workloads
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import sys
+
+import numpy as np
+import torch
+
+from . import fire, synth
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_schedules.json")
+
+
+def arch_name() -> str:
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def cells_bucket(cells: int) -> int:
+    b = 0
+    while (1 << b) < cells:
+        b += 1
+    return b
+
+
+def candidates(table_ok: bool):
+    for threads, wg, qcap in itertools.product((128, 256, 512), (1, 2, 4, 8), (1024, 4096)):
+        for table in ((0, 1) if table_ok else (0,)):
+            yield {"threads": threads, "queue_cap": qcap, "table_mode": table, "wg_per_cu": wg}
+
+
+def time_schedule(g: fire.FireGPU, sched, d_beta, d_sims, n, seed, out, reps=3):
+    g.set_schedule(**sched)
+    stream = torch.cuda.current_stream()
+    g.run_dev(d_beta, d_sims, n, seed, out, stream=stream)  # warm-up (allocations)
+    g.sync()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        g.run_dev(d_beta, d_sims, n, seed, out, stream=stream)
+        b.record(stream)
+    g.sync()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def tune(g: fire.FireGPU, lid: int, sims: np.ndarray, betas: np.ndarray, seed: int,
+         log=None):
+    """Tune one size class (all sims on landscape `lid`). Returns (best, table)."""
+    n = len(sims)
+    d_sims = torch.from_numpy(np.ascontiguousarray(sims).view(np.uint8).copy()).to(g.device)
+    d_beta = torch.from_numpy(np.ascontiguousarray(betas, dtype=np.float64)).to(g.device)
+    out = torch.empty((n, 24), dtype=torch.uint8, device=g.device)
+    ref = None
+    rows = []
+    for sched in candidates(table_ok=len(betas) <= 8):
+        try:
+            ms = time_schedule(g, sched, d_beta, d_sims, n, seed, out)
+        except fire.FireError as e:  # LDS budget exceeded for this shape
+            if log:
+                log(f"skip {sched}: {e}")
+            continue
+        if ref is None:
+            ref = out.clone()
+        elif not torch.equal(out, ref):
+            raise RuntimeError(f"schedule {sched} changed the results")
+        rows.append((ms, sched))
+        if log:
+            log(f"{ms:8.3f} ms  {sched}")
+    g.set_schedule(reset=True)
+    rows.sort(key=lambda r: r[0])
+    return rows[0][1], rows
+
+
+def load_cache(path: str = CACHE) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def apply_cache(g: fire.FireGPU, path: str = CACHE) -> int:
+    """Install the cached schedules of this architecture; returns how many."""
+    entries = load_cache(path).get(arch_name(), {})
+    for bucket, e in entries.items():
+        g.set_class_schedule(1 << int(bucket), e["schedule"])
+    return len(entries)
+
+
+def workloads():
+    """Representative batches per size class: replicate batches at a
+    contained parameter vector and random parameter vectors from the
+    search box, on the synthetic landscapes of the benchmark configs."""
+    rng = np.random.default_rng(7)
+    beta_star = np.array([[-1.15, -0.5, 0.3, 0.8, 1.0]])
+    for W, H, seed in ((128, 128, 101), (256, 256, 102), (512, 512, 102), (1024, 768, 104),
+                       (1024, 1024, 103)):
+        yield (W, H, seed, beta_star, 1280)
+        yield (W, H, seed, rng.uniform(-30, 30, size=(500, 5)), 500)
+
+
+def main():
+    log = lambda m: print(f"[autotune] {m}", flush=True)  # noqa: E731
+    g = fire.FireGPU(0)
+    cache = load_cache()
+    arch = arch_name()
+    mine = cache.setdefault(arch, {})
+    best_by_bucket = {}
+    for W, H, seed, betas, n in workloads():
+        ls = synth.make_landscape(W, H, seed)
+        lid = g.load_landscape(ls)
+        c = synth.nearest_burnable(ls["veg"], W // 2, H // 2)
+        sims = fire.make_sims(n, lid, -1, c, param_index=np.arange(n) % len(betas))
+        log(f"{W}x{H}, {len(betas)} parameter vector(s), {n} simulations")
+        best, rows = tune(g, lid, sims, betas, 0x5EED0001, log=log)
+        b = str(cells_bucket(W * H))
+        # keep the schedule that is best for the random-parameter batch when both
+        # kinds were tuned (it dominates GA and Monte Carlo workloads)
+        best_by_bucket.setdefault(b, {})[("table" if len(betas) == 1 else "random")] = (
+            best, rows[0][0])
+        g.free_landscape(lid)
+    for b, kinds in best_by_bucket.items():
+        best, ms = kinds.get("random", kinds.get("table"))
+        mine[b] = {"schedule": best, "ms": ms,
+                   "replicate_batch": kinds.get("table", (None, None))[0]}
+    with open(CACHE, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    log(f"wrote {CACHE}")
+    g.close()
+
+
+if __name__ == "__main__":
+    sys.exit(main())

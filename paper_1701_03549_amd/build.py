@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfiregpu.so")
-SOURCES = [os.path.join(CSRC, "fire_kernels.hip"), os.path.join(CSRC, "fire_abi.cpp")]
+SOURCES = [os.path.join(CSRC, "fire_kernels.hip"), os.path.join(CSRC, "fire_abi.cpp"),
+           os.path.join(CSRC, "surrogate.hip")]
 ARCH = os.environ.get("FIREGPU_ARCH", "gfx950")
 
 

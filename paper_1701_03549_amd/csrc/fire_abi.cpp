@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -47,7 +48,7 @@ struct fire_ctx {
   int d_ls_cap = 0;
   TargetDev *d_tg = nullptr;
   int d_tg_cap = 0;
-  uint32_t *d_work = nullptr;   // [0] sim counter, [1] error flag
+  uint32_t *d_work = nullptr;   // [0..kMaxClasses) work counters, [kErrWord] error flag
   uint32_t *d_ovf = nullptr;
   size_t ovf_words = 0;
   uint32_t *d_tables = nullptr;
@@ -61,12 +62,28 @@ struct fire_ctx {
   // fixed schedule (autotuner) or built-in choice
   bool sched_fixed = false;
   fire_schedule sched{};
+  // per size-class schedules (autotuner): log2 bucket of max_cells -> schedule
+  std::vector<std::pair<int, fire_schedule>> class_sched;
+  // side streams and events for running size classes concurrently
+  hipStream_t side[7] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[8] = {};
   // GA scratch
   double *d_ga = nullptr;
   size_t ga_bytes = 0;
 };
 
 namespace {
+
+constexpr int kMaxClasses = 8;   // concurrent persistent launches per fire_run
+constexpr int kErrWord = 16;     // error flag word in d_work
+constexpr int kWorkWords = 32;
+
+int cells_bucket(int64_t cells) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << b) < cells) ++b;
+  return b;
+}
 
 fire_status fail(fire_ctx *c, fire_status st, const char *fmt, ...) {
   char buf[512];
@@ -190,9 +207,14 @@ struct RunPlan {
 fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells,
                      int32_t n_params, int32_t n_sims, bool table_allowed,
                      RunPlan *out) {
-  fire_schedule s = c->sched_fixed
-                        ? c->sched
-                        : default_schedule(c, max_cells, bitset_words, n_params);
+  fire_schedule s = default_schedule(c, max_cells, bitset_words, n_params);
+  if (c->sched_fixed) {
+    s = c->sched;
+  } else {
+    const int b = cells_bucket(max_cells);
+    for (const auto &e : c->class_sched)
+      if (e.first == b) s = e.second;
+  }
   if (!table_allowed) s.table_mode = 0;
   size_t lds = lds_bytes_for(bitset_words, s.queue_cap);
   if (lds > c->max_lds)
@@ -214,33 +236,45 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells,
   return FIRE_OK;
 }
 
-fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
-                       int32_t n_params, const fire_sim *sims_dev,
-                       int32_t n_sims, uint64_t seed, const uint32_t *tables,
-                       int64_t table_stride, int32_t table_ls,
-                       fire_result *out, uint32_t *out_maps,
-                       int64_t map_words, hipStream_t st) {
+int64_t spill_words(const RunPlan &p) {
   int64_t ovf_cap = p.max_cells - p.s.queue_cap;
   if (ovf_cap < 1) ovf_cap = 1;
-  size_t ovf_need = (size_t)p.grid * 2 * (size_t)ovf_cap * sizeof(uint32_t);
-  if (ovf_need > c->ovf_words * sizeof(uint32_t)) {
-    HIP_OR_FAIL(c, hipDeviceSynchronize());
-    size_t have = c->ovf_words * sizeof(uint32_t);
-    HIP_OR_FAIL(c, ensure((void **)&c->d_ovf, &have, ovf_need));
-    c->ovf_words = have / sizeof(uint32_t);
-  }
+  return (int64_t)p.grid * 2 * ovf_cap;
+}
+
+// Make the spill area hold `words` entries (waits for the device when it grows).
+fire_status ensure_spill(fire_ctx *c, int64_t words) {
+  if ((size_t)words <= c->ovf_words && c->d_ovf) return FIRE_OK;
+  HIP_OR_FAIL(c, hipDeviceSynchronize());
+  size_t have = c->ovf_words * sizeof(uint32_t);
+  HIP_OR_FAIL(c, ensure((void **)&c->d_ovf, &have, (size_t)words * sizeof(uint32_t)));
+  c->ovf_words = have / sizeof(uint32_t);
+  return FIRE_OK;
+}
+
+// One persistent launch over n_sims descriptors (or over `order`, a list of
+// n_sims indices into sims_dev), with its own work counter and spill area.
+fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
+                       int32_t n_params, const fire_sim *sims_dev,
+                       const uint32_t *order, int32_t n_sims, uint64_t seed,
+                       const uint32_t *tables, int64_t table_stride,
+                       int32_t table_ls, fire_result *out, uint32_t *out_maps,
+                       int64_t map_words, int counter, uint32_t *spill,
+                       hipStream_t st) {
+  int64_t ovf_cap = p.max_cells - p.s.queue_cap;
+  if (ovf_cap < 1) ovf_cap = 1;
   SimArgs a{};
   a.ls = c->d_ls; a.n_ls = (int32_t)c->ls.size();
   a.tg = c->d_tg; a.n_tg = (int32_t)c->tg.size();
   a.betas = betas_dev; a.n_params = n_params;
-  a.sims = sims_dev; a.n_sims = n_sims;
+  a.sims = sims_dev; a.order = order; a.n_sims = n_sims;
   a.key0 = (uint32_t)seed; a.key1 = (uint32_t)(seed >> 32);
   a.tables = tables; a.table_stride = table_stride; a.table_ls = table_ls;
   a.out = out; a.maps = out_maps; a.map_words = map_words;
-  a.work = c->d_work; a.error_flag = c->d_work + 1;
-  a.ovf = c->d_ovf; a.ovf_cap = ovf_cap;
+  a.work = c->d_work + counter; a.error_flag = c->d_work + kErrWord;
+  a.ovf = spill; a.ovf_cap = ovf_cap;
   a.queue_cap = p.s.queue_cap; a.bitset_words = p.bitset_words;
-  HIP_OR_FAIL(c, launch_fill_u32(c->d_work, 0u, 1, st));
+  HIP_OR_FAIL(c, launch_fill_u32(a.work, 0u, 1, st));
   HIP_OR_FAIL(c, launch_sim(a, p.s.threads, tables != nullptr, p.grid, p.lds, st));
   return FIRE_OK;
 }
@@ -282,8 +316,11 @@ fire_status fire_ctx_create(int device, fire_ctx **out) {
     c->max_lds = prop.sharedMemPerBlock;
   // raising the dynamic-LDS ceiling is advisory on this platform
   if (set_sim_lds_limit(c->max_lds) != hipSuccess) (void)hipGetLastError();
-  if (hipMalloc(&c->d_work, 2 * sizeof(uint32_t)) != hipSuccess ||
-      hipMemset(c->d_work, 0, 2 * sizeof(uint32_t)) != hipSuccess ||
+  bool ev_ok = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < kMaxClasses && ev_ok; ++i)
+    ev_ok = hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!ev_ok || hipMalloc(&c->d_work, kWorkWords * sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(c->d_work, 0, kWorkWords * sizeof(uint32_t)) != hipSuccess ||
       hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     fire_ctx_destroy(c);
@@ -313,6 +350,11 @@ void fire_ctx_destroy(fire_ctx *c) {
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->d_ga) (void)hipFree(c->d_ga);
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  for (int i = 0; i < kMaxClasses; ++i)
+    if (c->join_ev[i]) (void)hipEventDestroy(c->join_ev[i]);
+  for (int i = 0; i < kMaxClasses - 1; ++i)
+    if (c->side[i]) (void)hipStreamDestroy(c->side[i]);
   delete c;
 }
 
@@ -325,10 +367,10 @@ fire_status fire_sync(fire_ctx *c, void *stream) {
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   HIP_OR_FAIL(c, hipStreamSynchronize((hipStream_t)stream));
   uint32_t flag = 0;
-  HIP_OR_FAIL(c, hipMemcpy(&flag, c->d_work + 1, sizeof flag, hipMemcpyDeviceToHost));
+  HIP_OR_FAIL(c, hipMemcpy(&flag, c->d_work + kErrWord, sizeof flag, hipMemcpyDeviceToHost));
   if (flag) {
     uint32_t zero = 0;
-    HIP_OR_FAIL(c, hipMemcpy(c->d_work + 1, &zero, sizeof zero, hipMemcpyHostToDevice));
+    HIP_OR_FAIL(c, hipMemcpy(c->d_work + kErrWord, &zero, sizeof zero, hipMemcpyHostToDevice));
     return fail(c, FIRE_E_INVALID,
                 "a simulation descriptor was rejected on the device "
                 "(bad id, ignition outside the lattice, map or table mismatch)");
@@ -572,13 +614,49 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
     return fail(c, FIRE_E_INVALID, "thresholds_override must be 16-byte aligned");
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
-  RunPlan plan;
-  fire_status ps = plan_run(c, bw, mc, n_params, n_sims, one_ls >= 0, &plan);
-  if (ps != FIRE_OK) return ps;
-  // stage descriptors and parameters
+
+  // Size classes: simulations grouped by landscape (by size when there are
+  // more landscapes than concurrent launches), each class run by its own
+  // persistent launch with LDS sized for that class.
+  std::vector<int> cls_of_ls(c->ls.size(), -1);
+  std::vector<int64_t> cls_cells;
+  std::vector<int> cls_words;
+  std::vector<int> ls_ids;
+  for (int32_t i = 0; i < n_sims; ++i) {
+    const int l = sims[i].landscape_id;
+    if (cls_of_ls[l] < 0) { cls_of_ls[l] = -2; ls_ids.push_back(l); }
+  }
+  if ((int)ls_ids.size() <= kMaxClasses) {
+    for (int l : ls_ids) {
+      cls_of_ls[l] = (int)cls_cells.size();
+      cls_cells.push_back((int64_t)c->ls[l].W * c->ls[l].H);
+      cls_words.push_back(c->ls[l].H * c->ls[l].stride);
+    }
+  } else {
+    for (int l : ls_ids) cls_of_ls[l] = 0;
+    cls_cells.push_back(mc);
+    cls_words.push_back(bw);
+  }
+  const int n_cls = (int)cls_cells.size();
+  std::vector<std::vector<uint32_t>> members(n_cls);
+  for (int32_t i = 0; i < n_sims; ++i)
+    members[cls_of_ls[sims[i].landscape_id]].push_back((uint32_t)i);
+  std::vector<RunPlan> plans(n_cls);
+  int64_t spill_total = 0;
+  for (int k = 0; k < n_cls; ++k) {
+    fire_status ps = plan_run(c, cls_words[k], cls_cells[k], n_params,
+                              (int32_t)members[k].size(), one_ls >= 0, &plans[k]);
+    if (ps != FIRE_OK) return ps;
+    spill_total += spill_words(plans[k]);
+  }
+  fire_status ss = ensure_spill(c, spill_total);
+  if (ss != FIRE_OK) return ss;
+
+  // stage descriptors, parameters and class member lists
   const size_t bbytes = sizeof(double) * 5 * (size_t)n_params;
   const size_t boff = (sizeof(fire_sim) * (size_t)n_sims + 255) / 256 * 256;
-  const size_t need = boff + bbytes;
+  const size_t ooff = (boff + bbytes + 255) / 256 * 256;
+  const size_t need = ooff + sizeof(uint32_t) * (size_t)n_sims;
   if (c->stage_pending) {
     HIP_OR_FAIL(c, hipEventSynchronize(c->stage_done));
     c->stage_pending = false;
@@ -596,21 +674,59 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
   }
   memcpy(c->h_stage, sims, sizeof(fire_sim) * (size_t)n_sims);
   memcpy((char *)c->h_stage + boff, betas, bbytes);
+  {
+    uint32_t *o = (uint32_t *)((char *)c->h_stage + ooff);
+    for (int k = 0; k < n_cls; ++k)
+      for (uint32_t v : members[k]) *o++ = v;
+  }
   HIP_OR_FAIL(c, hipMemcpyAsync(c->d_stage, c->h_stage, need, hipMemcpyHostToDevice, st));
   HIP_OR_FAIL(c, hipEventRecord(c->stage_done, st));
   c->stage_pending = true;
   const fire_sim *d_sims = (const fire_sim *)c->d_stage;
   const double *d_betas = (const double *)((char *)c->d_stage + boff);
+  const uint32_t *d_order = (const uint32_t *)((char *)c->d_stage + ooff);
+
   const uint32_t *tables = override_T;
   int64_t tstride = 0;
   if (override_T) {
     tstride = mc * 8;
-  } else if (plan.s.table_mode) {
+  } else if (n_cls == 1 && one_ls >= 0 && plans[0].s.table_mode) {
     fire_status tsx = build_tables(c, one_ls, d_betas, n_params, st, &tables, &tstride);
     if (tsx != FIRE_OK) return tsx;
   }
-  return launch_run(c, plan, d_betas, n_params, d_sims, n_sims, seed, tables, tstride,
-                    tables ? one_ls : -1, out, out_maps, map_words, st);
+  if (n_cls == 1)
+    return launch_run(c, plans[0], d_betas, n_params, d_sims, nullptr, n_sims, seed, tables,
+                      tstride, tables ? one_ls : -1, out, out_maps, map_words, 0, c->d_ovf, st);
+
+  // fork the classes onto side streams, join back to the caller's stream
+  for (int k = 0; k < n_cls - 1; ++k)
+    if (!c->side[k])
+      HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking));
+  HIP_OR_FAIL(c, hipEventRecord(c->fork_ev, st));
+  int64_t spill_off = 0, order_off = 0;
+  // largest class first, on the caller's stream
+  std::vector<int> by_size(n_cls);
+  for (int k = 0; k < n_cls; ++k) by_size[k] = k;
+  std::sort(by_size.begin(), by_size.end(),
+            [&](int x, int y) { return cls_cells[x] > cls_cells[y]; });
+  std::vector<int64_t> order_start(n_cls, 0);
+  for (int k = 1; k < n_cls; ++k) order_start[k] = order_start[k - 1] + (int64_t)members[k - 1].size();
+  for (int r = 0; r < n_cls; ++r) {
+    const int k = by_size[r];
+    hipStream_t ks = r == 0 ? st : c->side[r - 1];
+    if (r > 0) HIP_OR_FAIL(c, hipStreamWaitEvent(ks, c->fork_ev, 0));
+    order_off = order_start[k];
+    fire_status ls_ = launch_run(c, plans[k], d_betas, n_params, d_sims, d_order + order_off,
+                                 (int32_t)members[k].size(), seed, nullptr, 0, -1, out,
+                                 out_maps, map_words, k, c->d_ovf + spill_off, ks);
+    if (ls_ != FIRE_OK) return ls_;
+    spill_off += spill_words(plans[k]);
+    if (r > 0) {
+      HIP_OR_FAIL(c, hipEventRecord(c->join_ev[r], ks));
+      HIP_OR_FAIL(c, hipStreamWaitEvent(st, c->join_ev[r], 0));
+    }
+  }
+  return FIRE_OK;
 }
 
 fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
@@ -642,6 +758,8 @@ fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
   RunPlan plan;
   fire_status ps = plan_run(c, bw, mc, n_params, n_sims, nlive == 1, &plan);
   if (ps != FIRE_OK) return ps;
+  fire_status ss = ensure_spill(c, spill_words(plan));
+  if (ss != FIRE_OK) return ss;
   const uint32_t *tables = override_T;
   int64_t tstride = 0;
   if (override_T) {
@@ -650,8 +768,29 @@ fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
     fire_status tsx = build_tables(c, lid, betas_dev, n_params, st, &tables, &tstride);
     if (tsx != FIRE_OK) return tsx;
   }
-  return launch_run(c, plan, betas_dev, n_params, sims_dev, n_sims, seed, tables, tstride,
-                    tables ? lid : -1, out, out_maps, map_words, st);
+  return launch_run(c, plan, betas_dev, n_params, sims_dev, nullptr, n_sims, seed, tables,
+                    tstride, tables ? lid : -1, out, out_maps, map_words, 0, c->d_ovf, st);
+}
+
+fire_status fire_set_class_schedule(fire_ctx *c, int64_t max_cells, const fire_schedule *s) {
+  if (!c) return FIRE_E_INVALID;
+  if (max_cells < 1) return fail(c, FIRE_E_INVALID, "max_cells < 1");
+  const int b = cells_bucket(max_cells);
+  for (size_t i = 0; i < c->class_sched.size(); ++i)
+    if (c->class_sched[i].first == b) {
+      if (s) c->class_sched[i].second = *s;
+      else c->class_sched.erase(c->class_sched.begin() + i);
+      return FIRE_OK;
+    }
+  if (!s) return FIRE_OK;
+  if (s->threads != 64 && s->threads != 128 && s->threads != 256 && s->threads != 512 &&
+      s->threads != 1024)
+    return fail(c, FIRE_E_INVALID, "threads must be 64, 128, 256, 512 or 1024");
+  if (s->queue_cap < 64 || s->wg_per_cu < 1 || s->wg_per_cu > 32 ||
+      (s->table_mode != 0 && s->table_mode != 1))
+    return fail(c, FIRE_E_INVALID, "schedule field out of range");
+  c->class_sched.push_back({b, *s});
+  return FIRE_OK;
 }
 
 fire_status fire_set_schedule(fire_ctx *c, const fire_schedule *s) {
@@ -758,12 +897,8 @@ fire_status fire_ga_run(fire_ctx *c, int32_t lid, int32_t tid, int32_t ign_x, in
   if (ps != FIRE_OK) return ps;
   int64_t ovf_cap = plan.max_cells - plan.s.queue_cap;
   if (ovf_cap < 1) ovf_cap = 1;
-  size_t ovf_need = (size_t)plan.grid * 2 * (size_t)ovf_cap * sizeof(uint32_t);
-  if (ovf_need > c->ovf_words * sizeof(uint32_t)) {
-    size_t h2 = c->ovf_words * sizeof(uint32_t);
-    HIP_OR_FAIL(c, ensure((void **)&c->d_ovf, &h2, ovf_need));
-    c->ovf_words = h2 / sizeof(uint32_t);
-  }
+  fire_status ss = ensure_spill(c, spill_words(plan));
+  if (ss != FIRE_OK) return ss;
   SimArgs a{};
   a.ls = c->d_ls; a.n_ls = (int32_t)c->ls.size();
   a.tg = c->d_tg; a.n_tg = (int32_t)c->tg.size();
@@ -772,7 +907,7 @@ fire_status fire_ga_run(fire_ctx *c, int32_t lid, int32_t tid, int32_t ign_x, in
   a.key0 = (uint32_t)sim_seed; a.key1 = (uint32_t)(sim_seed >> 32);
   a.tables = nullptr; a.table_stride = 0; a.table_ls = -1;
   a.out = d_res; a.maps = nullptr; a.map_words = 0;
-  a.work = c->d_work; a.error_flag = c->d_work + 1;
+  a.work = c->d_work; a.error_flag = c->d_work + kErrWord;
   a.ovf = c->d_ovf; a.ovf_cap = ovf_cap;
   a.queue_cap = plan.s.queue_cap; a.bitset_words = plan.bitset_words;
 

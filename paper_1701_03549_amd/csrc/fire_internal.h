@@ -36,6 +36,7 @@ struct SimArgs {
   const double *betas;
   int32_t n_params;
   const fire_sim *sims;
+  const uint32_t *order;   // NULL, or the n_sims indices into sims[] to run
   int32_t n_sims;
   uint32_t key0, key1;
   const uint32_t *tables;  // NULL or [n_params][table_stride]

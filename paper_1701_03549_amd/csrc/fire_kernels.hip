@@ -233,10 +233,13 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
   };
 
   for (;;) {
-    if (tid == 0) ctl[kSim] = atomicAdd(a.work, 1u);
+    if (tid == 0) {
+      const uint32_t k = atomicAdd(a.work, 1u);
+      ctl[kSim] = k < (uint32_t)a.n_sims ? (a.order ? a.order[k] : k) : 0xFFFFFFFFu;
+    }
     __syncthreads();
     const uint32_t sim = ctl[kSim];
-    if (sim >= (uint32_t)a.n_sims) break;
+    if (sim == 0xFFFFFFFFu) break;
     const fire_sim sd = a.sims[sim];
 
     // -- descriptor checks (uniform over the workgroup) --------------------

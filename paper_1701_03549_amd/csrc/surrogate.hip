@@ -1,0 +1,756 @@
+// Learned surrogate of the fire simulator (include/fire_nn.h): bf16 GEMMs on
+// MFMA (v_mfma_f32_32x32x16_bf16, fp32 accumulation) for the MLP and the
+// decoder's dense layer, fp32 upsample+3x3-convolution layers for the
+// decoder, fused losses, Adam with fp32 master weights.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "fire_nn.h"
+
+namespace firenn {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+
+// fp32 -> bf16 with round-to-nearest-even (inputs are finite)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+int blocks_for(int64_t n, int t = 256) {
+  int64_t b = (n + t - 1) / t;
+  if (b < 1) b = 1;
+  if (b > 65535) b = 65535;
+  return (int)b;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: 64x64 output tile per workgroup of 4 waves, each wave one 32x32 MFMA
+// tile; K staged through LDS 32 at a time (A row-major, B transposed so that
+// each lane's 8 consecutive k of a fragment are contiguous).
+constexpr int kTM = 64, kTN = 64, kTK = 32, kLdt = kTK + 8;
+
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const uint16_t *A,
+                                                   int64_t sam, int64_t sak, const uint16_t *B,
+                                                   int64_t sbk, int64_t sbn, float *C,
+                                                   int64_t ldc, const float *bias, int relu,
+                                                   int accumulate, uint16_t *Cb) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[kTM * kLdt];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kTN * kLdt];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  f32x16_t acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  for (int k0 = 0; k0 < K; k0 += kTK) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + 256 * i;
+      const int r = e >> 5, kk = e & 31;
+      const int m = m0 + r, k = k0 + kk;
+      As[r * kLdt + kk] = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : (uint16_t)0;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + 256 * i;
+      const int nn = e & 63, kk = e >> 6;
+      const int n = n0 + nn, k = k0 + kk;
+      Bs[nn * kLdt + kk] = (n < N && k < K) ? B[(int64_t)k * sbk + (int64_t)n * sbn] : (uint16_t)0;
+    }
+    __syncthreads();
+    const int half = lane >> 5, r = lane & 31;
+#pragma unroll
+    for (int kk = 0; kk < kTK; kk += 16) {
+      const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(&As[(wr + r) * kLdt + kk + half * 8]);
+      const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(&Bs[(wc + r) * kLdt + kk + half * 8]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = wr + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int j = wc + (lane & 31);
+    const int m = m0 + i, n = n0 + j;
+    if (m < M && n < N) {
+      float val = acc[v];
+      if (bias) val += bias[n];
+      if (accumulate) val += C[(int64_t)m * ldc + n];
+      if (relu) val = fmaxf(val, 0.0f);
+      C[(int64_t)m * ldc + n] = val;
+      if (Cb) Cb[(int64_t)m * ldc + n] = f2bf(val);
+    }
+  }
+}
+
+hipError_t gemm(int M, int N, int K, const uint16_t *A, int64_t sam, int64_t sak,
+                const uint16_t *B, int64_t sbk, int64_t sbn, float *C, int64_t ldc,
+                const float *bias, int relu, int accumulate, uint16_t *Cb, hipStream_t s) {
+  dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM);
+  hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C,
+                     ldc, bias, relu, accumulate, Cb);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise and reduction kernels
+
+__global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = f2bf(x[i]);
+}
+
+// raw [B][7] -> bf16 [B][16]: beta/30, ignition scaled to [-1, 1], zero pad
+__global__ void prep_input_kernel(const float *x, int B, float inv_w, float inv_h, uint16_t *xb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * 16) return;
+  const int b = i >> 4, k = i & 15;
+  float v = 0.0f;
+  if (k < 5) v = x[b * 7 + k] * (1.0f / 30.0f);
+  else if (k == 5) v = 2.0f * x[b * 7 + 5] * inv_w - 1.0f;
+  else if (k == 6) v = 2.0f * x[b * 7 + 6] * inv_h - 1.0f;
+  xb[i] = f2bf(v);
+}
+
+// g <- g * (h > 0) (ReLU backward, in place) and its bf16 copy
+__global__ void relu_bwd_kernel(float *g, const float *h, uint16_t *gb, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = h[i] > 0.0f ? g[i] : 0.0f;
+    g[i] = v;
+    gb[i] = f2bf(v);
+  }
+}
+
+// column sums of d [M][N] (bias gradients), fixed order
+__global__ void colsum_kernel(const float *d, int M, int N, float *out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int m = 0; m < M; ++m) s += d[(int64_t)m * N + n];
+  out[n] = s;
+}
+
+__device__ float block_reduce(float v, float *red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  const float r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// fitness head: loss = mean((t - y)^2), dt = 2 (t - y) / B
+__global__ __launch_bounds__(256) void loss_fit_kernel(const float *t, const float *y, int B,
+                                                       float *dt, uint16_t *dtb, float *loss) {
+  __shared__ float red[256];
+  float acc = 0.0f;
+  for (int b = threadIdx.x; b < B; b += 256) {
+    const float e = t[b] - y[b];
+    acc += e * e;
+    const float g = 2.0f * e / (float)B;
+    dt[b] = g;
+    dtb[b] = f2bf(g);
+  }
+  const float s = block_reduce(acc, red);
+  if (threadIdx.x == 0) loss[0] = s / (float)B;
+}
+
+// map head: BCE with logits, dz = w (sigmoid(z) - y) / (B P); per-block
+// partial losses reduced afterwards in fixed order
+__global__ __launch_bounds__(256) void loss_map_kernel(const float *z, const uint8_t *y,
+                                                       int64_t n, float w, float *dz,
+                                                       float *partial) {
+  __shared__ float red[256];
+  float acc = 0.0f;
+  const float inv_n = 1.0f / (float)n;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float zi = z[i], yi = y[i] ? 1.0f : 0.0f;
+    acc += fmaxf(zi, 0.0f) - zi * yi + log1pf(expf(-fabsf(zi)));
+    const float sg = 1.0f / (1.0f + expf(-zi));
+    dz[i] = w * (sg - yi) * inv_n;
+  }
+  const float s = block_reduce(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void sum_partials_kernel(const float *p, int n, float scale,
+                                                           float *out) {
+  __shared__ float red[256];
+  float acc = 0.0f;
+  for (int i = threadIdx.x; i < n; i += 256) acc += p[i];
+  const float s = block_reduce(acc, red);
+  if (threadIdx.x == 0) out[0] = s * scale;
+}
+
+__global__ void sigmoid_kernel(const float *z, float *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 1.0f / (1.0f + expf(-z[i]));
+}
+
+// ---------------------------------------------------------------------------
+// Decoder layer: 2x nearest upsampling of in [B][Ci][S][S] followed by a 3x3
+// convolution with zero padding: out [B][Co][2S][2S].
+
+__device__ __forceinline__ float up_at(const float *in, int b, int ci, int Ci, int S, int Y,
+                                       int X) {
+  if (Y < 0 || X < 0 || Y >= 2 * S || X >= 2 * S) return 0.0f;
+  return in[(((int64_t)b * Ci + ci) * S + (Y >> 1)) * S + (X >> 1)];
+}
+
+__global__ void upconv_fwd_kernel(const float *in, const float *Kw, const float *kb, int B,
+                                  int Ci, int Co, int S, int relu, float *out) {
+  const int O = 2 * S;
+  const int64_t n = (int64_t)B * Co * O * O;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % O), y = (int)((i / O) % O);
+    const int co = (int)((i / ((int64_t)O * O)) % Co), b = (int)(i / ((int64_t)O * O * Co));
+    float acc = kb[co];
+    for (int ci = 0; ci < Ci; ++ci)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+          acc += Kw[((co * Ci + ci) * 3 + dy) * 3 + dx] * up_at(in, b, ci, Ci, S, y + dy - 1, x + dx - 1);
+    out[i] = relu ? fmaxf(acc, 0.0f) : acc;
+  }
+}
+
+// d(in) for in [B][Ci][S][S], masked by (act > 0) when act is given
+__global__ void upconv_bwd_data_kernel(const float *dout, const float *Kw, const float *act,
+                                       int B, int Ci, int Co, int S, float *din) {
+  const int O = 2 * S;
+  const int64_t n = (int64_t)B * Ci * S * S;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int xi = (int)(i % S), yi = (int)((i / S) % S);
+    const int ci = (int)((i / ((int64_t)S * S)) % Ci), b = (int)(i / ((int64_t)S * S * Ci));
+    float acc = 0.0f;
+    for (int co = 0; co < Co; ++co) {
+      const float *dptr = dout + ((int64_t)b * Co + co) * O * O;
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const float w = Kw[((co * Ci + ci) * 3 + dy) * 3 + dx];
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const int y = 2 * yi + a - dy + 1;
+            if (y < 0 || y >= O) continue;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const int x = 2 * xi + c - dx + 1;
+              if (x < 0 || x >= O) continue;
+              acc += w * dptr[(int64_t)y * O + x];
+            }
+          }
+        }
+    }
+    din[i] = (act == nullptr || act[i] > 0.0f) ? acc : 0.0f;
+  }
+}
+
+// partial weight and bias gradients: block (pair, part) sums over its slice of
+// the (b, y, x) positions; partial[(pair * parts + part) * 10 + tap]
+__global__ __launch_bounds__(256) void upconv_bwd_weight_kernel(const float *dout, const float *in,
+                                                                int B, int Ci, int Co, int S,
+                                                                int parts, float *partial) {
+  __shared__ float red[256];
+  const int pair = blockIdx.x / parts, part = blockIdx.x % parts;
+  const int co = pair / Ci, ci = pair % Ci;
+  const int O = 2 * S;
+  const int64_t n = (int64_t)B * O * O;
+  float acc[10];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) acc[t] = 0.0f;
+  for (int64_t i = (int64_t)part * 256 + threadIdx.x; i < n; i += (int64_t)parts * 256) {
+    const int x = (int)(i % O), y = (int)((i / O) % O), b = (int)(i / ((int64_t)O * O));
+    const float g = dout[(((int64_t)b * Co + co) * O + y) * O + x];
+    if (g == 0.0f) continue;
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) acc[dy * 3 + dx] += g * up_at(in, b, ci, Ci, S, y + dy - 1, x + dx - 1);
+    acc[9] += g;
+  }
+#pragma unroll
+  for (int t = 0; t < 10; ++t) {
+    const float s = block_reduce(acc[t], red);
+    if (threadIdx.x == 0) partial[((int64_t)pair * parts + part) * 10 + t] = s;
+  }
+}
+
+__global__ void upconv_weight_finish_kernel(const float *partial, int Ci, int Co, int parts,
+                                            float *dK, float *dkb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Co * Ci * 10) return;
+  const int pair = i / 10, t = i % 10;
+  float s = 0.0f;
+  for (int p = 0; p < parts; ++p) s += partial[((int64_t)pair * parts + p) * 10 + t];
+  const int co = pair / Ci, ci = pair % Ci;
+  if (t < 9) dK[(co * Ci + ci) * 9 + t] = s;
+  else if (ci == 0) {
+    // the bias gradient is the same sum for every ci; take ci == 0
+    dkb[co] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adam (bias-corrected), fp32 master weights
+__global__ void adam_kernel(float *w, float *m, float *v, const float *g, int64_t n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// Philox4x32-10 word 0 as the uniform source of the initial weights
+__device__ uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t k0, uint32_t k1) {
+  uint32_t c2 = 0, c3 = 0;
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p2 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p2 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p2;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c0;
+}
+
+__global__ void init_uniform_kernel(float *w, int64_t n, float limit, uint32_t tensor,
+                                    uint32_t k0, uint32_t k1, int rows_used, int cols) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = philox_word0((uint32_t)i, tensor, k0, k1);
+    const float v = (2.0f * ((float)(u >> 8) * (1.0f / 16777216.0f)) - 1.0f) * limit;
+    w[i] = (rows_used > 0 && (int)(i / cols) >= rows_used) ? 0.0f : v;
+  }
+}
+
+__global__ void fill_f32_kernel(float *p, float v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// maps: packed burn maps -> coarse uint8 occupancy grid
+__global__ void pool_maps_kernel(const uint32_t *maps, int n, int W, int H, int64_t map_words,
+                                 int ow, int oh, uint8_t *out) {
+  const int64_t total = (int64_t)n * ow * oh;
+  const int stride = (W + 31) / 32;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int X = (int)(i % ow), Y = (int)((i / ow) % oh), k = (int)(i / ((int64_t)ow * oh));
+    const int x0 = (int)((int64_t)X * W / ow), x1 = (int)((int64_t)(X + 1) * W / ow);
+    const int y0 = (int)((int64_t)Y * H / oh), y1 = (int)((int64_t)(Y + 1) * H / oh);
+    const uint32_t *m = maps + (int64_t)k * map_words;
+    uint8_t any = 0;
+    for (int y = y0; y < y1 && !any; ++y)
+      for (int x = x0; x < x1; ++x)
+        if ((m[(int64_t)y * stride + (x >> 5)] >> (x & 31)) & 1u) { any = 1; break; }
+    out[i] = any;
+  }
+}
+
+}  // namespace
+}  // namespace firenn
+
+using namespace firenn;
+
+// ---------------------------------------------------------------------------
+// Handle
+
+namespace {
+constexpr int kH = 256, kIn = 16, kD0C = 8, kD0S = 16, kDec = kD0C * kD0S * kD0S;
+constexpr int kP = FIRE_NN_MAP * FIRE_NN_MAP;
+
+struct Seg {
+  int64_t off, n;
+  int rows, cols;
+};
+
+struct Layout {
+  Seg W1, c1, W2, c2, W3, c3, Wf, cf, Wd, cd, K1, k1, K2, k2, K3, k3;
+  int64_t total;
+  Layout() {
+    int64_t o = 0;
+    auto add = [&](int rows, int cols) { Seg s{o, (int64_t)rows * cols, rows, cols}; o += s.n; return s; };
+    W1 = add(kIn, kH); c1 = add(1, kH);
+    W2 = add(kH, kH); c2 = add(1, kH);
+    W3 = add(kH, kH); c3 = add(1, kH);
+    Wf = add(kH, 1); cf = add(1, 1);
+    Wd = add(kH, kDec); cd = add(1, kDec);
+    K1 = add(kD0C * kD0C, 9); k1 = add(1, kD0C);
+    K2 = add(kD0C * kD0C, 9); k2 = add(1, kD0C);
+    K3 = add(1 * kD0C, 9); k3 = add(1, 1);
+    total = o;
+  }
+};
+}  // namespace
+
+struct fire_nn {
+  int device = 0;
+  fire_nn_cfg cfg{};
+  std::string err;
+  Layout L;
+  float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // [total]
+  uint16_t *wb = nullptr;                                        // bf16 copy [total]
+  // activations (max_batch rows)
+  uint16_t *xb = nullptr, *h1b = nullptr, *h2b = nullptr, *h3b = nullptr, *d0b = nullptr, *dtb = nullptr;
+  float *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *t = nullptr, *d0 = nullptr, *d1 = nullptr,
+        *d2 = nullptr, *z = nullptr;
+  float *gt = nullptr, *gd0 = nullptr, *gd1 = nullptr, *gd2 = nullptr, *gz = nullptr, *gh = nullptr;
+  uint16_t *ghb = nullptr;
+  float *partial = nullptr, *loss = nullptr;
+  std::vector<void *> allocs;
+};
+
+namespace {
+fire_status nn_fail(fire_nn *nn, fire_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (nn) nn->err = buf;
+  return s;
+}
+#define NN_HIP(nn, expr)                                                            \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return nn_fail((nn), e_ == hipErrorOutOfMemory ? FIRE_E_OOM : FIRE_E_DEVICE, \
+                     "%s: %s", #expr, hipGetErrorString(e_));                       \
+  } while (0)
+
+template <class T>
+hipError_t nn_alloc(fire_nn *nn, T **p, int64_t count) {
+  hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
+  if (e == hipSuccess) nn->allocs.push_back(*p);
+  return e;
+}
+
+constexpr int kWeightParts = 64;
+
+hipError_t refresh_bf16(fire_nn *nn, hipStream_t s) {
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(nn->L.total)), dim3(256), 0, s, nn->w, nn->wb,
+                     nn->L.total);
+  return hipGetLastError();
+}
+
+hipError_t forward(fire_nn *nn, const float *x, int B, hipStream_t s) {
+  const Layout &L = nn->L;
+  hipError_t e;
+  hipLaunchKernelGGL(prep_input_kernel, dim3(blocks_for((int64_t)B * 16)), dim3(256), 0, s, x, B,
+                     1.0f / (float)nn->cfg.lattice_w, 1.0f / (float)nn->cfg.lattice_h, nn->xb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const uint16_t *wb = nn->wb;
+  const float *w = nn->w;
+  if ((e = gemm(B, kH, kIn, nn->xb, kIn, 1, wb + L.W1.off, kH, 1, nn->h1, kH, w + L.c1.off, 1, 0,
+                nn->h1b, s)) != hipSuccess) return e;
+  if ((e = gemm(B, kH, kH, nn->h1b, kH, 1, wb + L.W2.off, kH, 1, nn->h2, kH, w + L.c2.off, 1, 0,
+                nn->h2b, s)) != hipSuccess) return e;
+  if ((e = gemm(B, kH, kH, nn->h2b, kH, 1, wb + L.W3.off, kH, 1, nn->h3, kH, w + L.c3.off, 1, 0,
+                nn->h3b, s)) != hipSuccess) return e;
+  if ((e = gemm(B, 1, kH, nn->h3b, kH, 1, wb + L.Wf.off, 1, 1, nn->t, 1, w + L.cf.off, 0, 0,
+                nullptr, s)) != hipSuccess) return e;
+  if ((e = gemm(B, kDec, kH, nn->h3b, kH, 1, wb + L.Wd.off, kDec, 1, nn->d0, kDec, w + L.cd.off,
+                1, 0, nn->d0b, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(upconv_fwd_kernel, dim3(blocks_for((int64_t)B * kD0C * 32 * 32)), dim3(256),
+                     0, s, nn->d0, w + L.K1.off, w + L.k1.off, B, kD0C, kD0C, 16, 1, nn->d1);
+  hipLaunchKernelGGL(upconv_fwd_kernel, dim3(blocks_for((int64_t)B * kD0C * 64 * 64)), dim3(256),
+                     0, s, nn->d1, w + L.K2.off, w + L.k2.off, B, kD0C, kD0C, 32, 1, nn->d2);
+  hipLaunchKernelGGL(upconv_fwd_kernel, dim3(blocks_for((int64_t)B * kP)), dim3(256), 0, s, nn->d2,
+                     w + L.K3.off, w + L.k3.off, B, kD0C, 1, 64, 0, nn->z);
+  return hipGetLastError();
+}
+
+hipError_t conv_weight_grad(fire_nn *nn, const float *dout, const float *in, int B, int Ci, int Co,
+                            int S, float *dK, float *dkb, hipStream_t s) {
+  hipLaunchKernelGGL(upconv_bwd_weight_kernel, dim3(Co * Ci * kWeightParts), dim3(256), 0, s, dout,
+                     in, B, Ci, Co, S, kWeightParts, nn->partial);
+  hipLaunchKernelGGL(upconv_weight_finish_kernel, dim3(blocks_for((int64_t)Co * Ci * 10)),
+                     dim3(256), 0, s, nn->partial, Ci, Co, kWeightParts, dK, dkb);
+  return hipGetLastError();
+}
+
+// loss and gradients into nn->g (forward must have run on the same x)
+hipError_t backward(fire_nn *nn, const float *y_t, const uint8_t *y_map, int B, hipStream_t s) {
+  const Layout &L = nn->L;
+  hipError_t e;
+  float *g = nn->g;
+  const uint16_t *wb = nn->wb;
+  const float *w = nn->w;
+  hipLaunchKernelGGL(loss_fit_kernel, dim3(1), dim3(256), 0, s, nn->t, y_t, B, nn->gt, nn->dtb,
+                     nn->loss);
+  const int64_t nz = (int64_t)B * kP;
+  const bool use_map = y_map != nullptr && nn->cfg.w_map > 0.0f;
+  if (use_map) {
+    const int nb = 1024;
+    hipLaunchKernelGGL(loss_map_kernel, dim3(nb), dim3(256), 0, s, nn->z, y_map, nz,
+                       nn->cfg.w_map, nn->gz, nn->partial);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, nn->partial, nb,
+                       1.0f / (float)nz, nn->loss + 1);
+    // decoder backward
+    if ((e = conv_weight_grad(nn, nn->gz, nn->d2, B, kD0C, 1, 64, g + L.K3.off, g + L.k3.off, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(upconv_bwd_data_kernel, dim3(blocks_for((int64_t)B * kD0C * 64 * 64)),
+                       dim3(256), 0, s, nn->gz, w + L.K3.off, nn->d2, B, kD0C, 1, 64, nn->gd2);
+    if ((e = conv_weight_grad(nn, nn->gd2, nn->d1, B, kD0C, kD0C, 32, g + L.K2.off, g + L.k2.off, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(upconv_bwd_data_kernel, dim3(blocks_for((int64_t)B * kD0C * 32 * 32)),
+                       dim3(256), 0, s, nn->gd2, w + L.K2.off, nn->d1, B, kD0C, kD0C, 32, nn->gd1);
+    if ((e = conv_weight_grad(nn, nn->gd1, nn->d0, B, kD0C, kD0C, 16, g + L.K1.off, g + L.k1.off, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(upconv_bwd_data_kernel, dim3(blocks_for((int64_t)B * kDec)), dim3(256), 0,
+                       s, nn->gd1, w + L.K1.off, nn->d0, B, kD0C, kD0C, 16, nn->gd0);
+    // dense decoder layer: gd0 already carries the ReLU mask of d0
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for((int64_t)B * kDec)), dim3(256), 0, s,
+                       nn->gd0, nn->d0b, (int64_t)B * kDec);
+    if ((e = gemm(kH, kDec, B, nn->h3b, 1, kH, nn->d0b, kDec, 1, g + L.Wd.off, kDec, nullptr, 0,
+                  0, nullptr, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum_kernel, dim3(blocks_for(kDec)), dim3(256), 0, s, nn->gd0, B, kDec,
+                       g + L.cd.off);
+  } else {
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, s, nn->loss + 1, 0.0f, (int64_t)1);
+    const int64_t o = L.Wd.off, n = L.k3.off + L.k3.n - L.Wd.off;
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks_for(n)), dim3(256), 0, s, g + o, 0.0f, n);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // fitness head
+  if ((e = gemm(kH, 1, B, nn->h3b, 1, kH, nn->dtb, 1, 1, g + L.Wf.off, 1, nullptr, 0, 0, nullptr,
+                s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(64), 0, s, nn->gt, B, 1, g + L.cf.off);
+  // dh3 = dt Wf^T (+ dd0 Wd^T)
+  if ((e = gemm(B, kH, 1, nn->dtb, 1, 1, wb + L.Wf.off, 1, 1, nn->gh, kH, nullptr, 0, 0, nullptr,
+                s)) != hipSuccess) return e;
+  if (use_map)
+    if ((e = gemm(B, kH, kDec, nn->d0b, kDec, 1, wb + L.Wd.off, 1, kDec, nn->gh, kH, nullptr, 0, 1,
+                  nullptr, s)) != hipSuccess) return e;
+  // through the three hidden layers
+  struct Lay { const uint16_t *in_b; const float *act; const Seg *W; const Seg *c; int kin; };
+  const Lay lays[3] = {{nn->h2b, nn->h3, &L.W3, &L.c3, kH},
+                       {nn->h1b, nn->h2, &L.W2, &L.c2, kH},
+                       {nn->xb, nn->h1, &L.W1, &L.c1, kIn}};
+  for (int li = 0; li < 3; ++li) {
+    const Lay &ly = lays[li];
+    hipLaunchKernelGGL(relu_bwd_kernel, dim3(blocks_for((int64_t)B * kH)), dim3(256), 0, s, nn->gh,
+                       ly.act, nn->ghb, (int64_t)B * kH);
+    if ((e = gemm(ly.kin, kH, B, ly.in_b, 1, ly.kin, nn->ghb, kH, 1, g + ly.W->off, kH, nullptr, 0,
+                  0, nullptr, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(colsum_kernel, dim3(blocks_for(kH)), dim3(256), 0, s, nn->gh, B, kH,
+                       g + ly.c->off);
+    if (li < 2)
+      if ((e = gemm(B, kH, kH, nn->ghb, kH, 1, wb + ly.W->off, 1, kH, nn->gh, kH, nullptr, 0, 0,
+                    nullptr, s)) != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
+extern "C" {
+
+fire_status fire_nn_create(int device, const fire_nn_cfg *cfg, uint64_t seed, fire_nn **out) {
+  if (!out || !cfg) return FIRE_E_INVALID;
+  *out = nullptr;
+  if (cfg->max_batch < 1 || cfg->max_batch > (1 << 16) || cfg->lattice_w < 1 || cfg->lattice_h < 1 ||
+      !(cfg->w_map >= 0.0f) || !(cfg->adam_b1 >= 0.0f && cfg->adam_b1 < 1.0f) ||
+      !(cfg->adam_b2 >= 0.0f && cfg->adam_b2 < 1.0f) || !(cfg->adam_eps > 0.0f))
+    return FIRE_E_INVALID;
+  fire_nn *nn = new (std::nothrow) fire_nn();
+  if (!nn) return FIRE_E_OOM;
+  nn->device = device;
+  nn->cfg = *cfg;
+  const int64_t Bm = cfg->max_batch, T = nn->L.total;
+  auto fail_out = [&](hipError_t e) {
+    fire_nn_destroy(nn);
+    return e == hipErrorOutOfMemory ? FIRE_E_OOM : FIRE_E_DEVICE;
+  };
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->w, T);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->m, T);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->v, T);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->g, T);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->wb, T);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->xb, Bm * kIn);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->h1b, Bm * kH);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->h2b, Bm * kH);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->h3b, Bm * kH);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->d0b, Bm * kDec);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->dtb, Bm);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->ghb, Bm * kH);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->h1, Bm * kH);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->h2, Bm * kH);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->h3, Bm * kH);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->t, Bm);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->d0, Bm * kDec);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->d1, Bm * kD0C * 32 * 32);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->d2, Bm * kD0C * 64 * 64);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->z, Bm * kP);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->gt, Bm);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->gd0, Bm * kDec);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->gd1, Bm * kD0C * 32 * 32);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->gd2, Bm * kD0C * 64 * 64);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->gz, Bm * kP);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->gh, Bm * kH);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->partial, (int64_t)kD0C * kD0C * kWeightParts * 10 + 1024);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->loss, 2);
+  if (e != hipSuccess) return fail_out(e);
+  // initial parameters
+  const Layout &L = nn->L;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks_for(T)), dim3(256), 0, nullptr, nn->w, 0.0f, T);
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks_for(T)), dim3(256), 0, nullptr, nn->m, 0.0f, T);
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks_for(T)), dim3(256), 0, nullptr, nn->v, 0.0f, T);
+  struct Init { const Seg *s; float fan_in, fan_out; int rows_used; };
+  const Init inits[] = {{&L.W1, (float)FIRE_NN_IN, (float)kH, FIRE_NN_IN}, {&L.W2, kH, kH, 0},
+                        {&L.W3, kH, kH, 0}, {&L.Wf, kH, 1, 0}, {&L.Wd, kH, kDec, 0},
+                        {&L.K1, kD0C * 9.0f, kD0C * 9.0f, 0}, {&L.K2, kD0C * 9.0f, kD0C * 9.0f, 0},
+                        {&L.K3, kD0C * 9.0f, 9.0f, 0}};
+  uint32_t tensor = 1;
+  for (const Init &in : inits) {
+    const float limit = sqrtf(6.0f / (in.fan_in + in.fan_out));
+    hipLaunchKernelGGL(init_uniform_kernel, dim3(blocks_for(in.s->n)), dim3(256), 0, nullptr,
+                       nn->w + in.s->off, in.s->n, limit, tensor++, k0, k1, in.rows_used, in.s->cols);
+  }
+  e = refresh_bf16(nn, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail_out(e);
+  *out = nn;
+  return FIRE_OK;
+}
+
+void fire_nn_destroy(fire_nn *nn) {
+  if (!nn) return;
+  (void)hipSetDevice(nn->device);
+  (void)hipDeviceSynchronize();
+  for (void *p : nn->allocs) (void)hipFree(p);
+  delete nn;
+}
+
+const char *fire_nn_last_error(const fire_nn *nn) { return nn ? nn->err.c_str() : "null handle"; }
+
+int64_t fire_nn_num_params(const fire_nn *nn) { return nn ? nn->L.total : 0; }
+
+fire_status fire_nn_get_params(fire_nn *nn, float *out, void *stream) {
+  if (!nn) return FIRE_E_INVALID;
+  if (!out) return nn_fail(nn, FIRE_E_INVALID, "null output");
+  NN_HIP(nn, hipSetDevice(nn->device));
+  NN_HIP(nn, hipMemcpyAsync(out, nn->w, sizeof(float) * nn->L.total, hipMemcpyDeviceToDevice,
+                            (hipStream_t)stream));
+  return FIRE_OK;
+}
+
+fire_status fire_nn_set_params(fire_nn *nn, const float *in, void *stream) {
+  if (!nn) return FIRE_E_INVALID;
+  if (!in) return nn_fail(nn, FIRE_E_INVALID, "null input");
+  NN_HIP(nn, hipSetDevice(nn->device));
+  NN_HIP(nn, hipMemcpyAsync(nn->w, in, sizeof(float) * nn->L.total, hipMemcpyDeviceToDevice,
+                            (hipStream_t)stream));
+  NN_HIP(nn, refresh_bf16(nn, (hipStream_t)stream));
+  return FIRE_OK;
+}
+
+fire_status fire_nn_forward(fire_nn *nn, const float *x, int32_t B, float *out_t, float *out_map,
+                            void *stream) {
+  if (!nn) return FIRE_E_INVALID;
+  if (!x || !out_t || B < 1 || B > nn->cfg.max_batch)
+    return nn_fail(nn, FIRE_E_INVALID, "bad batch (1..%d) or null pointer", nn->cfg.max_batch);
+  NN_HIP(nn, hipSetDevice(nn->device));
+  hipStream_t s = (hipStream_t)stream;
+  NN_HIP(nn, forward(nn, x, B, s));
+  NN_HIP(nn, hipMemcpyAsync(out_t, nn->t, sizeof(float) * B, hipMemcpyDeviceToDevice, s));
+  if (out_map) {
+    hipLaunchKernelGGL(sigmoid_kernel, dim3(blocks_for((int64_t)B * kP)), dim3(256), 0, s, nn->z,
+                       out_map, (int64_t)B * kP);
+    NN_HIP(nn, hipGetLastError());
+  }
+  return FIRE_OK;
+}
+
+fire_status fire_nn_gradients(fire_nn *nn, const float *x, const float *y_t, const uint8_t *y_map,
+                              int32_t B, float *out_loss, float *out_grads, void *stream) {
+  if (!nn) return FIRE_E_INVALID;
+  if (!x || !y_t || !out_loss || B < 1 || B > nn->cfg.max_batch)
+    return nn_fail(nn, FIRE_E_INVALID, "bad batch (1..%d) or null pointer", nn->cfg.max_batch);
+  NN_HIP(nn, hipSetDevice(nn->device));
+  hipStream_t s = (hipStream_t)stream;
+  NN_HIP(nn, forward(nn, x, B, s));
+  NN_HIP(nn, backward(nn, y_t, y_map, B, s));
+  NN_HIP(nn, hipMemcpyAsync(out_loss, nn->loss, 2 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (out_grads)
+    NN_HIP(nn, hipMemcpyAsync(out_grads, nn->g, sizeof(float) * nn->L.total,
+                              hipMemcpyDeviceToDevice, s));
+  return FIRE_OK;
+}
+
+fire_status fire_nn_train_step(fire_nn *nn, const float *x, const float *y_t, const uint8_t *y_map,
+                               int32_t B, float lr, int32_t step, float *out_loss, void *stream) {
+  if (!nn) return FIRE_E_INVALID;
+  if (!x || !y_t || B < 1 || B > nn->cfg.max_batch || step < 1 || !(lr > 0.0f))
+    return nn_fail(nn, FIRE_E_INVALID, "bad batch, step or learning rate");
+  NN_HIP(nn, hipSetDevice(nn->device));
+  hipStream_t s = (hipStream_t)stream;
+  NN_HIP(nn, forward(nn, x, B, s));
+  NN_HIP(nn, backward(nn, y_t, y_map, B, s));
+  const float c1 = 1.0f - powf(nn->cfg.adam_b1, (float)step);
+  const float c2 = 1.0f - powf(nn->cfg.adam_b2, (float)step);
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(nn->L.total)), dim3(256), 0, s, nn->w, nn->m,
+                     nn->v, nn->g, nn->L.total, lr, nn->cfg.adam_b1, nn->cfg.adam_b2,
+                     nn->cfg.adam_eps, c1, c2);
+  NN_HIP(nn, hipGetLastError());
+  NN_HIP(nn, refresh_bf16(nn, s));
+  if (out_loss)
+    NN_HIP(nn, hipMemcpyAsync(out_loss, nn->loss, 2 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return FIRE_OK;
+}
+
+fire_status fire_gemm_bf16(int M, int N, int K, const uint16_t *A, int64_t sam, int64_t sak,
+                           const uint16_t *Bm, int64_t sbk, int64_t sbn, float *C, int64_t ldc,
+                           const float *bias, int relu, int accumulate, uint16_t *Cb,
+                           void *stream) {
+  if (M < 1 || N < 1 || K < 1 || !A || !Bm || !C || ldc < N) return FIRE_E_INVALID;
+  if (gemm(M, N, K, A, sam, sak, Bm, sbk, sbn, C, ldc, bias, relu, accumulate, Cb,
+           (hipStream_t)stream) != hipSuccess)
+    return FIRE_E_DEVICE;
+  return FIRE_OK;
+}
+
+fire_status fire_pool_maps(const uint32_t *maps, int32_t n, int32_t W, int32_t H,
+                           int64_t map_words, int32_t out_w, int32_t out_h, uint8_t *out,
+                           void *stream) {
+  if (!maps || !out || n < 0 || W < 1 || H < 1 || out_w < 1 || out_h < 1 || out_w > W ||
+      out_h > H || map_words < (int64_t)H * ((W + 31) / 32))
+    return FIRE_E_INVALID;
+  if (n == 0) return FIRE_OK;
+  const int64_t total = (int64_t)n * out_w * out_h;
+  hipLaunchKernelGGL(pool_maps_kernel, dim3(blocks_for(total)), dim3(256), 0, (hipStream_t)stream,
+                     maps, n, W, H, map_words, out_w, out_h, out);
+  return hipGetLastError() == hipSuccess ? FIRE_OK : FIRE_E_DEVICE;
+}
+
+}  // extern "C"

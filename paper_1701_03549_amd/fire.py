@@ -29,7 +29,7 @@ STATUS = {0: "FIRE_OK", -1: "FIRE_E_INVALID", -2: "FIRE_E_OOM", -3: "FIRE_E_DEVI
 EXPORTS = ["fire_ctx_create", "fire_ctx_destroy", "fire_last_error", "fire_sync", "fire_version",
            "fire_landscape_load", "fire_landscape_free", "fire_target_load", "fire_target_free",
            "fire_thresholds", "fire_run", "fire_run_dev", "fire_set_schedule",
-           "fire_get_schedule", "fire_ga_step", "fire_ga_run", "fire_ensemble",
+           "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_run", "fire_ensemble",
            "fire_scan_reduce"]
 
 
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "fire_run_dev": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_set_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
         "fire_get_schedule": (i32, [vp, i64, i32, ctypes.POINTER(Schedule)]),
+        "fire_set_class_schedule": (i32, [vp, i64, ctypes.POINTER(Schedule)]),
         "fire_ga_step": (i32, [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(GACfg), u32, u64, vp]),
         "fire_ga_run": (i32, [vp, i32, i32, i32, i32, vp, i32, i32, ctypes.POINTER(GACfg), u64,
                               u64, vp, vp, vp]),
@@ -243,6 +244,15 @@ class FireGPU:
             return
         s = Schedule(int(threads), int(queue_cap), int(table_mode), int(wg_per_cu))
         self._check(self.lib.fire_set_schedule(self.ctx, ctypes.byref(s)))
+
+    def set_class_schedule(self, max_cells: int, sched: dict | None):
+        """Schedule for runs on landscapes of the size class of ``max_cells``."""
+        if sched is None:
+            self._check(self.lib.fire_set_class_schedule(self.ctx, int(max_cells), None))
+            return
+        s = Schedule(int(sched["threads"]), int(sched["queue_cap"]), int(sched["table_mode"]),
+                     int(sched["wg_per_cu"]))
+        self._check(self.lib.fire_set_class_schedule(self.ctx, int(max_cells), ctypes.byref(s)))
 
     def get_schedule(self, max_cells: int, n_params: int = 1) -> dict:
         s = Schedule()

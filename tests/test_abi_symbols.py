@@ -48,3 +48,13 @@ def test_null_context_is_rejected_without_gpu():
     lib.fire_ctx_create.argtypes = [ctypes.c_int, ctypes.c_void_p]
     lib.fire_ctx_create.restype = ctypes.c_int
     assert lib.fire_ctx_create(0, None) == -1
+
+
+def test_nn_library_exports():
+    from paper_1701_03549_amd import nn
+    text = open(os.path.join(ROOT, "include", "fire_nn.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    declared = sorted(set(re.findall(r"\b(fire_[a-z_0-9]+)\s*\(", text)))
+    assert sorted(nn.EXPORTS) == declared
+    lib = ctypes.CDLL(LIB)
+    assert all(hasattr(lib, n) for n in declared)

@@ -129,3 +129,36 @@ def test_scan_reduce_matches_oracle(g, shift):
     for k in ("mean", "sd", "posterior"):
         assert np.allclose(s[k].cpu().numpy(), want[k], rtol=1e-12, atol=1e-15), k
     assert abs(s["posterior"].sum().item() - 1.0) < 1e-12
+
+
+def test_ignition_scan_matches_oracle(g):
+    """Candidate scan on a 96x80 lattice with a smooth wind field: every
+    replicate's Eq. 2 value bit-exact, the reduction within 1e-12."""
+    from paper_1701_03549_amd import scan
+    W, H = 96, 80
+    ls = synth.make_landscape(W, H, 103, wind="smooth")
+    beta = (-0.9, -0.5, 0.3, 0.8, 1.0)
+    c = synth.nearest_burnable(ls["veg"], W // 2, H // 2)
+    ref, _ = oracle_target(ls, beta, c, lo=0.02, hi=0.6)
+    lid = g.load_landscape(ls)
+    tid = g.load_target(lid, ref)
+    cands = scan.candidate_grid(c, W, H, spacing=3, half=3)
+    R = 6
+    say("ignition scan")
+    out = scan.run_scan(g, lid, tid, beta, cands, R=R, seed=SEED, cutoff=0.6)
+    g.sync()
+    T = oracle.thresholds(ls, beta)
+    want = np.empty((len(cands), R))
+    for k, (x, y) in enumerate(cands):
+        for r in range(R):
+            o = oracle.simulate(ls["veg"], T, (int(x), int(y)), k * R + r, SEED)
+            want[k, r] = oracle.fitness(o["map"], ref, W, H)
+    assert np.array_equal(out["deltas"].cpu().numpy(), want)
+    red = oracle.scan_reduce(want, 0.6, tau=0.1)
+    assert np.array_equal(out["accept"].cpu().numpy(), red["accept"])
+    for k in ("mean", "sd", "posterior"):
+        assert np.allclose(out[k].cpu().numpy(), red[k], rtol=1e-12, atol=1e-15), k
+    # the true ignition is among the best-scoring candidates
+    centre_k = int(np.argmin(np.abs(cands - np.array(c)).sum(axis=1)))
+    assert out["mean"].cpu().numpy()[centre_k] <= np.sort(red["mean"])[len(cands) // 2]
+    g.free_landscape(lid)

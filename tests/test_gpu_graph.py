@@ -1,0 +1,97 @@
+"""Graph capture of a simulation launch (device descriptors) and size-class
+grouping: replays of a captured batch reproduce the eager results exactly,
+with the program's own work between replays."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import SEED, compare_with_oracle, say
+from paper_1701_03549_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    from paper_1701_03549_amd import fire
+    assert torch.cuda.is_available()
+    ctx = fire.FireGPU(0)
+    yield ctx
+    ctx.close()
+
+
+def _mixed(g, n=96):
+    from paper_1701_03549_amd import fire
+    sizes = [(128, 128, 101), (96, 200, 102), (160, 64, 103)]
+    lss = [synth.make_landscape(W, H, s) for W, H, s in sizes]
+    lids = [g.load_landscape(ls) for ls in lss]
+    rng = np.random.default_rng(31)
+    betas = rng.uniform(-4, 3, size=(n, 5))
+    which = rng.integers(0, 3, size=n)
+    sims = np.concatenate([
+        fire.make_sims(1, lids[w], -1, synth.nearest_burnable(lss[w]["veg"], sizes[w][0] // 2,
+                                                                sizes[w][1] // 2),
+                       param_index=i, sim_index=7000 + i) for i, w in enumerate(which)])
+    return lss, lids, betas, which, sims
+
+
+def test_captured_run_replays_match_eager(g):
+    import torch
+    lss, lids, betas, which, sims = _mixed(g)
+    n = len(sims)
+    d_sims = torch.from_numpy(sims.view(np.uint8).copy()).cuda()
+    d_beta = torch.from_numpy(betas.copy()).cuda()
+    out = torch.empty((n, 24), dtype=torch.uint8, device="cuda")
+    say("graph: eager")
+    g.run_dev(d_beta, d_sims, n, SEED, out)
+    g.sync()
+    eager = out.clone()
+    graph = torch.cuda.CUDAGraph()
+    say("graph: capture")
+    with torch.cuda.graph(graph):
+        g.run_dev(d_beta, d_sims, n, SEED, out, stream=torch.cuda.current_stream())
+    for k in range(3):
+        say(f"graph: replay {k}")
+        out.zero_()
+        scratch = torch.randn(1 << 20, device="cuda").sum()  # unrelated eager work
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), k
+        assert torch.isfinite(scratch)
+    g.sync()
+    for lid in lids:
+        g.free_landscape(lid)
+
+
+def test_grouped_classes_match_single_launch_and_oracle(g):
+    """fire_run groups by landscape into concurrent launches; the results
+    equal the single-launch device path and the oracle."""
+    import torch
+    from paper_1701_03549_amd import fire
+    lss, lids, betas, which, sims = _mixed(g, n=60)
+    n = len(sims)
+    say("grouped vs single")
+    res, _ = g.run(betas, sims, SEED)
+    g.sync()
+    d_sims = torch.from_numpy(sims.view(np.uint8).copy()).cuda()
+    d_beta = torch.from_numpy(betas.copy()).cuda()
+    out = torch.empty((n, 24), dtype=torch.uint8, device="cuda")
+    g.run_dev(d_beta, d_sims, n, SEED, out)
+    g.sync()
+    assert torch.equal(res, out)
+    r = fire.results_to_numpy(res)
+    for i in range(0, n, 4):
+        ls = lss[which[i]]
+        sd = sims[i:i + 1].copy()
+        sd["param_index"] = 0
+        compare_with_oracle(ls, [oracle.thresholds(ls, betas[i])], r[i:i + 1], None, sd, SEED)
+    # a class schedule changes nothing either
+    g.set_class_schedule(128 * 128, {"threads": 512, "queue_cap": 1024, "table_mode": 0,
+                                     "wg_per_cu": 2})
+    res2, _ = g.run(betas, sims, SEED)
+    g.sync()
+    assert torch.equal(res, res2)
+    g.set_class_schedule(128 * 128, None)
+    for lid in lids:
+        g.free_landscape(lid)

@@ -1,0 +1,141 @@
+"""GPU checks of the learned surrogate (through the C ABI in fire_nn.h).
+
+* the MFMA bf16 GEMM against binary64 products of the same bf16 inputs, for
+  every transpose pattern the network uses, ragged sizes and the epilogues;
+* burn-map pooling against numpy;
+* loss and every parameter gradient of the whole network against the
+  binary64 reference with the same bf16 rounding points (oracle/surrogate_ref),
+  tolerance derived from fp32 accumulation and bf16 re-rounding;
+* Adam training on a fixed batch lowers the loss.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import say
+from oracle import surrogate_ref as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_tensor(a):
+    import torch
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).cuda().to(torch.bfloat16)
+
+
+def _bits(t):
+    import torch
+    return t.view(torch.int16)
+
+
+@pytest.mark.parametrize("M,N,K,ta,tb", [(64, 64, 32, 0, 0), (100, 37, 70, 0, 0),
+                                          (256, 16, 513, 1, 0), (33, 300, 17, 0, 1),
+                                          (7, 1, 256, 0, 0), (256, 2048, 9, 1, 0),
+                                          (130, 257, 129, 1, 1)])
+def test_gemm_bf16_against_binary64(M, N, K, ta, tb):
+    import torch
+    from paper_1701_03549_amd import nn
+    say(f"gemm {M}x{N}x{K} ta={ta} tb={tb}")
+    rng = np.random.default_rng(M * N + K)
+    a = S.round_bf16(rng.normal(size=(M, K)))
+    b = S.round_bf16(rng.normal(size=(K, N)))
+    bias = rng.normal(size=N).astype(np.float32)
+    A = _bf16_tensor(a.T.copy() if ta else a)
+    Bm = _bf16_tensor(b.T.copy() if tb else b)
+    sam, sak = (1, M) if ta else (K, 1)
+    sbk, sbn = (1, K) if tb else (N, 1)
+    C = torch.full((M, N), 0.5, dtype=torch.float32, device="cuda")
+    Cb = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
+    nn.gemm_bf16(_bits(A), _bits(Bm), M, N, K, sam, sak, sbk, sbn, C, N,
+                 bias=torch.from_numpy(bias).cuda(), relu=True, accumulate=True, Cb=_bits(Cb))
+    torch.cuda.synchronize()
+    want = np.maximum(a @ b + bias + 0.5, 0.0)
+    got = C.cpu().numpy().astype(np.float64)
+    # fp32 accumulation of K products of bf16 values
+    tol = 1e-5 * np.sqrt(K) * (np.abs(a) @ np.abs(b) + 1.0)
+    assert np.all(np.abs(got - want) <= tol)
+    assert np.array_equal(Cb.float().cpu().numpy(), S.round_bf16(got).astype(np.float32))
+
+
+def test_pool_maps():
+    import torch
+    from paper_1701_03549_amd import nn, synth
+    rng = np.random.default_rng(3)
+    W, H, n = 256, 200, 5
+    m = rng.random((n, H, W)) < 0.01
+    packed = np.stack([synth.pack_bits(x) for x in m])
+    mw = packed.shape[1] * packed.shape[2]
+    t = torch.from_numpy(packed.reshape(n, -1).view(np.int32)).cuda()
+    say("pool maps")
+    out = nn.pool_maps(t, n, W, H, mw, 128, 100).cpu().numpy()
+    want = m.reshape(n, 100, 2, 128, 2).any(axis=(2, 4))
+    assert np.array_equal(out.astype(bool), want)
+
+
+def _random_problem(B, seed, W=256, H=256):
+    rng = np.random.default_rng(seed)
+    x = np.column_stack([rng.uniform(-10, 10, size=(B, 5)), rng.integers(0, W, B),
+                         rng.integers(0, H, B)]).astype(np.float32)
+    y_t = rng.uniform(0, 3, size=B).astype(np.float32)
+    y_map = (rng.random((B, 128, 128)) < 0.2).astype(np.uint8)
+    return x, y_t, y_map
+
+
+def test_gradients_match_reference():
+    import torch
+    from paper_1701_03549_amd import nn
+    B, W, H = 6, 256, 256
+    net = nn.Surrogate(max_batch=64, lattice=(W, H), w_map=0.5, seed=11)
+    # biases shifted positive so that most ReLUs are active (sharper test)
+    p = net.get_params().cpu().numpy().astype(np.float64)
+    d = S.unflatten(p)
+    rng = np.random.default_rng(4)
+    for k in ("c1", "c2", "c3", "cd", "k1", "k2"):
+        d[k] = rng.uniform(0.02, 0.1, size=d[k].shape)
+    p = S.flatten(d).astype(np.float32)
+    net.set_params(torch.from_numpy(p))
+    x, y_t, y_map = _random_problem(B, 5, W, H)
+    say("surrogate gradients")
+    loss, g = net.gradients(torch.from_numpy(x), torch.from_numpy(y_t),
+                            torch.from_numpy(y_map).cuda())
+    torch.cuda.synchronize()
+    lf, lm, gw = S.loss_and_grads(p.astype(np.float64), x, y_t, y_map, W, H, 0.5, bf16=True)
+    loss = loss.cpu().numpy()
+    assert abs(loss[0] - lf) <= 1e-3 * abs(lf) + 1e-6
+    assert abs(loss[1] - lm) <= 1e-3 * abs(lm) + 1e-6
+    g = g.cpu().numpy().astype(np.float64)
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in S.layout()])
+    for (name, _), o0, o1 in zip(S.layout(), offs[:-1], offs[1:]):
+        a, b = g[o0:o1], gw[o0:o1]
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+        # fp32 accumulation, and bf16 re-rounding of activations that land on
+        # a rounding boundary differently in fp32 and binary64
+        assert err < 2e-2, (name, err)
+    # forward agrees too
+    t, mp = net.forward(torch.from_numpy(x), want_map=True)
+    c = S.forward(p.astype(np.float64), x, W, H, bf16=True)
+    assert np.allclose(t.cpu().numpy(), c["t"], rtol=1e-2, atol=1e-3)
+    assert np.allclose(mp.cpu().numpy(), 1 / (1 + np.exp(-c["z"])), atol=2e-3)
+    net.close()
+
+
+def test_training_lowers_loss():
+    import torch
+    from paper_1701_03549_amd import nn
+    B = 64
+    net = nn.Surrogate(max_batch=B, lattice=(256, 256), w_map=1.0, seed=3)
+    x, _, _ = _random_problem(B, 9)
+    # a smooth target of the inputs and a map that depends on the ignition
+    y_t = (np.tanh(x[:, 0] / 10.0) + 0.5 * np.cos(x[:, 1] / 5.0) + 1.5).astype(np.float32)
+    yy, xx = np.mgrid[0:128, 0:128]
+    y_map = np.stack([((xx - xi / 2) ** 2 + (yy - yi / 2) ** 2 < 400) for xi, yi in x[:, 5:7]])
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.from_numpy(y_t).cuda()
+    ym = torch.from_numpy(y_map.astype(np.uint8)).cuda()
+    say("surrogate training")
+    first = net.train_step(xt, yt, ym, lr=1e-3).cpu().numpy()
+    for _ in range(150):
+        last = net.train_step(xt, yt, ym, lr=1e-3)
+    last = last.cpu().numpy()
+    assert last[0] < 0.2 * first[0]
+    assert last[1] < first[1]
+    net.close()
