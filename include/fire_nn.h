@@ -106,6 +106,16 @@ fire_status fire_pool_maps(const uint32_t *maps, int32_t n, int32_t W,
                            int32_t H, int64_t map_words, int32_t out_w,
                            int32_t out_h, uint8_t *out, void *stream);
 
+/* Screening selection for oversampled GA offspring: out [k][G] receives
+ * the first `keep` rows of cand unchanged (the elites), then the k - keep
+ * rows of cand[keep..n) with the lowest score, in ascending score order
+ * (ties by row index); out_idx [k] (NULL allowed) their row numbers.
+ * cand [n][G] binary64, score [n] fp32 (non-finite scores rank last);
+ * 1 <= k <= n <= 4096, 0 <= keep <= k. */
+fire_status fire_nn_select(const double *cand, const float *score, int32_t n,
+                           int32_t G, int32_t keep, int32_t k, double *out,
+                           int32_t *out_idx, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,7 +38,7 @@ def cells_bucket(cells: int) -> int:
 
 
 def candidates(table_ok: bool):
-    for threads, wg, qcap in itertools.product((128, 256, 512), (1, 2, 4, 8), (1024, 4096)):
+    for threads, wg, qcap in itertools.product((256, 512, 1024), (1, 2, 4, 8), (1024, 4096)):
         for table in ((0, 1) if table_ok else (0,)):
             yield {"threads": threads, "queue_cap": qcap, "table_mode": table, "wg_per_cu": wg}
 
@@ -114,9 +114,13 @@ def workloads():
 
 
 def main():
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=CACHE, help="cache file to update")
+    args = ap.parse_args()
     log = lambda m: print(f"[autotune] {m}", flush=True)  # noqa: E731
     g = fire.FireGPU(0)
-    cache = load_cache()
+    cache = load_cache(args.out)
     arch = arch_name()
     mine = cache.setdefault(arch, {})
     best_by_bucket = {}
@@ -137,9 +141,9 @@ def main():
         best, ms = kinds.get("random", kinds.get("table"))
         mine[b] = {"schedule": best, "ms": ms,
                    "replicate_batch": kinds.get("table", (None, None))[0]}
-    with open(CACHE, "w") as f:
+    with open(args.out, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
-    log(f"wrote {CACHE}")
+    log(f"wrote {args.out}")
     g.close()
 
 

@@ -175,7 +175,7 @@ size_t lds_bytes_for(int bitset_words, int queue_cap) {
 fire_schedule default_schedule(const fire_ctx *c, int64_t max_cells,
                                int bitset_words, int32_t n_params) {
   fire_schedule s{};
-  s.threads = max_cells <= 4096 ? 64 : (max_cells <= 16384 ? 128 : 256);
+  s.threads = max_cells <= 4096 ? 256 : 512;
   s.table_mode = n_params <= 8 ? 1 : 0;
   size_t budget = c->max_lds;  // per CU
   int per_cu = 1;

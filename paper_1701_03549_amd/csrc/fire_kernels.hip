@@ -209,7 +209,7 @@ enum CtlSlot { kSim = 0, kLen0 = 1, kTrials = 4, kNew = 5, kInter = 6, kRowLo = 
 
 // register-resident rounds of the small-front step (fronts of up to
 // kRegRounds * BLOCK / 8 cells)
-constexpr int kRegRounds = 2;
+constexpr int kRegRounds = 4;
 
 template <int BLOCK, bool TABLE>
 __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {

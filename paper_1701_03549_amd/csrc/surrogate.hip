@@ -379,6 +379,33 @@ __global__ void pool_maps_kernel(const uint32_t *maps, int n, int W, int H, int6
   }
 }
 
+// rank of each non-elite candidate by (score, index); one workgroup
+__global__ __launch_bounds__(1024) void select_kernel(const double *cand, const float *score,
+                                                      int n, int G, int keep, int k, double *out,
+                                                      int32_t *out_idx) {
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    int slot;
+    if (i < keep) {
+      slot = i;
+    } else {
+      const float si = score[i];
+      const bool fi = isfinite(si);
+      int rank = 0;
+      for (int j = keep; j < n; ++j) {
+        const float sj = score[j];
+        const bool fj = isfinite(sj);
+        const bool before = (fj && !fi) || (fj == fi && ((fi && sj < si) || ((!fi || sj == si) && j < i)));
+        rank += before ? 1 : 0;
+      }
+      slot = keep + rank;
+    }
+    if (slot < k) {
+      for (int c = 0; c < G; ++c) out[(int64_t)slot * G + c] = cand[(int64_t)i * G + c];
+      if (out_idx) out_idx[slot] = i;
+    }
+  }
+}
+
 }  // namespace
 }  // namespace firenn
 
@@ -750,6 +777,16 @@ fire_status fire_pool_maps(const uint32_t *maps, int32_t n, int32_t W, int32_t H
   const int64_t total = (int64_t)n * out_w * out_h;
   hipLaunchKernelGGL(pool_maps_kernel, dim3(blocks_for(total)), dim3(256), 0, (hipStream_t)stream,
                      maps, n, W, H, map_words, out_w, out_h, out);
+  return hipGetLastError() == hipSuccess ? FIRE_OK : FIRE_E_DEVICE;
+}
+
+fire_status fire_nn_select(const double *cand, const float *score, int32_t n, int32_t G,
+                           int32_t keep, int32_t k, double *out, int32_t *out_idx, void *stream) {
+  if (!cand || !score || !out || n < 1 || n > 4096 || G < 1 || k < 1 || k > n || keep < 0 ||
+      keep > k)
+    return FIRE_E_INVALID;
+  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, cand, score, n,
+                     G, keep, k, out, out_idx);
   return hipGetLastError() == hipSuccess ? FIRE_OK : FIRE_E_DEVICE;
 }
 

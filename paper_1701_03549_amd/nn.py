@@ -11,7 +11,7 @@ from . import fire
 
 EXPORTS = ["fire_nn_create", "fire_nn_destroy", "fire_nn_last_error", "fire_nn_num_params",
            "fire_nn_get_params", "fire_nn_set_params", "fire_nn_forward", "fire_nn_gradients",
-           "fire_nn_train_step", "fire_gemm_bf16", "fire_pool_maps"]
+           "fire_nn_train_step", "fire_gemm_bf16", "fire_pool_maps", "fire_nn_select"]
 MAP = 128
 
 
@@ -45,6 +45,7 @@ def _lib():
         "fire_gemm_bf16": (i32, [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, i64, i64, vp, i64,
                                  i64, vp, i64, vp, ctypes.c_int, ctypes.c_int, vp, vp]),
         "fire_pool_maps": (i32, [vp, i32, i32, i32, i64, i32, i32, vp, vp]),
+        "fire_nn_select": (i32, [vp, vp, i32, i32, i32, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -81,6 +82,19 @@ def pool_maps(maps: torch.Tensor, n: int, W: int, H: int, map_words: int, out_w=
     if st != 0:
         raise fire.FireError(st, "fire_pool_maps failed")
     return out
+
+
+def select(cand: torch.Tensor, score: torch.Tensor, keep: int, k: int, stream=None):
+    """Keep the first `keep` rows, then the k - keep lowest-score rows."""
+    lib = _lib()
+    n, G = cand.shape
+    out = torch.empty((k, G), dtype=torch.float64, device=cand.device)
+    idx = torch.empty(k, dtype=torch.int32, device=cand.device)
+    st = lib.fire_nn_select(_p(cand.contiguous()), _p(score.contiguous()), n, G, keep, k, _p(out),
+                            _p(idx), _s(stream))
+    if st != 0:
+        raise fire.FireError(st, "fire_nn_select failed")
+    return out, idx
 
 
 class Surrogate:

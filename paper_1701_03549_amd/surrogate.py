@@ -1,0 +1,130 @@
+"""Learned-surrogate pipeline over the library (sequencing of ABI calls).
+
+1. ``make_dataset``: runs of the simulator (fire_run) on one landscape with
+   parameter vectors drawn uniformly from the GA search box and ignitions
+   uniform in the central half of the lattice; each run gives the inputs
+   (beta, ignition), the target log(1 + delta) of its Eq. 2 fitness against
+   the reference map, and its burn map pooled to 128x128 (fire_pool_maps).
+2. ``train``: Adam on the fire_nn surrogate (MFMA bf16 GEMMs).
+3. ``run_ga``: the GA (Appendix B operators on the device) where, with
+   ``oversample > 1``, each generation draws `oversample` offspring sets
+   from the same parents, ranks all non-elite offspring by the surrogate's
+   prediction (fire_nn_select) and keeps the best; every kept individual is
+   then evaluated by exact simulation, which is what the GA uses. With
+   ``oversample == 1`` it is the plain GA and reproduces fire_ga_run.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import fire, nn
+
+
+def make_dataset(g: fire.FireGPU, lid: int, tid: int, n: int, seed: int, sim_seed: int,
+                 box=(-30.0, 30.0), chunk=8192, maps=True):
+    W, H = g.dims[lid]
+    rng = np.random.default_rng(seed)
+    betas = rng.uniform(box[0], box[1], size=(n, 5))
+    ign = np.stack([rng.integers(W // 4, 3 * W // 4, n), rng.integers(H // 4, 3 * H // 4, n)], 1)
+    X = torch.empty((n, 7), dtype=torch.float32, device=g.device)
+    y_t = torch.empty(n, dtype=torch.float32, device=g.device)
+    y_map = torch.empty((n, nn.MAP, nn.MAP), dtype=torch.uint8, device=g.device) if maps else None
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        sims = fire.make_sims(e - s, lid, tid, ign[s:e], param_index=np.arange(e - s),
+                              sim_index=np.arange(s, e, dtype=np.uint32))
+        res, m = g.run(betas[s:e], sims, sim_seed, want_maps=maps)
+        delta = res.view(torch.float64).reshape(-1, 3)[:, 2]
+        y_t[s:e] = torch.log1p(delta).float()
+        X[s:e, :5] = torch.from_numpy(betas[s:e]).float().to(g.device)
+        X[s:e, 5:] = torch.from_numpy(ign[s:e]).float().to(g.device)
+        if maps:
+            y_map[s:e] = nn.pool_maps(m, e - s, W, H, m.shape[1])
+    g.sync()
+    return X, y_t, y_map
+
+
+def train(net: nn.Surrogate, X, y_t, y_map, epochs=4, batch=512, lr=1e-3, seed=0, log=None):
+    n = X.shape[0]
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=gen).to(X.device)
+        acc = torch.zeros(2, device=X.device)
+        k = 0
+        for s in range(0, n - batch + 1, batch):
+            idx = perm[s:s + batch]
+            xm = y_map[idx] if y_map is not None else None
+            acc += net.train_step(X[idx], y_t[idx], xm, lr=lr)
+            k += 1
+        ep_loss = (acc / max(k, 1)).cpu().numpy()
+        hist.append(ep_loss)
+        if log:
+            log(f"epoch {ep}: fitness loss {ep_loss[0]:.4f}, map loss {ep_loss[1]:.4f}")
+    return hist
+
+
+def spearman(a: np.ndarray, b: np.ndarray) -> float:
+    ra = np.argsort(np.argsort(a)).astype(np.float64)
+    rb = np.argsort(np.argsort(b)).astype(np.float64)
+    ra -= ra.mean()
+    rb -= rb.mean()
+    return float((ra * rb).sum() / np.sqrt((ra ** 2).sum() * (rb ** 2).sum()))
+
+
+def run_ga(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=0, ga_seed=0,
+           net: nn.Surrogate | None = None, oversample=1, cfg=None):
+    """GA with optional surrogate screening. Returns (hist_pop, hist_fit,
+    timings)."""
+    from .ga import default_cfg
+    cfg = cfg or default_cfg(generations)
+    W, H = g.dims[lid]
+    P = pop0.shape[0]
+    E = int(cfg.elite)
+    dev = g.device
+    stream = torch.cuda.current_stream()
+    pop = torch.from_numpy(np.ascontiguousarray(pop0, dtype=np.float64)).to(dev)
+    hist_pop = torch.empty((generations, P, 5), dtype=torch.float64, device=dev)
+    hist_fit = torch.empty((generations, P, R), dtype=torch.float64, device=dev)
+    res = torch.empty((P * R, 24), dtype=torch.uint8, device=dev)
+    base = fire.make_sims(P * R, lid, tid, ign, param_index=np.repeat(np.arange(P), R))
+    t_sim = t_nn = 0.0
+    for gen in range(generations):
+        sims = base.copy()
+        sims["sim_index"] = (gen * P * R + np.arange(P * R)).astype(np.uint32)
+        d_sims = torch.from_numpy(sims.view(np.uint8).copy()).to(dev)
+        hist_pop[gen].copy_(pop)
+        t0 = time.perf_counter()
+        g.run_dev(pop, d_sims, P * R, sim_seed, res, stream=stream)
+        fit = res.view(torch.float64).reshape(P * R, 3)[:, 2].reshape(P, R).contiguous()
+        hist_fit[gen].copy_(fit)
+        torch.cuda.synchronize()
+        t_sim += time.perf_counter() - t0
+        if net is None or oversample <= 1:
+            g.ga_step(pop, fit, cfg, gen, ga_seed, stream=stream)
+            continue
+        t0 = time.perf_counter()
+        sets = []
+        for o in range(oversample):
+            p = pop.clone()
+            g.ga_step(p, fit, cfg, gen, ga_seed + o * 0x9E3779B97F4A7C15, stream=stream)
+            sets.append(p if o == 0 else p[E:])
+        cand = torch.cat(sets).contiguous()
+        x = torch.empty((cand.shape[0], 7), dtype=torch.float32, device=dev)
+        x[:, :5] = cand.float()
+        x[:, 5] = float(ign[0])
+        x[:, 6] = float(ign[1])
+        score = net.predict(x)
+        pop, _ = nn.select(cand, score, keep=E, k=P)
+        torch.cuda.synchronize()
+        t_nn += time.perf_counter() - t0
+    g.sync()
+    return hist_pop, hist_fit, {"simulation_s": t_sim, "screening_s": t_nn}
+
+
+def best_mean_fitness(hist_fit: torch.Tensor) -> float:
+    """Lowest mean-over-replicates fitness of any evaluated individual."""
+    return float(hist_fit.mean(dim=2).min().item())

@@ -167,3 +167,23 @@ def nearest_burnable(veg: np.ndarray, x: int, y: int):
     d2 = (xs - x) ** 2 + (ys - y) ** 2
     k = np.lexsort((xs, ys, d2))[0]
     return int(xs[k]), int(ys[k])
+
+
+def ignition_site(ls: dict, x=None, y=None):
+    """Reference ignition of the workloads: the burnable cell nearest (x, y)
+    (default: the centre) on a slope steeper than 5 degrees facing within 45
+    degrees of north-west, the driest exposure in the paper's study area; the
+    reference fires of the benchmarks start there so that they stay on their
+    hillside, as the paper's reference fire stays away from the lattice edge."""
+    veg = np.asarray(ls["veg"])
+    H, W = veg.shape
+    x = W // 2 if x is None else x
+    y = H // 2 if y is None else y
+    dev = (np.asarray(ls["aspect_deg"], dtype=np.float64) - 315.0 + 180.0) % 360.0 - 180.0
+    ok = (veg != 0) & (np.asarray(ls["slope_deg"]) > 5.0) & (np.abs(dev) <= 45.0)
+    if not ok.any():
+        return nearest_burnable(veg, x, y)
+    ys, xs = np.nonzero(ok)
+    d2 = (xs - x) ** 2 + (ys - y) ** 2
+    k = np.lexsort((xs, ys, d2))[0]
+    return int(xs[k]), int(ys[k])

@@ -7,7 +7,7 @@ from paper_1701_03549_amd import synth
 
 SEED = 0x5EED0001
 TARGET_SEED = 0x7A26E7
-BETA_STAR = (-1.15, -0.5, 0.3, 0.8, 1.0)
+BETA_STAR = (-3.0, -0.5, 6.0, 1.0, 2.0)
 
 
 def say(msg):

@@ -194,7 +194,7 @@ def test_config2_512_sampled(g):
     from paper_1701_03549_amd import fire
     W = H = 512
     ls = synth.make_landscape(W, H, 102)
-    centre = synth.nearest_burnable(ls["veg"], 256, 256)
+    centre = synth.ignition_site(ls)
     ref, _ = oracle_target(ls, BETA_STAR, centre, lo=0.01, hi=0.15)
     T = [oracle.thresholds(ls, BETA_STAR)]
     lid = g.load_landscape(ls)
