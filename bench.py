@@ -134,6 +134,69 @@ def run_ga(g, lid, tid, centre, plain: bool):
     return out
 
 
+def run_surrogate(log_fn):
+    """Learned surrogate on the 256x256 landscape (seed 105): simulator-made
+    training data, MFMA training, and the GA with and without screening."""
+    import torch
+    from paper_1701_03549_amd import fire, nn, surrogate, synth
+    g = fire.FireGPU(0)
+    W = H = 256
+    ls = synth.make_landscape(W, H, 105)
+    c = synth.ignition_site(ls)
+    lid = g.load_landscape(ls)
+    res, maps = g.run(np.array([BETA_STAR]), fire.make_sims(64, lid, -1, c), TARGET_SEED,
+                      want_maps=True)
+    g.sync()
+    r = fire.results_to_numpy(res)
+    k = int(np.argmax(r["burnt"] >= 0.001 * W * H))
+    tid = g.load_target(lid, maps.cpu().numpy().view(np.uint32)[k].reshape(H, -1))
+    n_data, epochs, batch = 100000, 4, 512
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, y_t, y_map = surrogate.make_dataset(g, lid, tid, n_data, seed=5, sim_seed=0xDA7A,
+                                           prior_sd=5.0, ign=c)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = nn.Surrogate(max_batch=batch, lattice=(W, H), w_map=1.0, seed=1)
+    n_train = n_data - n_data // 10
+    t0 = time.perf_counter()
+    surrogate.train(net, X[n_data // 10:], y_t[n_data // 10:], y_map[n_data // 10:],
+                    epochs=epochs, batch=batch)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    steps = epochs * (n_train // batch)
+    # MFMA work per sample: forward GEMMs (16x256, 2 x 256x256, 256x1, 256x2048) and
+    # twice that in the backward pass
+    gemm_flop = 3 * 2 * (16 * 256 + 2 * 256 * 256 + 256 + 256 * 2048)
+    pv = net.predict(X[:n_data // 10]).cpu().numpy()
+    rho = surrogate.spearman(pv, y_t[:n_data // 10].cpu().numpy())
+    trained = net.get_params()
+    log_fn(f"surrogate: data {t_data:.2f} s, training {t_train:.2f} s, held-out Spearman {rho:.3f}")
+    plain, screened, tp, ts = [], [], 0.0, 0.0
+    for s_ in range(5):
+        pop0 = np.clip(np.random.default_rng(100 + s_).normal(0, 5, size=(64, 5)), -30, 30)
+        t0 = time.perf_counter()
+        _, fp, _ = surrogate.run_ga(g, lid, tid, c, pop0, R=20, generations=30,
+                                    sim_seed=SIM_SEED + s_, ga_seed=GA_SEED + s_)
+        tp += time.perf_counter() - t0
+        net.set_params(trained)
+        t0 = time.perf_counter()
+        _, fs, _ = surrogate.run_ga(g, lid, tid, c, pop0, R=20, generations=30,
+                                    sim_seed=SIM_SEED + s_, ga_seed=GA_SEED + s_, net=net, seed=s_)
+        ts += time.perf_counter() - t0
+        plain.append(surrogate.best_mean_fitness(fp))
+        screened.append(surrogate.best_mean_fitness(fs))
+    net.close()
+    g.close()
+    return {"lattice": [W, H], "training_runs": n_data, "data_s": t_data,
+            "train_s": t_train, "train_samples_per_s": steps * batch / t_train,
+            "gemm_tflops": steps * batch * gemm_flop / t_train / 1e12,
+            "gemm_peak_tflops": 2500.0, "heldout_spearman": rho,
+            "ga_seeds": 5, "ga_sims_per_run": 64 * 20 * 30,
+            "plain_best_mean_fitness": plain, "screened_best_mean_fitness": screened,
+            "plain_wall_s": tp / 5, "screened_wall_s": ts / 5}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +205,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ga", action="store_true", help="skip the GA wall-time comparison")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain GA run")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise copy of 256 MiB (read) + 256 MiB (write) "
                          "three times, to scale the profiler's HBM byte counters")
@@ -243,6 +307,9 @@ def main():
         log("GA calibration runs ...")
         result["ga"] = run_ga(g, lid, tid, centre, plain=not args.no_plain)
     g.close()
+    if not args.no_surrogate:
+        log("surrogate ...")
+        result["surrogate"] = run_surrogate(log)
     print(json.dumps(result), flush=True)
 
 

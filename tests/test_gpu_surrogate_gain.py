@@ -1,0 +1,61 @@
+"""What the trained surrogate gains: the GA with surrogate screening against
+the GA without it, same seeds and the same number of exact simulations
+(64 individuals x 20 replicates x 30 generations), on the 256x256 landscape.
+Every individual the screened GA keeps is re-scored by exact simulation, so
+the comparison is on exact Eq. 2 values."""
+import numpy as np
+import pytest
+
+from gpu_util import say
+from paper_1701_03549_amd import synth
+
+pytestmark = pytest.mark.gpu
+BETA_STAR = (-3.0, -0.5, 6.0, 1.0, 2.0)
+
+
+def test_screened_ga_beats_plain_ga():
+    import torch
+    from paper_1701_03549_amd import fire, ga, nn, surrogate
+    g = fire.FireGPU(0)
+    W = H = 256
+    ls = synth.make_landscape(W, H, 105)
+    c = synth.ignition_site(ls)
+    lid = g.load_landscape(ls)
+    res, maps = g.run(np.array([BETA_STAR]), fire.make_sims(64, lid, -1, c), 0x7A26E7,
+                      want_maps=True)
+    g.sync()
+    r = fire.results_to_numpy(res)
+    k = int(np.argmax(r["burnt"] >= 0.001 * W * H))
+    ref = maps.cpu().numpy().view(np.uint32)[k].reshape(H, -1)
+    tid = g.load_target(lid, ref)
+    say("surrogate gain: dataset + training")
+    X, y_t, y_map = surrogate.make_dataset(g, lid, tid, 100000, seed=5, sim_seed=0xDA7A,
+                                           prior_sd=5.0, ign=c)
+    net = nn.Surrogate(max_batch=512, lattice=(W, H), w_map=1.0, seed=1)
+    surrogate.train(net, X[10000:], y_t[10000:], y_map[10000:], epochs=4)
+    pv = net.predict(X[:10000]).cpu().numpy()
+    assert surrogate.spearman(pv, y_t[:10000].cpu().numpy()) > 0.85
+    trained = net.get_params()
+    # the plain driver is the library's graph-captured GA, bit for bit
+    pop0 = np.clip(np.random.default_rng(0).normal(0, 5, size=(64, 5)), -30, 30)
+    hb = ga.run_batched(g, lid, tid, c, pop0, R=20, generations=3, sim_seed=1, ga_seed=2)
+    hp, hf, _ = surrogate.run_ga(g, lid, tid, c, pop0, R=20, generations=3, sim_seed=1,
+                                 ga_seed=2)
+    assert torch.equal(hb[0], hp) and torch.equal(hb[1], hf)
+    plain, screened = [], []
+    for s in range(5):
+        say(f"surrogate gain: seed {s}")
+        pop0 = np.clip(np.random.default_rng(100 + s).normal(0, 5, size=(64, 5)), -30, 30)
+        _, fp, _ = surrogate.run_ga(g, lid, tid, c, pop0, R=20, generations=30,
+                                    sim_seed=0x5EED0001 + s, ga_seed=0x6A00001 + s)
+        net.set_params(trained)
+        _, fs, _ = surrogate.run_ga(g, lid, tid, c, pop0, R=20, generations=30,
+                                    sim_seed=0x5EED0001 + s, ga_seed=0x6A00001 + s, net=net,
+                                    seed=s)
+        plain.append(surrogate.best_mean_fitness(fp))
+        screened.append(surrogate.best_mean_fitness(fs))
+    say(f"plain {np.round(plain, 4)} screened {np.round(screened, 4)}")
+    assert np.mean(screened) < np.mean(plain)
+    assert sum(b < a for a, b in zip(plain, screened)) >= 4
+    net.close()
+    g.close()
