@@ -134,6 +134,94 @@ def run_ga(g, lid, tid, centre, plain: bool):
     return out
 
 
+def run_scan(log_fn):
+    """Ignition-point scan on the 1024x1024 landscape (seed 103, smooth wind):
+    256 candidate cells on a 4-cell grid around the true ignition x 32
+    replicates, Eq. 2 against the reference fire, device reduction."""
+    import torch
+    from paper_1701_03549_amd import fire, scan, synth
+    g = fire.FireGPU(0)
+    W = H = 1024
+    ls = synth.make_landscape(W, H, 103, wind="smooth")
+    c = synth.ignition_site(ls)
+    lid = g.load_landscape(ls)
+    res, maps = g.run(np.array([BETA_STAR]), fire.make_sims(16, lid, -1, c), TARGET_SEED,
+                      want_maps=True)
+    g.sync()
+    r = fire.results_to_numpy(res)
+    k = int(np.argmax(r["burnt"]))
+    tid = g.load_target(lid, maps.cpu().numpy().view(np.uint32)[k].reshape(H, -1))
+    cands = scan.candidate_grid(c, W, H, spacing=4, half=8)
+    scan.run_scan(g, lid, tid, BETA_STAR, cands, R=32, seed=SIM_SEED, cutoff=0.3)  # warm-up
+    g.sync()
+    times = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = scan.run_scan(g, lid, tid, BETA_STAR, cands, R=32, seed=SIM_SEED, cutoff=0.3)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    mean = out["mean"].cpu().numpy()
+    true_k = int(np.argmin(np.abs(cands - np.array(c)).sum(axis=1)))
+    rank = int((mean < mean[true_k]).sum())
+    dt = float(np.median(times))
+    g.close()
+    log_fn(f"scan: {len(cands)} x 32 simulations in {dt * 1e3:.2f} ms; true ignition ranks {rank}")
+    return {"lattice": [W, H], "candidates": len(cands), "replicates": 32,
+            "wall_ms": dt * 1e3, "sims_per_s": len(cands) * 32 / dt,
+            "true_candidate_rank": rank, "reference_cells": int(r["burnt"][k])}
+
+
+def run_uneven(log_fn):
+    """2000 simulations over four landscapes of different sizes with
+    parameter vectors drawn uniformly from the search box, as one fire_run
+    (grouped by landscape into concurrent persistent launches) and as one
+    persistent launch sized for the largest lattice (fire_run_dev)."""
+    import torch
+    from paper_1701_03549_amd import fire, synth
+    g = fire.FireGPU(0)
+    sizes = [(128, 128, 101), (256, 256, 102), (512, 512, 103), (1024, 768, 104)]
+    lids, sims = [], []
+    rng = np.random.default_rng(404)
+    betas = rng.uniform(-30.0, 30.0, size=(2000, 5))
+    for k, (W, H, sd) in enumerate(sizes):
+        ls = synth.make_landscape(W, H, sd)
+        lid = g.load_landscape(ls)
+        lids.append(lid)
+        sims.append(fire.make_sims(500, lid, -1, synth.ignition_site(ls),
+                                   param_index=np.arange(500 * k, 500 * (k + 1)),
+                                   sim_index=np.arange(500 * k, 500 * (k + 1), dtype=np.uint32)))
+    sims = np.concatenate(sims)
+    res, _ = g.run(betas, sims, SIM_SEED)  # warm-up
+    g.sync()
+    d_sims = torch.from_numpy(sims.view(np.uint8).copy()).cuda()
+    d_beta = torch.from_numpy(betas).cuda()
+    out = torch.empty((2000, 24), dtype=torch.uint8, device="cuda")
+    g.run_dev(d_beta, d_sims, 2000, SIM_SEED, out)
+    g.sync()
+    tg, ts = [], []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, _ = g.run(betas, sims, SIM_SEED)
+        torch.cuda.synchronize()
+        tg.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        g.run_dev(d_beta, d_sims, 2000, SIM_SEED, out)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    same = bool(torch.equal(res, out))
+    r = fire.results_to_numpy(res)
+    trials = int(r["trials"].sum())
+    g.close()
+    dt_g, dt_s = float(np.median(tg)), float(np.median(ts))
+    log_fn(f"uneven: grouped {dt_g * 1e3:.1f} ms, single launch {dt_s * 1e3:.1f} ms")
+    return {"sims": 2000, "lattices": [[w, h] for w, h, _ in sizes],
+            "grouped_ms": dt_g * 1e3, "single_launch_ms": dt_s * 1e3,
+            "grouped_sims_per_s": 2000 / dt_g, "grouped_trials_per_s": trials / dt_g,
+            "identical_results": same, "mean_burnt": float(r["burnt"].mean())}
+
+
 def run_surrogate(log_fn):
     """Learned surrogate on the 256x256 landscape (seed 105): simulator-made
     training data, MFMA training, and the GA with and without screening."""
@@ -206,6 +294,8 @@ def main():
     ap.add_argument("--no-ga", action="store_true", help="skip the GA wall-time comparison")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain GA run")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate section")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the ignition-scan and uneven-batch sections")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain elementwise copy of 256 MiB (read) + 256 MiB (write) "
                          "three times, to scale the profiler's HBM byte counters")
@@ -307,6 +397,11 @@ def main():
         log("GA calibration runs ...")
         result["ga"] = run_ga(g, lid, tid, centre, plain=not args.no_plain)
     g.close()
+    if not args.no_extra:
+        log("ignition scan ...")
+        result["scan"] = run_scan(log)
+        log("uneven batch ...")
+        result["uneven"] = run_uneven(log)
     if not args.no_surrogate:
         log("surrogate ...")
         result["surrogate"] = run_surrogate(log)

@@ -226,11 +226,36 @@ typedef struct {
  * genes [c, G) with c = 1 + ((out0*(G-1))>>32), counter (gen, k, 1, 0);
  * gene j of non-elite slot i mutates iff out0*2^-32 < p_m(gen), counter
  * (gen, i, 2, j), by mut_h*(2*out1*2^-32 - 1), clamped to [lo, hi].
- * 1 <= P <= 1024, 2 <= G <= 16, R >= 1. Stream-ordered. */
+ * 1 <= P <= 1024, 2 <= G <= 16, R >= 1, and the population must fit the
+ * LDS of one workgroup (8*(P + 2*P*G) + 4*P bytes <= the device's LDS per
+ * workgroup, 160 KiB on gfx950). Stream-ordered. */
 fire_status fire_ga_step(fire_ctx *ctx, double *pop, const double *fit,
                          double *mean_fit, int32_t P, int32_t G, int32_t R,
                          const fire_ga_cfg *cfg, uint32_t gen,
                          uint64_t ga_seed, void *stream);
+
+/* fire_ga_step with a box and a mutation half-width per gene (host arrays
+ * lo[G], hi[G], h[G]); used when genes have different ranges, e.g. the
+ * ignition cell carried as genes 5 and 6 (Appendix B: 7 parameters when
+ * the ignition point is estimated). 2 <= G <= 16. */
+fire_status fire_ga_step_genes(fire_ctx *ctx, double *pop, const double *fit,
+                               double *mean_fit, int32_t P, int32_t G, int32_t R,
+                               int32_t elite, double pm0, const double *lo,
+                               const double *hi, const double *h,
+                               uint32_t generations, uint32_t gen,
+                               uint64_t ga_seed, void *stream);
+
+/* Descriptors of one generation whose individuals carry their ignition as
+ * genes 5 and 6 (device pop [P][G], G >= 7): out_sims [P*R] (device) with
+ * sims[i*R + r] = {landscape_id, target_id, ignition (floor(g5 + 0.5),
+ * floor(g6 + 0.5)) clamped to the lattice, param_index i, sim_index
+ * (gen*P + i)*R + r, run to extinction}; out_betas [P][5] (device) = genes
+ * 0..4. Stream-ordered. */
+fire_status fire_ga_sims_from_pop(fire_ctx *ctx, const double *pop, int32_t P,
+                                  int32_t G, int32_t R, int32_t landscape_id,
+                                  int32_t target_id, uint32_t gen,
+                                  fire_sim *out_sims, double *out_betas,
+                                  void *stream);
 
 /* A whole GA calibration on one landscape and reference map (5 genes, the
  * betas): for g in [0, generations): evaluate every individual by R
@@ -263,6 +288,23 @@ fire_status fire_ensemble(fire_ctx *ctx, const double *params,
                           int32_t R, double cutoff, int32_t *out_best,
                           int32_t *out_n, double *out_mean, double *out_sd,
                           void *stream);
+
+/* A whole GA calibration with the ignition point estimated (Appendix B:
+ * 7 parameters, beta[5] then the ignition x, y): as fire_ga_run, but each
+ * generation's simulations start at the cell of the individual's genes 5
+ * and 6 (floor(g + 0.5), clamped to the lattice; a non-burnable cell burns
+ * nothing and scores 1). lo, hi, h: host arrays [7], the clamp box and
+ * mutation half-width of each gene. pop0: host [P][7]; hist_pop: device
+ * [generations][P][7]; hist_fit: device [generations][P][R]. Returns after
+ * the last generation has finished. */
+fire_status fire_ga_run_ignition(fire_ctx *ctx, int32_t landscape_id,
+                                 int32_t target_id, const double *pop0,
+                                 int32_t P, int32_t R, int32_t elite,
+                                 double pm0, uint32_t generations,
+                                 const double *lo, const double *hi,
+                                 const double *h, uint64_t sim_seed,
+                                 uint64_t ga_seed, double *hist_pop,
+                                 double *hist_fit, void *stream);
 
 /* Ignition-scan reduction (Methods: ignition points; cutoff rule of the
  * CUDA-implementation section) over device deltas [n_cand][R]: per

@@ -83,7 +83,7 @@ def _load():
         lib.oracle_fitness.restype = ctypes.c_double
         lib.oracle_ga_step.argtypes = [
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
+            ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
             ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_ga_step.restype = ctypes.c_int
         _lib = lib
@@ -199,23 +199,37 @@ def run_batch(veg, T_by_param, sims, seed, ref_bits=None, want_maps=False, threa
         return list(ex.map(one, sims))
 
 
-def ga_step(pop: np.ndarray, fit: np.ndarray, *, elite: int, pm0: float, h: float, lo: float,
-            hi: float, gen: int, generations: int, ga_seed: int):
-    """One GA generation (Appendix B). Returns (new_pop, mean_fitness)."""
+def ga_step(pop: np.ndarray, fit: np.ndarray, *, elite: int, pm0: float, h, lo, hi, gen: int,
+            generations: int, ga_seed: int):
+    """One GA generation (Appendix B). h, lo, hi: a scalar for every gene or
+    one value per gene. Returns (new_pop, mean_fitness)."""
     lib = _load()
     pop = np.ascontiguousarray(pop, dtype=np.float64)
     fit = np.ascontiguousarray(fit, dtype=np.float64)
     P, G = pop.shape
     R = fit.shape[1]
     assert fit.shape[0] == P
+    h, lo, hi = (np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (G,)))
+                 for a in (h, lo, hi))
     new = np.empty_like(pop)
     mean = np.empty(P, dtype=np.float64)
-    rc = lib.oracle_ga_step(_ptr(pop), _ptr(fit), P, G, R, int(elite), float(pm0), float(h),
-                            float(lo), float(hi), int(gen), int(generations),
+    rc = lib.oracle_ga_step(_ptr(pop), _ptr(fit), P, G, R, int(elite), float(pm0), _ptr(h),
+                            _ptr(lo), _ptr(hi), int(gen), int(generations),
                             int(ga_seed) & ((1 << 64) - 1), _ptr(new), _ptr(mean))
     if rc != 0:
         raise ValueError("oracle_ga_step failed")
     return new, mean
+
+
+def ignition_cell(gx: float, gy: float, W: int, H: int):
+    """The lattice cell of an individual's ignition genes (Appendix B, 7
+    parameters): the paper treats the coordinates as real parameters
+    without saying how a simulation starts from them; the reading here is
+    the nearest cell, halves rounded up (floor(g + 1/2)), clamped to the
+    lattice."""
+    x = int(np.floor(gx + 0.5))
+    y = int(np.floor(gy + 0.5))
+    return min(max(x, 0), W - 1), min(max(y, 0), H - 1)
 
 
 def _sample_sd(x: np.ndarray, axis=None) -> np.ndarray:

@@ -315,8 +315,10 @@ double oracle_fitness(int W, int H, const uint32_t *sim_bits,
  *     swapped; an odd slot left over is not crossed;
  *   - each gene j of a non-elite slot i is mutated with counter
  *     (gen, i, 2, j): it mutates iff out0 * 2^-32 < pm0 * (1 - gen /
- *     generations), by delta = h * (2 * out1 * 2^-32 - 1), and the result is
- *     clamped to [lo, hi].
+ *     generations), by delta = h[j] * (2 * out1 * 2^-32 - 1), and the result
+ *     is clamped to [lo[j], hi[j]]. Each gene has its own box and width so
+ *     that the 7-parameter search of Appendix B (beta[5] and the ignition
+ *     x, y) keeps the coordinates on the lattice.
  * Only + - * / and comparisons are used, so any IEEE implementation gives
  * the same bits. pop is [P][G], fit is [P][R], new_pop is [P][G].         */
 
@@ -333,7 +335,8 @@ static int rank_cmp(const void *a, const void *b) {
 }
 
 int oracle_ga_step(const double *pop, const double *fit, int P, int G, int R,
-                   int elite, double pm0, double h, double lo, double hi,
+                   int elite, double pm0, const double *h, const double *lo,
+                   const double *hi,
                    uint32_t gen, uint32_t generations, uint64_t ga_seed,
                    double *new_pop, double *out_mean_fitness) {
   if (P <= 0 || G <= 1 || R <= 0 || elite < 0 || elite > P) return -1;
@@ -392,9 +395,9 @@ int oracle_ga_step(const double *pop, const double *fit, int P, int G, int R,
       double u0 = (double)out[0] * (1.0 / 4294967296.0);
       if (u0 < pm) {
         double u1 = (double)out[1] * (1.0 / 4294967296.0);
-        double g = new_pop[(long)i * G + j] + h * (2.0 * u1 - 1.0);
-        if (g < lo) g = lo;
-        if (g > hi) g = hi;
+        double g = new_pop[(long)i * G + j] + h[j] * (2.0 * u1 - 1.0);
+        if (g < lo[j]) g = lo[j];
+        if (g > hi[j]) g = hi[j];
         new_pop[(long)i * G + j] = g;
       }
     }

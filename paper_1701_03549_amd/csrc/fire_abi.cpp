@@ -830,44 +830,95 @@ fire_status fire_ga_step(fire_ctx *c, double *pop, const double *fit, double *me
   if (!c) return FIRE_E_INVALID;
   if (!pop || !fit || !cfg) return fail(c, FIRE_E_INVALID, "null argument");
   if (P < 1 || P > 1024 || G < 2 || G > 16 || R < 1 || cfg->elite < 0 || cfg->elite > P ||
-      cfg->generations < 1 || !(cfg->lo <= cfg->hi))
+      cfg->generations < 1 || !(cfg->lo <= cfg->hi) || ga_step_lds(P, G) > c->max_lds)
     return fail(c, FIRE_E_INVALID, "GA sizes or configuration out of range");
   HIP_OR_FAIL(c, hipSetDevice(c->device));
-  HIP_OR_FAIL(c, launch_ga_step(pop, fit, mean_fit, P, G, R, cfg->elite, cfg->pm0, cfg->mut_h,
-                                cfg->lo, cfg->hi, gen, nullptr, cfg->generations,
+  HIP_OR_FAIL(c, launch_ga_step(pop, fit, mean_fit, P, G, R, cfg->elite, cfg->pm0,
+                                uniform_box(cfg->lo, cfg->hi, cfg->mut_h), gen, nullptr,
+                                cfg->generations,
                                 (uint32_t)ga_seed, (uint32_t)(ga_seed >> 32),
                                 (hipStream_t)stream));
   return FIRE_OK;
 }
 
-fire_status fire_ga_run(fire_ctx *c, int32_t lid, int32_t tid, int32_t ign_x, int32_t ign_y,
-                        const double *pop0, int32_t P, int32_t R, const fire_ga_cfg *cfg,
-                        uint64_t sim_seed, uint64_t ga_seed, double *hist_pop,
-                        double *hist_fit, void *stream) {
+fire_status fire_ga_step_genes(fire_ctx *c, double *pop, const double *fit, double *mean_fit,
+                               int32_t P, int32_t G, int32_t R, int32_t elite, double pm0,
+                               const double *lo, const double *hi, const double *h,
+                               uint32_t generations, uint32_t gen, uint64_t ga_seed,
+                               void *stream) {
   if (!c) return FIRE_E_INVALID;
-  if (!pop0 || !cfg || !hist_pop || !hist_fit) return fail(c, FIRE_E_INVALID, "null argument");
-  const int G = 5;
-  if (P < 1 || P > 1024 || R < 1 || (int64_t)P * R > (1 << 24) || cfg->elite < 0 ||
-      cfg->elite > P || cfg->generations < 1 || !(cfg->lo <= cfg->hi))
+  if (!pop || !fit || !lo || !hi || !h) return fail(c, FIRE_E_INVALID, "null argument");
+  if (P < 1 || P > 1024 || G < 2 || G > kMaxGenes || R < 1 || elite < 0 || elite > P ||
+      generations < 1 || ga_step_lds(P, G) > c->max_lds)
+    return fail(c, FIRE_E_INVALID, "GA sizes out of range");
+  GeneBox box;
+  for (int j = 0; j < kMaxGenes; ++j) {
+    const int k = j < G ? j : G - 1;
+    if (!(lo[k] <= hi[k]) || !std::isfinite(h[k]))
+      return fail(c, FIRE_E_INVALID, "gene %d: bad box or mutation width", k);
+    box.lo[j] = lo[k];
+    box.hi[j] = hi[k];
+    box.h[j] = h[k];
+  }
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, launch_ga_step(pop, fit, mean_fit, P, G, R, elite, pm0, box, gen, nullptr,
+                                generations, (uint32_t)ga_seed, (uint32_t)(ga_seed >> 32),
+                                (hipStream_t)stream));
+  return FIRE_OK;
+}
+
+fire_status fire_ga_sims_from_pop(fire_ctx *c, const double *pop, int32_t P, int32_t G, int32_t R,
+                                  int32_t lid, int32_t tid, uint32_t gen, fire_sim *out_sims,
+                                  double *out_betas, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (!pop || !out_sims || !out_betas) return fail(c, FIRE_E_INVALID, "null argument");
+  if (P < 1 || R < 1 || G < 7 || G > kMaxGenes || (int64_t)P * R > (1 << 24))
+    return fail(c, FIRE_E_INVALID, "sizes out of range (G must hold beta[5], x, y)");
+  if (lid < 0 || lid >= (int)c->ls.size() || !c->ls[lid].live)
+    return fail(c, FIRE_E_INVALID, "unknown landscape id %d", lid);
+  if (tid != -1 && (tid < 0 || tid >= (int)c->tg.size() || !c->tg[tid].live ||
+                    c->tg[tid].landscape_id != lid))
+    return fail(c, FIRE_E_INVALID, "unknown target id %d for landscape %d", tid, lid);
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  const LandscapeHost &L = c->ls[lid];
+  HIP_OR_FAIL(c, launch_sims_from_pop(pop, P, G, R, lid, tid, L.W, L.H, gen, nullptr, out_sims, out_betas,
+                                      (hipStream_t)stream));
+  return FIRE_OK;
+}
+
+// One GA calibration as a captured generation replayed `generations` times:
+// prepare (sim indices, population history, work counter) -> [descriptors and
+// betas from the ignition genes] -> persistent simulation -> fitness gather ->
+// GA step. With ign_genes the individuals are (beta[5], x, y) and every
+// generation's ignitions come from genes 5 and 6; otherwise all simulations
+// start at (ign_x, ign_y).
+static fire_status ga_run_graph(fire_ctx *c, int32_t lid, int32_t tid, int32_t ign_x,
+                                int32_t ign_y, bool ign_genes, const double *pop0, int P, int G,
+                                int R, int elite, double pm0, const GeneBox &box,
+                                uint32_t generations, uint64_t sim_seed, uint64_t ga_seed,
+                                double *hist_pop, double *hist_fit, void *stream) {
+  if (P < 1 || P > 1024 || R < 1 || (int64_t)P * R > (1 << 24) || elite < 0 || elite > P ||
+      generations < 1 || ga_step_lds(P, G) > c->max_lds)
     return fail(c, FIRE_E_INVALID, "GA sizes or configuration out of range");
   if (lid < 0 || lid >= (int)c->ls.size() || !c->ls[lid].live)
     return fail(c, FIRE_E_INVALID, "unknown landscape id %d", lid);
   if (tid < 0 || tid >= (int)c->tg.size() || !c->tg[tid].live || c->tg[tid].landscape_id != lid)
     return fail(c, FIRE_E_INVALID, "unknown target id %d for landscape %d", tid, lid);
   const LandscapeHost &L = c->ls[lid];
-  if (ign_x < 0 || ign_x >= L.W || ign_y < 0 || ign_y >= L.H)
+  if (!ign_genes && (ign_x < 0 || ign_x >= L.W || ign_y < 0 || ign_y >= L.H))
     return fail(c, FIRE_E_INVALID, "ignition outside the lattice");
   for (int i = 0; i < P * G; ++i)
     if (!std::isfinite(pop0[i])) return fail(c, FIRE_E_INVALID, "non-finite initial population");
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   hipStream_t user = (hipStream_t)stream;
   const int n = P * R;
-  // scratch: pop [P*G] | fit [n] | results [n] | sims [n] | gen counter
+  // scratch: pop [P*G] | fit [n] | results [n] | sims [n] | betas [P*5] | gen counter
   const size_t o_pop = 0;
   const size_t o_fit = o_pop + sizeof(double) * P * G;
   const size_t o_res = (o_fit + sizeof(double) * n + 255) / 256 * 256;
   const size_t o_sims = (o_res + sizeof(fire_result) * n + 255) / 256 * 256;
-  const size_t o_gen = (o_sims + sizeof(fire_sim) * n + 255) / 256 * 256;
+  const size_t o_beta = (o_sims + sizeof(fire_sim) * n + 255) / 256 * 256;
+  const size_t o_gen = (o_beta + sizeof(double) * P * 5 + 255) / 256 * 256;
   const size_t need = o_gen + 256;
   HIP_OR_FAIL(c, hipDeviceSynchronize());
   size_t have = c->ga_bytes;
@@ -878,6 +929,7 @@ fire_status fire_ga_run(fire_ctx *c, int32_t lid, int32_t tid, int32_t ign_x, in
   double *d_fit = (double *)(base + o_fit);
   fire_result *d_res = (fire_result *)(base + o_res);
   fire_sim *d_sims = (fire_sim *)(base + o_sims);
+  double *d_beta = (double *)(base + o_beta);
   uint32_t *d_gen = (uint32_t *)(base + o_gen);
   std::vector<fire_sim> hs(n);
   for (int i = 0; i < P; ++i)
@@ -902,7 +954,7 @@ fire_status fire_ga_run(fire_ctx *c, int32_t lid, int32_t tid, int32_t ign_x, in
   SimArgs a{};
   a.ls = c->d_ls; a.n_ls = (int32_t)c->ls.size();
   a.tg = c->d_tg; a.n_tg = (int32_t)c->tg.size();
-  a.betas = d_pop; a.n_params = P;
+  a.betas = ign_genes ? d_beta : d_pop; a.n_params = P;
   a.sims = d_sims; a.n_sims = n;
   a.key0 = (uint32_t)sim_seed; a.key1 = (uint32_t)(sim_seed >> 32);
   a.tables = nullptr; a.table_stride = 0; a.table_ls = -1;
@@ -918,12 +970,13 @@ fire_status fire_ga_run(fire_ctx *c, int32_t lid, int32_t tid, int32_t ign_x, in
   hipGraphExec_t exec = nullptr;
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) e = launch_ga_prepare(d_gen, d_sims, P, R, c->d_work, d_pop, G, hist_pop, cap);
+  if (e == hipSuccess && ign_genes)
+    e = launch_sims_from_pop(d_pop, P, G, R, lid, tid, L.W, L.H, 0u, d_gen, d_sims, d_beta, cap);
   if (e == hipSuccess) e = launch_sim(a, plan.s.threads, false, plan.grid, plan.lds, cap);
   if (e == hipSuccess) e = launch_ga_gather(d_gen, d_res, P, R, d_fit, hist_fit, cap);
   if (e == hipSuccess)
-    e = launch_ga_step(d_pop, d_fit, nullptr, P, G, R, cfg->elite, cfg->pm0, cfg->mut_h, cfg->lo,
-                       cfg->hi, 0u, d_gen, cfg->generations, (uint32_t)ga_seed,
-                       (uint32_t)(ga_seed >> 32), cap);
+    e = launch_ga_step(d_pop, d_fit, nullptr, P, G, R, elite, pm0, box, 0u, d_gen, generations,
+                       (uint32_t)ga_seed, (uint32_t)(ga_seed >> 32), cap);
   hipError_t e2 = hipStreamEndCapture(cap, &graph);
   if (e == hipSuccess) e = e2;
   if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -932,7 +985,7 @@ fire_status fire_ga_run(fire_ctx *c, int32_t lid, int32_t tid, int32_t ign_x, in
     (void)hipStreamDestroy(cap);
     return fail(c, FIRE_E_UNSUPPORTED, "GA graph capture failed: %s", hipGetErrorString(e));
   }
-  for (uint32_t g = 0; g < cfg->generations && e == hipSuccess; ++g)
+  for (uint32_t g = 0; g < generations && e == hipSuccess; ++g)
     e = hipGraphLaunch(exec, user);
   hipError_t e3 = hipStreamSynchronize(user);
   (void)hipGraphExecDestroy(exec);
@@ -941,6 +994,41 @@ fire_status fire_ga_run(fire_ctx *c, int32_t lid, int32_t tid, int32_t ign_x, in
   if (e == hipSuccess) e = e3;
   if (e != hipSuccess) return fail(c, FIRE_E_DEVICE, "GA graph launch: %s", hipGetErrorString(e));
   return FIRE_OK;
+}
+
+fire_status fire_ga_run(fire_ctx *c, int32_t lid, int32_t tid, int32_t ign_x, int32_t ign_y,
+                        const double *pop0, int32_t P, int32_t R, const fire_ga_cfg *cfg,
+                        uint64_t sim_seed, uint64_t ga_seed, double *hist_pop,
+                        double *hist_fit, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (!pop0 || !cfg || !hist_pop || !hist_fit) return fail(c, FIRE_E_INVALID, "null argument");
+  if (!(cfg->lo <= cfg->hi) || !std::isfinite(cfg->mut_h))
+    return fail(c, FIRE_E_INVALID, "GA sizes or configuration out of range");
+  return ga_run_graph(c, lid, tid, ign_x, ign_y, false, pop0, P, 5, R, cfg->elite, cfg->pm0,
+                      uniform_box(cfg->lo, cfg->hi, cfg->mut_h), cfg->generations, sim_seed,
+                      ga_seed, hist_pop, hist_fit, stream);
+}
+
+fire_status fire_ga_run_ignition(fire_ctx *c, int32_t lid, int32_t tid, const double *pop0,
+                                 int32_t P, int32_t R, int32_t elite, double pm0,
+                                 uint32_t generations, const double *lo, const double *hi,
+                                 const double *h, uint64_t sim_seed, uint64_t ga_seed,
+                                 double *hist_pop, double *hist_fit, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (!pop0 || !lo || !hi || !h || !hist_pop || !hist_fit)
+    return fail(c, FIRE_E_INVALID, "null argument");
+  const int G = 7;
+  GeneBox box;
+  for (int j = 0; j < kMaxGenes; ++j) {
+    const int k = j < G ? j : G - 1;
+    if (!(lo[k] <= hi[k]) || !std::isfinite(h[k]))
+      return fail(c, FIRE_E_INVALID, "gene %d: bad box or mutation width", k);
+    box.lo[j] = lo[k];
+    box.hi[j] = hi[k];
+    box.h[j] = h[k];
+  }
+  return ga_run_graph(c, lid, tid, 0, 0, true, pop0, P, G, R, elite, pm0, box, generations,
+                      sim_seed, ga_seed, hist_pop, hist_fit, stream);
 }
 
 fire_status fire_ensemble(fire_ctx *c, const double *params, const double *deltas, int32_t N,

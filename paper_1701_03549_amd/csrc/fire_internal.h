@@ -66,11 +66,26 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_sim(const SimArgs &a, int threads, bool table, int grid,
                       size_t lds_bytes, hipStream_t s);
 hipError_t set_sim_lds_limit(size_t bytes);
+constexpr int kMaxGenes = 16;
+// per-gene clamp box and mutation half-width
+struct GeneBox {
+  double lo[kMaxGenes], hi[kMaxGenes], h[kMaxGenes];
+};
+GeneBox uniform_box(double lo, double hi, double h);
+// LDS of the one-workgroup GA step: means, old and new population, ranking
+inline size_t ga_step_lds(int P, int G) {
+  return sizeof(double) * ((size_t)P + 2 * (size_t)P * G) + sizeof(int) * (size_t)P;
+}
+
 hipError_t launch_ga_step(double *pop, const double *fit, double *mean_fit,
                           int P, int G, int R, int elite, double pm0,
-                          double h, double lo, double hi, uint32_t gen,
+                          const GeneBox &box, uint32_t gen,
                           uint32_t *gen_ptr, uint32_t generations,
                           uint32_t key0, uint32_t key1, hipStream_t s);
+hipError_t launch_sims_from_pop(const double *pop, int P, int G, int R,
+                                int32_t landscape_id, int32_t target_id, int W,
+                                int H, uint32_t gen, const uint32_t *gen_ptr,
+                                fire_sim *sims, double *betas, hipStream_t s);
 hipError_t launch_ga_prepare(const uint32_t *gen_ptr, fire_sim *sims, int P,
                              int R, uint32_t *work, const double *pop, int G,
                              double *hist_pop, hipStream_t s);

@@ -494,8 +494,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
 // One workgroup, thread i owns slot i. Only exact IEEE operations.
 __global__ void ga_step_kernel(double *pop, const double *fit,
                                double *mean_fit, int P, int G, int R,
-                               int elite, double pm0, double h, double lo,
-                               double hi, uint32_t gen_arg,
+                               int elite, double pm0, GeneBox box, uint32_t gen_arg,
                                uint32_t *gen_ptr, uint32_t generations,
                                uint32_t k0, uint32_t k1) {
   extern __shared__ double sh[];
@@ -562,9 +561,9 @@ __global__ void ga_step_kernel(double *pop, const double *fit,
         const double u0 = (double)o.v[0] * (1.0 / 4294967296.0);
         if (u0 < pm) {
           const double u1 = (double)o.v[1] * (1.0 / 4294967296.0);
-          double g = newp[i * G + j] + h * (2.0 * u1 - 1.0);
-          if (g < lo) g = lo;
-          if (g > hi) g = hi;
+          double g = newp[i * G + j] + box.h[j] * (2.0 * u1 - 1.0);
+          if (g < box.lo[j]) g = box.lo[j];
+          if (g > box.hi[j]) g = box.hi[j];
           newp[i * G + j] = g;
         }
       }
@@ -604,6 +603,35 @@ __global__ void ga_gather_kernel(const uint32_t *gen_ptr,
     const double f = res[k].fitness;
     fit[k] = f;
     hist_fit[(int64_t)gen * n + k] = f;
+  }
+}
+
+// Descriptors of a generation whose individuals carry their ignition cell as
+// genes 5 and 6: the cell is the nearest one (round half up), clamped to the
+// lattice; genes 0..4 are copied to a [P][5] parameter array.
+__global__ void sims_from_pop_kernel(const double *pop, int P, int G, int R,
+                                     int32_t landscape_id, int32_t target_id, int W,
+                                     int H, uint32_t gen_arg, const uint32_t *gen_ptr,
+                                     fire_sim *sims, double *betas) {
+  const uint32_t gen = gen_ptr ? *gen_ptr : gen_arg;
+  const int n = P * R;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int i = k / R;
+    const double *ind = pop + (int64_t)i * G;
+    double fx = floor(ind[5] + 0.5), fy = floor(ind[6] + 0.5);
+    fx = fx < 0.0 ? 0.0 : (fx > (double)(W - 1) ? (double)(W - 1) : fx);
+    fy = fy < 0.0 ? 0.0 : (fy > (double)(H - 1) ? (double)(H - 1) : fy);
+    fire_sim sd;
+    sd.landscape_id = landscape_id;
+    sd.target_id = target_id;
+    sd.ign_x = (int32_t)fx;
+    sd.ign_y = (int32_t)fy;
+    sd.param_index = (uint32_t)i;
+    sd.sim_index = (gen * (uint32_t)P + (uint32_t)i) * (uint32_t)R + (uint32_t)(k % R);
+    sd.max_steps = 0xFFFFFFFFu;
+    sims[k] = sd;
+    if (k % R == 0)
+      for (int j = 0; j < 5; ++j) betas[(int64_t)i * 5 + j] = ind[j];
   }
 }
 
@@ -817,16 +845,34 @@ hipError_t set_sim_lds_limit(size_t bytes) {
   return set_limit_block<1024>(bytes);
 }
 
+GeneBox uniform_box(double lo, double hi, double h) {
+  GeneBox b;
+  for (int j = 0; j < kMaxGenes; ++j) {
+    b.lo[j] = lo;
+    b.hi[j] = hi;
+    b.h[j] = h;
+  }
+  return b;
+}
+
+hipError_t launch_sims_from_pop(const double *pop, int P, int G, int R,
+                                int32_t landscape_id, int32_t target_id, int W,
+                                int H, uint32_t gen, const uint32_t *gen_ptr, fire_sim *sims,
+                                double *betas, hipStream_t s) {
+  hipLaunchKernelGGL(sims_from_pop_kernel, dim3(grid_for((int64_t)P * R, 256)), dim3(256), 0, s,
+                     pop, P, G, R, landscape_id, target_id, W, H, gen, gen_ptr, sims, betas);
+  return hipGetLastError();
+}
+
 hipError_t launch_ga_step(double *pop, const double *fit, double *mean_fit,
                           int P, int G, int R, int elite, double pm0,
-                          double h, double lo, double hi, uint32_t gen,
+                          const GeneBox &box, uint32_t gen,
                           uint32_t *gen_ptr, uint32_t generations,
                           uint32_t key0, uint32_t key1, hipStream_t s) {
   const int threads = ((P + 63) / 64) * 64;
-  const size_t lds = sizeof(double) * ((size_t)P + 2 * (size_t)P * G) +
-                     sizeof(int) * (size_t)P;
+  const size_t lds = ga_step_lds(P, G);
   hipLaunchKernelGGL(ga_step_kernel, dim3(1), dim3(threads), lds, s, pop, fit,
-                     mean_fit, P, G, R, elite, pm0, h, lo, hi, gen, gen_ptr,
+                     mean_fit, P, G, R, elite, pm0, box, gen, gen_ptr,
                      generations, key0, key1);
   return hipGetLastError();
 }

@@ -29,8 +29,8 @@ STATUS = {0: "FIRE_OK", -1: "FIRE_E_INVALID", -2: "FIRE_E_OOM", -3: "FIRE_E_DEVI
 EXPORTS = ["fire_ctx_create", "fire_ctx_destroy", "fire_last_error", "fire_sync", "fire_version",
            "fire_landscape_load", "fire_landscape_free", "fire_target_load", "fire_target_free",
            "fire_thresholds", "fire_run", "fire_run_dev", "fire_set_schedule",
-           "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_run", "fire_ensemble",
-           "fire_scan_reduce"]
+           "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_step_genes",
+           "fire_ga_sims_from_pop", "fire_ga_run", "fire_ga_run_ignition", "fire_ensemble", "fire_scan_reduce"]
 
 
 class FireError(RuntimeError):
@@ -91,8 +91,13 @@ def load_library(path: str = LIB_PATH):
         "fire_get_schedule": (i32, [vp, i64, i32, ctypes.POINTER(Schedule)]),
         "fire_set_class_schedule": (i32, [vp, i64, ctypes.POINTER(Schedule)]),
         "fire_ga_step": (i32, [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(GACfg), u32, u64, vp]),
+        "fire_ga_step_genes": (i32, [vp, vp, vp, vp, i32, i32, i32, i32, dbl, vp, vp, vp, u32, u32,
+                                     u64, vp]),
+        "fire_ga_sims_from_pop": (i32, [vp, vp, i32, i32, i32, i32, i32, u32, vp, vp, vp]),
         "fire_ga_run": (i32, [vp, i32, i32, i32, i32, vp, i32, i32, ctypes.POINTER(GACfg), u64,
                               u64, vp, vp, vp]),
+        "fire_ga_run_ignition": (i32, [vp, i32, i32, vp, i32, i32, i32, dbl, u32, vp, vp, vp, u64,
+                                       u64, vp, vp, vp]),
         "fire_ensemble": (i32, [vp, vp, vp, i32, i32, i32, dbl, vp, vp, vp, vp, vp]),
         "fire_scan_reduce": (i32, [vp, vp, i32, i32, dbl, dbl, vp, vp, vp, vp, vp]),
     }
@@ -273,6 +278,34 @@ class FireGPU:
                                           ctypes.byref(cfg), int(gen), int(ga_seed) & (2 ** 64 - 1),
                                           _stream(stream)))
 
+    def ga_step_genes(self, pop: torch.Tensor, fit: torch.Tensor, *, elite: int, pm0: float,
+                      lo, hi, h, generations: int, gen: int, ga_seed: int,
+                      mean_fit: torch.Tensor | None = None, stream=None):
+        """GA generation with a box and mutation width per gene."""
+        P, G = pop.shape
+        R = fit.shape[1]
+        arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (G,)))
+                for a in (lo, hi, h)]
+        self._check(self.lib.fire_ga_step_genes(
+            self.ctx, _ptr(pop), _ptr(fit), _ptr(mean_fit), P, G, R, int(elite), float(pm0),
+            arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data, int(generations),
+            int(gen), int(ga_seed) & (2 ** 64 - 1), _stream(stream)))
+
+    def ga_sims_from_pop(self, pop: torch.Tensor, R: int, lid: int, tid: int, gen: int,
+                         sims: torch.Tensor | None = None, betas: torch.Tensor | None = None,
+                         stream=None):
+        """Device descriptors (uint8 [P*R, 28]) and betas [P, 5] of a generation
+        whose genes 5 and 6 are the ignition cell."""
+        P, G = pop.shape
+        if sims is None:
+            sims = torch.empty((P * R, SIM_DTYPE.itemsize), dtype=torch.uint8, device=self.device)
+        if betas is None:
+            betas = torch.empty((P, 5), dtype=torch.float64, device=self.device)
+        self._check(self.lib.fire_ga_sims_from_pop(self.ctx, _ptr(pop), P, G, R, lid, tid,
+                                                   int(gen), _ptr(sims), _ptr(betas),
+                                                   _stream(stream)))
+        return sims, betas
+
     def ga_run(self, lid: int, tid: int, ign, pop0: np.ndarray, R: int, cfg: GACfg,
                sim_seed: int, ga_seed: int, stream=None):
         p0 = np.ascontiguousarray(pop0, dtype=np.float64)
@@ -285,6 +318,25 @@ class FireGPU:
                                          int(sim_seed) & (2 ** 64 - 1),
                                          int(ga_seed) & (2 ** 64 - 1), _ptr(hist_pop),
                                          _ptr(hist_fit), _stream(stream)))
+        return hist_pop, hist_fit
+
+    def ga_run_ignition(self, lid: int, tid: int, pop0: np.ndarray, R: int, *, elite: int,
+                        pm0: float, generations: int, lo, hi, h, sim_seed: int, ga_seed: int,
+                        stream=None):
+        """GA over (beta[5], x, y) (fire_ga_run_ignition). Returns device
+        histories (pop [gens][P][7], fitness [gens][P][R])."""
+        p0 = np.ascontiguousarray(pop0, dtype=np.float64)
+        P = p0.shape[0]
+        assert p0.shape[1] == 7
+        arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (7,)))
+                for a in (lo, hi, h)]
+        hist_pop = torch.empty((generations, P, 7), dtype=torch.float64, device=self.device)
+        hist_fit = torch.empty((generations, P, R), dtype=torch.float64, device=self.device)
+        self._check(self.lib.fire_ga_run_ignition(
+            self.ctx, lid, tid, p0.ctypes.data, P, R, int(elite), float(pm0), int(generations),
+            arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
+            int(sim_seed) & (2 ** 64 - 1), int(ga_seed) & (2 ** 64 - 1), _ptr(hist_pop),
+            _ptr(hist_fit), _stream(stream)))
         return hist_pop, hist_fit
 
     def ensemble(self, params: torch.Tensor, deltas: torch.Tensor, cutoff: float, stream=None):

@@ -3,6 +3,11 @@
 ``run_batched`` is the library's captured-graph GA (fire_ga_run): each
 generation evaluates P individuals by R replicate simulations in one
 persistent launch and applies the GA operators on the device.
+``run_ignition`` is the 7-parameter search of Appendix B
+(fire_ga_run_ignition): each individual also carries its ignition point as
+genes 5 and 6, every generation's simulations start from each individual's
+cell, and the initial points are drawn from the reference fire's burnt cells
+(Methods: simulations start at a random point of the reference burnt area).
 ``run_plain`` evaluates the same generations one simulation per launch with a
 host synchronisation after each (the paper's execution style: simulations run
 one after another) and applies the same device GA step; because every
@@ -25,6 +30,46 @@ def run_batched(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_
                 ga_seed=0, cfg=None, stream=None):
     cfg = cfg or default_cfg(generations)
     return g.ga_run(lid, tid, ign, pop0, R, cfg, sim_seed, ga_seed, stream=stream)
+
+
+def ignition_box(W, H, beta_box=(-30.0, 30.0), beta_h=1.0, xy_h=None):
+    """Per-gene (lo, hi, h) of the 7-gene search: the betas in `beta_box`
+    with width `beta_h`, the coordinates on the lattice with width `xy_h`
+    cells (default max(W, H) / 32)."""
+    xy_h = float(max(W, H)) / 32.0 if xy_h is None else float(xy_h)
+    lo = [beta_box[0]] * 5 + [0.0, 0.0]
+    hi = [beta_box[1]] * 5 + [float(W - 1), float(H - 1)]
+    h = [beta_h] * 5 + [xy_h, xy_h]
+    return lo, hi, h
+
+
+def initial_population_ignition(ref_bits, W, H, P, seed, prior_sd=5.0, beta_box=(-30.0, 30.0)):
+    """P individuals (beta[5], x, y): betas Gaussian(0, prior_sd) clamped to
+    the box (uniform over it if prior_sd is None), ignition cells uniform over
+    the burnt cells of the reference map (packed rows, as given to
+    fire_target_load)."""
+    from .synth import unpack_bits
+    rng = np.random.default_rng(seed)
+    if prior_sd is None:
+        betas = rng.uniform(beta_box[0], beta_box[1], size=(P, 5))
+    else:
+        betas = np.clip(rng.normal(0.0, prior_sd, size=(P, 5)), beta_box[0], beta_box[1])
+    ys, xs = np.nonzero(unpack_bits(np.asarray(ref_bits).reshape(H, -1), W))
+    if xs.size == 0:
+        raise ValueError("empty reference map")
+    k = rng.integers(0, xs.size, size=P)
+    return np.concatenate([betas, xs[k, None].astype(np.float64), ys[k, None].astype(np.float64)],
+                          axis=1)
+
+
+def run_ignition(g: fire.FireGPU, lid, tid, pop0, R=20, generations=50, sim_seed=0, ga_seed=0,
+                 elite=2, pm0=0.2, box=None, stream=None):
+    """Captured-graph GA over (beta[5], x, y). Returns device histories."""
+    W, H = g.dims[lid]
+    lo, hi, h = box or ignition_box(W, H)
+    return g.ga_run_ignition(lid, tid, pop0, R, elite=elite, pm0=pm0, generations=generations,
+                             lo=lo, hi=hi, h=h, sim_seed=sim_seed, ga_seed=ga_seed,
+                             stream=stream)
 
 
 def run_plain(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=0,

@@ -162,3 +162,26 @@ def test_ignition_scan_matches_oracle(g):
     centre_k = int(np.argmin(np.abs(cands - np.array(c)).sum(axis=1)))
     assert out["mean"].cpu().numpy()[centre_k] <= np.sort(red["mean"])[len(cands) // 2]
     g.free_landscape(lid)
+
+
+def test_monte_carlo_fit_matches_oracle(g):
+    """Appendix C brute-force fit: every sampled vector's Eq. 2 value
+    bit-exact against the oracle, ensemble statistics as the oracle's."""
+    from paper_1701_03549_amd import mc
+    ls, c, ref, lid, tid = _ga_fixture(g)
+    H, W = ls["veg"].shape
+    n = 300
+    say("monte carlo fit")
+    out = mc.run_mc(g, lid, tid, c, n, seed=77, sim_seed=SEED, box=(-3.0, 3.0), cutoff=1.0)
+    params = out["params"]
+    want = np.empty(n)
+    for i in range(n):
+        T = oracle.thresholds(ls, params[i])
+        o = oracle.simulate(ls["veg"], T, c, i, SEED)
+        want[i] = oracle.fitness(o["map"], ref, W, H)
+    assert np.array_equal(out["deltas"].cpu().numpy(), want)
+    e = oracle.ensemble(params, want, 1.0)
+    assert out["best_index"] == e["best_index"] and out["n_accepted"] == e["n_accepted"]
+    assert np.allclose(out["accepted_mean"], e["accepted_mean"], rtol=1e-12)
+    assert np.allclose(out["accepted_sd"], e["spread"], rtol=1e-12)
+    g.free_landscape(lid)

@@ -120,6 +120,50 @@ def test_ga_clamps(oracle_mod):
     assert np.all(new <= 30.0) and np.any(new == 30.0)
 
 
+BOX7 = dict(lo=[-30, -30, -30, -30, -30, 0, 0], hi=[30, 30, 30, 30, 30, 127, 95],
+            h=[1.0, 1.0, 0.0, 1.0, 1.0, 8.0, 4.0])
+
+
+def test_ga_per_gene_boxes(oracle_mod):
+    # 7 genes (beta[5], ignition x, y): each gene mutates by at most its own
+    # width and stays in its own box; a gene of width 0 never mutates
+    P, G, R = 256, 7, 1
+    rng = np.random.default_rng(11)
+    pop = np.concatenate([rng.uniform(-30, 30, (P, 5)), rng.uniform(0, 127, (P, 1)),
+                          rng.uniform(0, 95, (P, 1))], axis=1)
+    fit = np.zeros((P, R))
+    cfg = dict(GA, **BOX7, pm0=0.9)
+    base, _ = oracle_mod.ga_step(pop, fit, gen=0, **dict(cfg, pm0=0.0))
+    new, _ = oracle_mod.ga_step(pop, fit, gen=0, **cfg)
+    diff = np.abs(new[2:] - base[2:])
+    for j in range(G):
+        lo, hi, h = BOX7["lo"][j], BOX7["hi"][j], BOX7["h"][j]
+        assert np.all(new[:, j] >= lo) and np.all(new[:, j] <= hi), j
+        assert np.all(diff[:, j] <= h + 1e-12), j
+        if h == 0.0:
+            assert np.all(diff[:, j] == 0.0)
+        else:
+            assert np.mean(diff[:, j] > 0) > 0.7, j
+    # the wide coordinate genes really use their width
+    assert diff[:, 5].max() > 4.0 and diff[:, 6].max() > 2.0
+    # a gene pinned by its box (lo == hi) is constant
+    box = dict(BOX7, lo=[-30, -30, 1.5, -30, -30, 0, 0], hi=[30, 30, 1.5, 30, 30, 127, 95],
+               h=[1.0] * 7)
+    p2 = pop.copy()
+    p2[:, 2] = 1.5
+    new2, _ = oracle_mod.ga_step(p2, fit, gen=0, **dict(GA, **box, pm0=1.0))
+    assert np.all(new2[:, 2] == 1.5)
+
+
+def test_ignition_cell_reading(oracle_mod):
+    W, H = 128, 96
+    cases = {(2.5, 3.49): (3, 3), (2.49, 3.5): (2, 4), (-0.5, -0.49): (0, 0),
+             (-0.51, -7.0): (0, 0), (127.49, 95.49): (127, 95), (127.5, 95.5): (127, 95),
+             (400.0, 1e9): (127, 95), (0.0, 0.0): (0, 0), (63.0, 47.0): (63, 47)}
+    for (gx, gy), want in cases.items():
+        assert oracle_mod.ignition_cell(gx, gy, W, H) == want, (gx, gy)
+
+
 def test_ga_converges_on_smooth_objective(oracle_mod):
     # the operators, iterated, minimise a smooth bowl (a weak end-to-end check)
     rng = np.random.default_rng(8)
