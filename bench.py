@@ -134,6 +134,56 @@ def run_ga(g, lid, tid, centre, plain: bool):
     return out
 
 
+def run_mc(g, lid, tid, centre, ga_sims_per_s):
+    """Brute-force Monte Carlo fit (Appendix C): as many simulations as the
+    GA's (64 x 20 x 50), parameters uniform over the search box, one
+    persistent launch; throughput against the GA's and the spread of work
+    per simulation (trials) that drives it."""
+    import torch
+    from paper_1701_03549_amd import mc
+    n = 64 * 20 * 50
+    mc.run_mc(g, lid, tid, centre, 4096, seed=7, sim_seed=SIM_SEED)  # warm-up
+    torch.cuda.synchronize()
+    out = mc.run_mc(g, lid, tid, centre, n, seed=2025, sim_seed=SIM_SEED, cutoff=0.3, chunk=n)
+    tr = out["trials"].double()
+    res = {"sims": n, "wall_s": out["wall_s"], "sims_per_s": n / out["wall_s"],
+           "trials_per_s": float(tr.sum().item()) / out["wall_s"],
+           "trials_per_sim_mean": float(tr.mean().item()),
+           "trials_per_sim_cv": float((tr.std() / tr.mean()).item()),
+           "ga_over_mc_sims_per_s": (ga_sims_per_s / (n / out["wall_s"])) if ga_sims_per_s else None,
+           "best_fitness": out["best_fitness"], "n_accepted": out["n_accepted"],
+           "accepted_mean": out["accepted_mean"]}
+    log(f"MC: {n} sims in {out['wall_s']:.3f} s, best fitness {out['best_fitness']:.3f}")
+    return res
+
+
+def run_ignition_ga(g, lid, tid, centre, ref_bits):
+    """The 7-parameter GA (ignition estimated): 64 individuals x 20
+    replicates x 50 generations, betas from Table 1's Gaussian prior,
+    ignitions uniform over the reference burnt cells; accepted ensemble at
+    the variable-ignition cutoff 1.5."""
+    import torch
+    from paper_1701_03549_amd import ga
+    W, H = g.dims[lid]
+    pop0 = ga.initial_population_ignition(ref_bits, W, H, 64, seed=2024)
+    ga.run_ignition(g, lid, tid, pop0, R=20, generations=2, sim_seed=SIM_SEED, ga_seed=GA_SEED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = ga.run_ignition(g, lid, tid, pop0, R=20, generations=50, sim_seed=SIM_SEED,
+                           ga_seed=GA_SEED)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rec = ga.recovered(g, hist, cutoff=1.5)
+    m = rec["accepted_mean"]
+    err = float(np.hypot(m[5] - centre[0], m[6] - centre[1]))
+    bp = rec["best_params"]
+    log(f"7-gene GA: {dt:.2f} s, ignition error {err:.1f} cells")
+    return {"wall_s": dt, "sims_per_s": 64 * 20 * 50 / dt, "recovered": rec,
+            "true_ignition": list(map(int, centre)),
+            "accepted_ignition_error_cells": err,
+            "best_ignition_error_cells": float(np.hypot(bp[5] - centre[0], bp[6] - centre[1]))}
+
+
 def run_scan(log_fn):
     """Ignition-point scan on the 1024x1024 landscape (seed 103, smooth wind):
     256 candidate cells on a 4-cell grid around the true ignition x 32
@@ -396,6 +446,10 @@ def main():
     if not args.no_ga:
         log("GA calibration runs ...")
         result["ga"] = run_ga(g, lid, tid, centre, plain=not args.no_plain)
+        log("Monte Carlo fit ...")
+        result["mc"] = run_mc(g, lid, tid, centre, result["ga"]["batched_sims_per_s"])
+        log("7-gene GA ...")
+        result["ignition_ga"] = run_ignition_ga(g, lid, tid, centre, ref)
     g.close()
     if not args.no_extra:
         log("ignition scan ...")

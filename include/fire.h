@@ -99,6 +99,17 @@ fire_status fire_landscape_load(fire_ctx *ctx, const fire_landscape_desc *desc,
                                 int32_t *out_id);
 fire_status fire_landscape_free(fire_ctx *ctx, int32_t landscape_id);
 
+/* Turn-off times (Methods: burnt cells are active or inactive, and a
+ * burning cell turns inactive after a time set by its vegetation type; the
+ * paper's results use one step for forest and shrubland). steps: NULL, or a
+ * host array [256] where steps[v] is the number of consecutive steps a cell
+ * of vegetation value v tries to ignite its unburnt neighbours after it
+ * ignites (entry 0 is ignored; entries 1..255 must be >= 1, else
+ * FIRE_E_INVALID). NULL or all ones restores the one-step model. Applies to
+ * every later simulation on the landscape; waits for the device. */
+fire_status fire_landscape_set_burn_steps(fire_ctx *ctx, int32_t landscape_id,
+                                          const uint8_t *steps);
+
 /* Copy a packed reference burn map (host pointer, H*ceil(W/32) words) for
  * landscape `landscape_id`. Padding bits are ignored. FIRE_E_INVALID when
  * the map is empty (Eq. 2 divides by |A|). Synchronous. */

@@ -16,7 +16,9 @@ Functions and the passages of the paper they follow:
 * :func:`thresholds` -- Eq. 1 and the covariate definitions after it (Methods,
   "Forest Fire Spread Simulation"), quantised to 32-bit thresholds.
 * :func:`simulate` -- the propagation rules of the same section: synchronous
-  steps, one-step burn duration, ignition through independent per-edge coins.
+  steps, ignition through independent per-edge coins, a burn duration of one
+  step (the paper's setting) or a turn-off time per vegetation type (the
+  four-state model of the same section).
 * :func:`fitness` -- Eq. 2.
 * :func:`ga_step` -- Appendix B (elitism, tournament of two, one-point
   crossover, dynamic mutation).
@@ -76,7 +78,7 @@ def _load():
         lib.oracle_simulate.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
             ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p,
-            ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+            ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
             ctypes.POINTER(ctypes.c_uint64)]
         lib.oracle_simulate.restype = ctypes.c_int
         lib.oracle_fitness.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
@@ -146,9 +148,15 @@ def words_per_row(W: int) -> int:
 
 
 def simulate(veg: np.ndarray, T: np.ndarray, ign, sim_index: int, seed: int,
-             max_steps: int = U32_MAX, static_edges: bool = False, want_map: bool = True):
-    """One simulation. Returns dict(map, burnt, steps, trials)."""
+             max_steps: int = U32_MAX, static_edges: bool = False, want_map: bool = True,
+             burn_steps=None):
+    """One simulation. burn_steps: None (every cell active for one step) or
+    256 turn-off times indexed by vegetation value. Returns dict(map, burnt,
+    steps, trials)."""
     lib = _load()
+    if burn_steps is not None:
+        burn_steps = np.ascontiguousarray(burn_steps, dtype=np.uint8)
+        assert burn_steps.shape == (256,)
     veg = np.ascontiguousarray(veg, dtype=np.uint8)
     H, W = veg.shape
     T = np.ascontiguousarray(T, dtype=np.uint32)
@@ -160,6 +168,7 @@ def simulate(veg: np.ndarray, T: np.ndarray, ign, sim_index: int, seed: int,
     rc = lib.oracle_simulate(W, H, _ptr(veg), _ptr(T), int(ign[0]), int(ign[1]),
                              int(sim_index) & U32_MAX, int(seed) & ((1 << 64) - 1),
                              int(max_steps) & U32_MAX, 1 if static_edges else 0,
+                             _ptr(burn_steps) if burn_steps is not None else None,
                              _ptr(bits) if want_map else None,
                              ctypes.byref(burnt), ctypes.byref(steps), ctypes.byref(trials))
     if rc != 0:
@@ -176,7 +185,8 @@ def fitness(sim_bits: np.ndarray, ref_bits: np.ndarray, W: int, H: int) -> float
     return lib.oracle_fitness(W, H, _ptr(a), _ptr(b))
 
 
-def run_batch(veg, T_by_param, sims, seed, ref_bits=None, want_maps=False, threads=1):
+def run_batch(veg, T_by_param, sims, seed, ref_bits=None, want_maps=False, threads=1,
+              burn_steps=None):
     """Run many simulations (a list of dicts with param, ign, sim_index, max_steps).
 
     Returns a list of result dicts (burnt, steps, trials, fitness[, map]); each
@@ -187,7 +197,7 @@ def run_batch(veg, T_by_param, sims, seed, ref_bits=None, want_maps=False, threa
 
     def one(sd):
         r = simulate(veg, T_by_param[sd["param"]], sd["ign"], sd["sim_index"], seed,
-                     sd.get("max_steps", U32_MAX), want_map=True)
+                     sd.get("max_steps", U32_MAX), want_map=True, burn_steps=burn_steps)
         r["fitness"] = fitness(r["map"], ref_bits, W, H) if ref_bits is not None else float("nan")
         if not want_maps:
             r["map"] = None

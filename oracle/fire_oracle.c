@@ -175,6 +175,15 @@ int oracle_thresholds(int W, int H, const uint8_t *veg, const float *elev,
 /* ---------------------------------------------------------------------- */
 /* One simulation (Methods, fire ignition and propagation rules).
  *
+ * Cells are unburnable (veg == 0), burnable, burnt and active, or burnt and
+ * inactive (the four states of the Methods). A cell that ignites is active
+ * for burn_steps[veg] consecutive steps (its turn-off time, set by its
+ * vegetation; the paper's results use 1 step for every type, which is what
+ * burn_steps == NULL gives) and then inactive. At every step each active
+ * cell tries each neighbour that is burnable and unburnt at the start of the
+ * step once; the cells ignited during a step become active from the next
+ * step on (synchronous update).
+ *
  * The coin for the directed edge (source s -> direction d) tried at step k
  * of simulation sim_index is word (d mod 4) of
  *   Philox4x32-10(counter = (sim_index, k, s, d div 4),
@@ -185,16 +194,22 @@ int oracle_thresholds(int W, int H, const uint8_t *veg, const float *elev,
  *
  * Outputs: map_bits (optional, H rows of ceil(W/32) words, cell (x, y) is
  * bit x%32 of word y*ceil(W/32) + x/32), number of burnt cells, number of
- * steps executed and number of coin trials. Returns 0 on success, -1 on a
- * bad argument, -2 on allocation failure.                                 */
+ * steps executed (steps with at least one active cell, up to max_steps) and
+ * number of coin trials. Returns 0 on success, -1 on a bad argument
+ * (including a burn_steps entry of 0 for a vegetation value present in the
+ * landscape), -2 on allocation failure.                                   */
 int oracle_simulate(int W, int H, const uint8_t *veg, const uint32_t *T,
                     int ign_x, int ign_y, uint32_t sim_index, uint64_t seed,
-                    uint32_t max_steps, int static_edges, uint32_t *map_bits,
+                    uint32_t max_steps, int static_edges,
+                    const uint8_t *burn_steps, uint32_t *map_bits,
                     uint32_t *out_burnt, uint32_t *out_steps,
                     uint64_t *out_trials) {
   if (W <= 0 || H <= 0 || !in_lattice(W, H, ign_x, ign_y)) return -1;
   long n = (long)W * H;
   long stride = (W + 31) / 32;
+  if (burn_steps)
+    for (long c = 0; c < n; ++c)
+      if (veg[c] != 0 && burn_steps[veg[c]] == 0) return -1;
   if (map_bits) memset(map_bits, 0, sizeof(uint32_t) * stride * H);
   *out_burnt = 0;
   *out_steps = 0;
@@ -202,17 +217,19 @@ int oracle_simulate(int W, int H, const uint8_t *veg, const uint32_t *T,
   long ign = (long)ign_y * W + ign_x;
   if (veg[ign] == 0) return 0; /* a non-burnable ignition burns nothing */
 
-  uint8_t *burnt = calloc(n, 1);     /* burnt at the start of this step */
-  uint8_t *is_new = calloc(n, 1);    /* ignited during this step        */
+  uint8_t *burnt = calloc(n, 1);     /* burnt at the start of this step   */
+  uint8_t *is_new = calloc(n, 1);    /* ignited during this step          */
+  int *life = calloc(n, sizeof(int)); /* active steps left (0: inactive)  */
   long *active = malloc(sizeof(long) * n);
   long *next = malloc(sizeof(long) * n);
-  if (!burnt || !is_new || !active || !next) {
-    free(burnt); free(is_new); free(active); free(next);
+  if (!burnt || !is_new || !life || !active || !next) {
+    free(burnt); free(is_new); free(life); free(active); free(next);
     return -2;
   }
   const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
 
   burnt[ign] = 1;
+  life[ign] = burn_steps ? burn_steps[veg[ign]] : 1;
   active[0] = ign;
   long n_active = 1;
   uint32_t n_burnt = 1;
@@ -249,12 +266,20 @@ int oracle_simulate(int W, int H, const uint8_t *veg, const uint32_t *T,
         }
       }
     }
-    /* synchronous update: the new cells burn from the next step on */
-    for (long i = 0; i < n_next; ++i) {
-      burnt[next[i]] = 1;
-      is_new[next[i]] = 0;
-    }
     n_burnt += (uint32_t)n_next;
+    /* synchronous update: the new cells burn from the next step on, the
+     * active ones lose one step of life */
+    for (long i = 0; i < n_next; ++i) {
+      long t = next[i];
+      burnt[t] = 1;
+      is_new[t] = 0;
+      life[t] = burn_steps ? burn_steps[veg[t]] : 1;
+    }
+    for (long i = 0; i < n_active; ++i) {
+      long s = active[i];
+      life[s] -= 1;
+      if (life[s] > 0) next[n_next++] = s;
+    }
     long *tmp = active; active = next; next = tmp;
     n_active = n_next;
     step++;
@@ -271,7 +296,7 @@ int oracle_simulate(int W, int H, const uint8_t *veg, const uint32_t *T,
   *out_burnt = n_burnt;
   *out_steps = step;
   *out_trials = trials;
-  free(burnt); free(is_new); free(active); free(next);
+  free(burnt); free(is_new); free(life); free(active); free(next);
   return 0;
 }
 

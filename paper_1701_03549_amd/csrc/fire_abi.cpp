@@ -26,6 +26,7 @@ struct LandscapeHost {
   uint4 *rec = nullptr;
   double *psi = nullptr;
   uint32_t *blocked = nullptr;
+  uint8_t *burn_steps = nullptr;  // device [256], NULL = one step for every type
 };
 
 struct TargetHost {
@@ -126,6 +127,7 @@ fire_status sync_tables(fire_ctx *c) {
     LandscapeDev d{};
     d.W = L.W; d.H = L.H; d.stride = L.stride; d.valid = L.live ? 1 : 0;
     d.rec = L.rec; d.psi = L.psi; d.blocked = L.blocked;
+    d.burn_steps = L.burn_steps;
     d.forest_class = L.forest;
     hl[i] = d;
   }
@@ -165,15 +167,26 @@ bool valid_threads(int t) {
   return t == 64 || t == 128 || t == 256 || t == 512 || t == 1024;
 }
 
-size_t lds_bytes_for(int bitset_words, int queue_cap) {
-  return sizeof(uint32_t) * ((size_t)bitset_words + 2 * (size_t)queue_cap + 16);
+// LDS of one simulation workgroup: bitset, two frontier queues, control
+// words and, with turn-off times, a remaining-life byte per queue entry.
+size_t lds_bytes_for(int bitset_words, int queue_cap, bool dur = false) {
+  size_t b = sizeof(uint32_t) * ((size_t)bitset_words + 2 * (size_t)queue_cap + 16);
+  if (dur) b += (2 * (size_t)queue_cap + 3) / 4 * 4;
+  return b;
+}
+
+// Largest queue_cap whose LDS fits `bytes`.
+int queue_cap_for(size_t bytes, int bitset_words, bool dur) {
+  const size_t fixed = sizeof(uint32_t) * ((size_t)bitset_words + 16) + (dur ? 3 : 0);
+  if (bytes <= fixed) return 0;
+  return (int)((bytes - fixed) / (dur ? 10 : 8));
 }
 
 // Built-in schedule for landscapes of up to max_cells cells: threads grow
 // with the lattice; the LDS queues take what the bitset leaves of a budget
 // chosen so that several workgroups share a compute unit.
 fire_schedule default_schedule(const fire_ctx *c, int64_t max_cells,
-                               int bitset_words, int32_t n_params) {
+                               int bitset_words, int32_t n_params, bool dur = false) {
   fire_schedule s{};
   s.threads = max_cells <= 4096 ? 256 : 512;
   s.table_mode = n_params <= 8 ? 1 : 0;
@@ -181,14 +194,14 @@ fire_schedule default_schedule(const fire_ctx *c, int64_t max_cells,
   int per_cu = 1;
   for (int k = 8; k >= 1; --k) {
     size_t slot = budget / k;
-    if (slot >= lds_bytes_for(bitset_words, 256) && slot <= c->max_lds) {
+    if (slot >= lds_bytes_for(bitset_words, 256, dur) && slot <= c->max_lds) {
       per_cu = k;
       break;
     }
   }
   size_t slot = budget / per_cu;
   if (slot > c->max_lds) slot = c->max_lds;
-  int qcap = (int)((slot / sizeof(uint32_t) - bitset_words - 16) / 2);
+  int qcap = queue_cap_for(slot, bitset_words, dur);
   if (qcap > 16384) qcap = 16384;
   if (qcap < 64) qcap = 64;
   s.queue_cap = qcap;
@@ -198,6 +211,7 @@ fire_schedule default_schedule(const fire_ctx *c, int64_t max_cells,
 
 struct RunPlan {
   fire_schedule s;
+  bool dur;  // some landscape of the launch has turn-off times
   int bitset_words;
   int64_t max_cells;
   size_t lds;
@@ -206,8 +220,8 @@ struct RunPlan {
 
 fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells,
                      int32_t n_params, int32_t n_sims, bool table_allowed,
-                     RunPlan *out) {
-  fire_schedule s = default_schedule(c, max_cells, bitset_words, n_params);
+                     RunPlan *out, bool dur = false) {
+  fire_schedule s = default_schedule(c, max_cells, bitset_words, n_params, dur);
   if (c->sched_fixed) {
     s = c->sched;
   } else {
@@ -216,7 +230,13 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells,
       if (e.first == b) s = e.second;
   }
   if (!table_allowed) s.table_mode = 0;
-  size_t lds = lds_bytes_for(bitset_words, s.queue_cap);
+  if (dur && lds_bytes_for(bitset_words, s.queue_cap, true) > c->max_lds) {
+    // a schedule tuned without life bytes: shrink the LDS queues to fit
+    // (results do not depend on the queue capacity)
+    const int q = queue_cap_for(c->max_lds, bitset_words, true);
+    if (q >= 64) s.queue_cap = q;
+  }
+  size_t lds = lds_bytes_for(bitset_words, s.queue_cap, dur);
   if (lds > c->max_lds)
     return fail(c, FIRE_E_UNSUPPORTED,
                 "LDS needed (%zu B: %d bitset words + 2x%d queue entries) "
@@ -229,6 +249,7 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells,
   if (grid > n_sims) grid = n_sims;
   if (grid < 1) grid = 1;
   out->s = s;
+  out->dur = dur;
   out->bitset_words = bitset_words;
   out->max_cells = max_cells;
   out->lds = lds;
@@ -236,10 +257,13 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells,
   return FIRE_OK;
 }
 
+// Spill words of a launch: 2 * ovf_cap entries per workgroup, then (with
+// turn-off times) as many remaining-life bytes.
 int64_t spill_words(const RunPlan &p) {
   int64_t ovf_cap = p.max_cells - p.s.queue_cap;
   if (ovf_cap < 1) ovf_cap = 1;
-  return (int64_t)p.grid * 2 * ovf_cap;
+  const int64_t entries = (int64_t)p.grid * 2 * ovf_cap;
+  return entries + (p.dur ? (entries + 3) / 4 : 0);
 }
 
 // Make the spill area hold `words` entries (waits for the device when it grows).
@@ -273,9 +297,10 @@ fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
   a.out = out; a.maps = out_maps; a.map_words = map_words;
   a.work = c->d_work + counter; a.error_flag = c->d_work + kErrWord;
   a.ovf = spill; a.ovf_cap = ovf_cap;
+  a.ovf_life = p.dur ? reinterpret_cast<uint8_t *>(spill + (int64_t)p.grid * 2 * ovf_cap) : nullptr;
   a.queue_cap = p.s.queue_cap; a.bitset_words = p.bitset_words;
   HIP_OR_FAIL(c, launch_fill_u32(a.work, 0u, 1, st));
-  HIP_OR_FAIL(c, launch_sim(a, p.s.threads, tables != nullptr, p.grid, p.lds, st));
+  HIP_OR_FAIL(c, launch_sim(a, p.s.threads, tables != nullptr, p.dur, p.grid, p.lds, st));
   return FIRE_OK;
 }
 
@@ -338,6 +363,7 @@ void fire_ctx_destroy(fire_ctx *c) {
     if (L.rec) (void)hipFree(L.rec);
     if (L.psi) (void)hipFree(L.psi);
     if (L.blocked) (void)hipFree(L.blocked);
+    if (L.burn_steps) (void)hipFree(L.burn_steps);
   }
   for (auto &T : c->tg)
     if (T.bits) (void)hipFree(T.bits);
@@ -425,6 +451,7 @@ fire_status fire_landscape_load(fire_ctx *c, const fire_landscape_desc *d,
     if (L.rec) (void)hipFree(L.rec);
     if (L.psi) (void)hipFree(L.psi);
     if (L.blocked) (void)hipFree(L.blocked);
+    if (L.burn_steps) (void)hipFree(L.burn_steps);
     return fail(c, e == hipErrorOutOfMemory ? FIRE_E_OOM : FIRE_E_DEVICE,
                 "landscape upload: %s", hipGetErrorString(e));
   }
@@ -448,12 +475,39 @@ fire_status fire_landscape_free(fire_ctx *c, int32_t id) {
   HIP_OR_FAIL(c, hipDeviceSynchronize());
   LandscapeHost &L = c->ls[id];
   (void)hipFree(L.rec); (void)hipFree(L.psi); (void)hipFree(L.blocked);
+  if (L.burn_steps) (void)hipFree(L.burn_steps);
   L = LandscapeHost();
   for (auto &T : c->tg)
     if (T.live && T.landscape_id == id) {
       (void)hipFree(T.bits);
       T = TargetHost();
     }
+  return sync_tables(c);
+}
+
+fire_status fire_landscape_set_burn_steps(fire_ctx *c, int32_t id, const uint8_t *steps) {
+  if (!c) return FIRE_E_INVALID;
+  if (id < 0 || id >= (int)c->ls.size() || !c->ls[id].live)
+    return fail(c, FIRE_E_INVALID, "unknown landscape id %d", id);
+  bool all_one = true;
+  if (steps)
+    for (int v = 1; v < 256; ++v) {
+      if (steps[v] == 0) return fail(c, FIRE_E_INVALID, "turn-off time 0 for vegetation %d", v);
+      all_one = all_one && steps[v] == 1;
+    }
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, hipDeviceSynchronize());
+  LandscapeHost &L = c->ls[id];
+  if (!steps || all_one) {
+    if (L.burn_steps) HIP_OR_FAIL(c, hipFree(L.burn_steps));
+    L.burn_steps = nullptr;
+    return sync_tables(c);
+  }
+  if (!L.burn_steps) HIP_OR_FAIL(c, hipMalloc(&L.burn_steps, 256));
+  uint8_t h[256];
+  std::memcpy(h, steps, 256);
+  h[0] = 1;
+  HIP_OR_FAIL(c, hipMemcpy(L.burn_steps, h, 256, hipMemcpyHostToDevice));
   return sync_tables(c);
 }
 
@@ -621,6 +675,7 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
   std::vector<int> cls_of_ls(c->ls.size(), -1);
   std::vector<int64_t> cls_cells;
   std::vector<int> cls_words;
+  std::vector<char> cls_dur;
   std::vector<int> ls_ids;
   for (int32_t i = 0; i < n_sims; ++i) {
     const int l = sims[i].landscape_id;
@@ -631,11 +686,17 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
       cls_of_ls[l] = (int)cls_cells.size();
       cls_cells.push_back((int64_t)c->ls[l].W * c->ls[l].H);
       cls_words.push_back(c->ls[l].H * c->ls[l].stride);
+      cls_dur.push_back(c->ls[l].burn_steps != nullptr);
     }
   } else {
-    for (int l : ls_ids) cls_of_ls[l] = 0;
+    bool any = false;
+    for (int l : ls_ids) {
+      cls_of_ls[l] = 0;
+      any = any || c->ls[l].burn_steps != nullptr;
+    }
     cls_cells.push_back(mc);
     cls_words.push_back(bw);
+    cls_dur.push_back(any);
   }
   const int n_cls = (int)cls_cells.size();
   std::vector<std::vector<uint32_t>> members(n_cls);
@@ -645,7 +706,8 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
   int64_t spill_total = 0;
   for (int k = 0; k < n_cls; ++k) {
     fire_status ps = plan_run(c, cls_words[k], cls_cells[k], n_params,
-                              (int32_t)members[k].size(), one_ls >= 0, &plans[k]);
+                              (int32_t)members[k].size(), one_ls >= 0, &plans[k],
+                              cls_dur[k] != 0);
     if (ps != FIRE_OK) return ps;
     spill_total += spill_words(plans[k]);
   }
@@ -740,11 +802,13 @@ fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
   // sized for every loaded landscape (the descriptors stay on the device)
   int bw = 0, nlive = 0, lid = -1;
   int64_t mc = 1;
+  bool any_dur = false;
   for (size_t i = 0; i < c->ls.size(); ++i) {
     const LandscapeHost &L = c->ls[i];
     if (!L.live) continue;
     ++nlive;
     lid = (int)i;
+    any_dur = any_dur || L.burn_steps != nullptr;
     if (L.H * L.stride > bw) bw = L.H * L.stride;
     if ((int64_t)L.W * L.H > mc) mc = (int64_t)L.W * L.H;
   }
@@ -756,7 +820,7 @@ fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   RunPlan plan;
-  fire_status ps = plan_run(c, bw, mc, n_params, n_sims, nlive == 1, &plan);
+  fire_status ps = plan_run(c, bw, mc, n_params, n_sims, nlive == 1, &plan, any_dur);
   if (ps != FIRE_OK) return ps;
   fire_status ss = ensure_spill(c, spill_words(plan));
   if (ss != FIRE_OK) return ss;
@@ -945,7 +1009,8 @@ static fire_status ga_run_graph(fire_ctx *c, int32_t lid, int32_t tid, int32_t i
   // plan the simulation launch for this landscape only (on-the-fly thresholds,
   // since the parameters change every generation)
   RunPlan plan;
-  fire_status ps = plan_run(c, L.H * L.stride, (int64_t)L.W * L.H, P, n, false, &plan);
+  fire_status ps = plan_run(c, L.H * L.stride, (int64_t)L.W * L.H, P, n, false, &plan,
+                            L.burn_steps != nullptr);
   if (ps != FIRE_OK) return ps;
   int64_t ovf_cap = plan.max_cells - plan.s.queue_cap;
   if (ovf_cap < 1) ovf_cap = 1;
@@ -961,6 +1026,8 @@ static fire_status ga_run_graph(fire_ctx *c, int32_t lid, int32_t tid, int32_t i
   a.out = d_res; a.maps = nullptr; a.map_words = 0;
   a.work = c->d_work; a.error_flag = c->d_work + kErrWord;
   a.ovf = c->d_ovf; a.ovf_cap = ovf_cap;
+  a.ovf_life = plan.dur ? reinterpret_cast<uint8_t *>(c->d_ovf + (int64_t)plan.grid * 2 * ovf_cap)
+                        : nullptr;
   a.queue_cap = plan.s.queue_cap; a.bitset_words = plan.bitset_words;
 
   // capture one generation
@@ -972,7 +1039,7 @@ static fire_status ga_run_graph(fire_ctx *c, int32_t lid, int32_t tid, int32_t i
   if (e == hipSuccess) e = launch_ga_prepare(d_gen, d_sims, P, R, c->d_work, d_pop, G, hist_pop, cap);
   if (e == hipSuccess && ign_genes)
     e = launch_sims_from_pop(d_pop, P, G, R, lid, tid, L.W, L.H, 0u, d_gen, d_sims, d_beta, cap);
-  if (e == hipSuccess) e = launch_sim(a, plan.s.threads, false, plan.grid, plan.lds, cap);
+  if (e == hipSuccess) e = launch_sim(a, plan.s.threads, false, plan.dur, plan.grid, plan.lds, cap);
   if (e == hipSuccess) e = launch_ga_gather(d_gen, d_res, P, R, d_fit, hist_fit, cap);
   if (e == hipSuccess)
     e = launch_ga_step(d_pop, d_fit, nullptr, P, G, R, elite, pm0, box, 0u, d_gen, generations,

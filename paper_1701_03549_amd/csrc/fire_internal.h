@@ -18,6 +18,8 @@ struct LandscapeDev {
                                 //        veg | up_mask << 8}
   const double *psi;            // [H*W] aspect covariate (binary64)
   const uint32_t *blocked;      // [H*stride] 1 = non-burnable or padding
+  const uint8_t *burn_steps;    // NULL (one step for every type) or [256]
+                                // active steps of a burning cell by veg value
   uint32_t forest_class;
   uint32_t pad0;
 };
@@ -48,6 +50,8 @@ struct SimArgs {
   uint32_t *work;          // work-stealing counter (zeroed before launch)
   uint32_t *error_flag;    // set to 1 on an invalid descriptor
   uint32_t *ovf;           // per workgroup: 2 * ovf_cap frontier entries
+  uint8_t *ovf_life;       // turn-off-time kernels: per workgroup 2 * ovf_cap
+                           // remaining-life bytes of the spilled entries
   int64_t ovf_cap;
   int32_t queue_cap;       // frontier entries per queue held in LDS
   int32_t bitset_words;    // LDS words reserved for the burn bitset
@@ -63,7 +67,7 @@ hipError_t launch_thresholds(const LandscapeDev *ls_dev_entry, int W, int H,
                              const double *beta_dev, uint32_t forest,
                              uint32_t *out, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
-hipError_t launch_sim(const SimArgs &a, int threads, bool table, int grid,
+hipError_t launch_sim(const SimArgs &a, int threads, bool table, bool dur, int grid,
                       size_t lds_bytes, hipStream_t s);
 hipError_t set_sim_lds_limit(size_t bytes);
 constexpr int kMaxGenes = 16;

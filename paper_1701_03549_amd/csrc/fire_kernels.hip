@@ -184,11 +184,21 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
 // Every coin is a pure function of (sim_index, step, source cell, direction)
 // and ignition is an OR, so the burnt set, step count, trial count and
 // fitness do not depend on thread order or on the schedule.
+//
+// With DUR (landscapes with a turn-off time per vegetation type) every
+// frontier entry also carries the number of steps its cell stays active, in
+// a byte array beside the queue (LDS up to queue_cap, then the spill area):
+// a new cell starts with its vegetation's turn-off time, and after the
+// step's new cells are appended each entry with more than one step left is
+// appended again with one step less. The next frontier is thus every cell
+// that is still burning.
 // ---------------------------------------------------------------------------
 
 typedef const __attribute__((address_space(1))) uint32_t gmem_cu32;
 typedef __attribute__((address_space(1))) uint32_t gmem_u32;
 typedef const __attribute__((address_space(1))) double gmem_cf64;
+typedef __attribute__((address_space(1))) uint8_t gmem_u8;
+typedef const __attribute__((address_space(1))) uint8_t gmem_cu8;
 
 __device__ __forceinline__ uint4 load_rec(const uint4 *base, int64_t t) {
   gmem_cu32 *q = (gmem_cu32 *)(base + t);
@@ -211,7 +221,7 @@ enum CtlSlot { kSim = 0, kLen0 = 1, kTrials = 4, kNew = 5, kInter = 6, kRowLo = 
 // kRegRounds * BLOCK / 8 cells)
 constexpr int kRegRounds = 4;
 
-template <int BLOCK, bool TABLE>
+template <int BLOCK, bool TABLE, bool DUR>
 __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
   extern __shared__ uint32_t lds[];
   const int bw = a.bitset_words;
@@ -221,6 +231,18 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
   gmem_u32 *const spill_base = (gmem_u32 *)(a.ovf + (int64_t)blockIdx.x * 2 * a.ovf_cap);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+  // remaining active steps of the queue entries (DUR only)
+  uint8_t *const life_lds = reinterpret_cast<uint8_t *>(ctl + kCtlWords);
+  gmem_u8 *const life_spill =
+      DUR ? (gmem_u8 *)(a.ovf_life + (int64_t)blockIdx.x * 2 * a.ovf_cap) : nullptr;
+  auto l_load = [&](uint32_t q, uint32_t i) -> uint32_t {
+    if (i < cap) return life_lds[q * cap + i];
+    return life_spill[(int64_t)q * a.ovf_cap + (i - cap)];
+  };
+  auto l_store = [&](uint32_t q, uint32_t i, uint32_t v) {
+    if (i < cap) life_lds[q * cap + i] = (uint8_t)v;
+    else life_spill[(int64_t)q * a.ovf_cap + (i - cap)] = (uint8_t)v;
+  };
 
   // frontier queue q (0 or 1), entry i
   auto q_load = [&](uint32_t q, uint32_t i) -> uint32_t {
@@ -305,9 +327,16 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       ctl[kRowLo] = (uint32_t)iy; ctl[kRowHi] = (uint32_t)iy;
     }
     __syncthreads();
+    gmem_cu8 *const bsteps = DUR ? (gmem_cu8 *)L.burn_steps : nullptr;
+    // active steps of a cell that ignites
+    auto life_of = [&](int x, int y) -> uint32_t {
+      if (!DUR || bsteps == nullptr) return 1u;
+      return bsteps[load_rec(L.rec, (int64_t)y * W + x).w & 0xFFu];
+    };
     if (tid == 0) {
       bits[iy * stride + (ix >> 5)] |= 1u << (ix & 31);
       q_store(0, 0, (uint32_t)ix | ((uint32_t)iy << 12));
+      if (DUR) l_store(0, 0, life_of(ix, iy));
     }
     double beta[5];
     if (!TABLE) {
@@ -395,8 +424,9 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
             if (lane == 0) wbase = atomicAdd(&ctl[kLen0 + nslot], (uint32_t)__popcll(bal));
             wbase = __builtin_amdgcn_readfirstlane(wbase);
             if (fresh) {
-              lds[bw + (cq ^ 1u) * cap + wbase + lane_prefix(bal)] =
-                  (uint32_t)htx[rr] | ((uint32_t)hty[rr] << 12);
+              const uint32_t idx = wbase + lane_prefix(bal);
+              lds[bw + (cq ^ 1u) * cap + idx] = (uint32_t)htx[rr] | ((uint32_t)hty[rr] << 12);
+              if (DUR) life_lds[(cq ^ 1u) * cap + idx] = (uint8_t)life_of(htx[rr], hty[rr]);
               ++my_new;
               row_lo = min(row_lo, (uint32_t)hty[rr]);
               row_hi = max(row_hi, (uint32_t)hty[rr]);
@@ -437,10 +467,36 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
             if (lane == 0) wbase = atomicAdd(&ctl[kLen0 + nslot], (uint32_t)__popcll(bal));
             wbase = __builtin_amdgcn_readfirstlane(wbase);
             if (fresh) {
-              q_store(cq ^ 1u, wbase + lane_prefix(bal), (uint32_t)tx | ((uint32_t)ty << 12));
+              const uint32_t idx = wbase + lane_prefix(bal);
+              q_store(cq ^ 1u, idx, (uint32_t)tx | ((uint32_t)ty << 12));
+              if (DUR) l_store(cq ^ 1u, idx, life_of(tx, ty));
               ++my_new;
               row_lo = min(row_lo, (uint32_t)ty);
               row_hi = max(row_hi, (uint32_t)ty);
+            }
+          }
+        }
+      }
+      if (DUR) {
+        // cells still burning after this step follow the new ones
+        __syncthreads();
+        for (uint32_t base = 0; base < n_cur; base += BLOCK) {
+          const uint32_t i = base + (uint32_t)tid;
+          uint32_t lf = 0, e = 0;
+          if (i < n_cur) {
+            lf = l_load(cq, i);
+            if (lf > 1u) e = q_load(cq, i) & 0xFFFFFFu;
+          }
+          const bool keep = lf > 1u;
+          const uint64_t bal = __ballot(keep);
+          if (bal != 0) {
+            uint32_t wbase = 0;
+            if (lane == 0) wbase = atomicAdd(&ctl[kLen0 + nslot], (uint32_t)__popcll(bal));
+            wbase = __builtin_amdgcn_readfirstlane(wbase);
+            if (keep) {
+              const uint32_t idx = wbase + lane_prefix(bal);
+              q_store(cq ^ 1u, idx, e);
+              l_store(cq ^ 1u, idx, lf - 1u);
             }
           }
         }
@@ -802,38 +858,48 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
 }
 
 template <int BLOCK>
-static hipError_t launch_sim_block(const SimArgs &a, bool table, int grid,
+static hipError_t launch_sim_block(const SimArgs &a, bool table, bool dur, int grid,
                                    size_t lds, hipStream_t s) {
-  if (table)
-    hipLaunchKernelGGL((sim_kernel<BLOCK, true>), dim3(grid), dim3(BLOCK), lds,
-                       s, a);
-  else
-    hipLaunchKernelGGL((sim_kernel<BLOCK, false>), dim3(grid), dim3(BLOCK),
-                       lds, s, a);
+  if (dur) {
+    if (table)
+      hipLaunchKernelGGL((sim_kernel<BLOCK, true, true>), dim3(grid), dim3(BLOCK), lds, s, a);
+    else
+      hipLaunchKernelGGL((sim_kernel<BLOCK, false, true>), dim3(grid), dim3(BLOCK), lds, s, a);
+  } else {
+    if (table)
+      hipLaunchKernelGGL((sim_kernel<BLOCK, true, false>), dim3(grid), dim3(BLOCK), lds, s, a);
+    else
+      hipLaunchKernelGGL((sim_kernel<BLOCK, false, false>), dim3(grid), dim3(BLOCK), lds, s, a);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_sim(const SimArgs &a, int threads, bool table, int grid,
+hipError_t launch_sim(const SimArgs &a, int threads, bool table, bool dur, int grid,
                       size_t lds_bytes, hipStream_t s) {
+  if (dur && a.ovf_life == nullptr) return hipErrorInvalidValue;
   switch (threads) {
-    case 64: return launch_sim_block<64>(a, table, grid, lds_bytes, s);
-    case 128: return launch_sim_block<128>(a, table, grid, lds_bytes, s);
-    case 256: return launch_sim_block<256>(a, table, grid, lds_bytes, s);
-    case 512: return launch_sim_block<512>(a, table, grid, lds_bytes, s);
-    case 1024: return launch_sim_block<1024>(a, table, grid, lds_bytes, s);
+    case 64: return launch_sim_block<64>(a, table, dur, grid, lds_bytes, s);
+    case 128: return launch_sim_block<128>(a, table, dur, grid, lds_bytes, s);
+    case 256: return launch_sim_block<256>(a, table, dur, grid, lds_bytes, s);
+    case 512: return launch_sim_block<512>(a, table, dur, grid, lds_bytes, s);
+    case 1024: return launch_sim_block<1024>(a, table, dur, grid, lds_bytes, s);
     default: return hipErrorInvalidValue;
   }
 }
 
+template <int BLOCK, bool TABLE, bool DUR>
+static hipError_t set_limit_one(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <int BLOCK>
 static hipError_t set_limit_block(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute(
-      reinterpret_cast<const void *>(&sim_kernel<BLOCK, true>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(
-      reinterpret_cast<const void *>(&sim_kernel<BLOCK, false>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  hipError_t e;
+  if ((e = set_limit_one<BLOCK, true, false>(bytes)) != hipSuccess) return e;
+  if ((e = set_limit_one<BLOCK, false, false>(bytes)) != hipSuccess) return e;
+  if ((e = set_limit_one<BLOCK, true, true>(bytes)) != hipSuccess) return e;
+  return set_limit_one<BLOCK, false, true>(bytes);
 }
 
 hipError_t set_sim_lds_limit(size_t bytes) {

@@ -27,7 +27,8 @@ STATUS = {0: "FIRE_OK", -1: "FIRE_E_INVALID", -2: "FIRE_E_OOM", -3: "FIRE_E_DEVI
           -4: "FIRE_E_UNSUPPORTED"}
 
 EXPORTS = ["fire_ctx_create", "fire_ctx_destroy", "fire_last_error", "fire_sync", "fire_version",
-           "fire_landscape_load", "fire_landscape_free", "fire_target_load", "fire_target_free",
+           "fire_landscape_load", "fire_landscape_free", "fire_landscape_set_burn_steps",
+           "fire_target_load", "fire_target_free",
            "fire_thresholds", "fire_run", "fire_run_dev", "fire_set_schedule",
            "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_step_genes",
            "fire_ga_sims_from_pop", "fire_ga_run", "fire_ga_run_ignition", "fire_ensemble", "fire_scan_reduce"]
@@ -84,6 +85,7 @@ def load_library(path: str = LIB_PATH):
         "fire_landscape_free": (i32, [vp, i32]),
         "fire_target_load": (i32, [vp, i32, vp, ctypes.POINTER(i32)]),
         "fire_target_free": (i32, [vp, i32]),
+        "fire_landscape_set_burn_steps": (i32, [vp, i32, vp]),
         "fire_thresholds": (i32, [vp, i32, vp, vp, vp]),
         "fire_run": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_run_dev": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
@@ -183,6 +185,17 @@ class FireGPU:
         self._check(self.lib.fire_landscape_load(self.ctx, ctypes.byref(d), ctypes.byref(out)))
         self.dims[out.value] = (W, H)
         return out.value
+
+    def set_burn_steps(self, lid: int, steps=None):
+        """Turn-off time per vegetation value (uint8 [256]), or None for the
+        one-step model."""
+        if steps is None:
+            self._check(self.lib.fire_landscape_set_burn_steps(self.ctx, lid, None))
+            return
+        a = np.ascontiguousarray(steps, dtype=np.uint8)
+        if a.shape != (256,):
+            raise ValueError("steps must have 256 entries")
+        self._check(self.lib.fire_landscape_set_burn_steps(self.ctx, lid, a.ctypes.data))
 
     def free_landscape(self, lid: int):
         self._check(self.lib.fire_landscape_free(self.ctx, lid))

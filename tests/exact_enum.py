@@ -88,3 +88,54 @@ def by_count(dist):
     for k, v in dist.items():
         out[len(k)] = out.get(len(k), Fraction(0)) + v
     return dict(sorted(out.items()))
+
+
+def final_distribution_dur(W, H, burnable, probs, ign, life):
+    """As final_distribution, for cells that stay active for life[(x, y)]
+    steps after igniting (turn-off time): the state is the burnt set and the
+    remaining active steps of every active cell; at each step every active
+    cell holds one fresh coin per unburnt burnable neighbour."""
+    if not burnable[ign[1]][ign[0]]:
+        return {frozenset(): Fraction(1)}
+
+    def neighbours(c):
+        x, y = c
+        for dx, dy in OFFSETS:
+            tx, ty = x + dx, y + dy
+            if 0 <= tx < W and 0 <= ty < H and burnable[ty][tx]:
+                yield (tx, ty)
+
+    @lru_cache(maxsize=None)
+    def go(burnt: frozenset, active: frozenset):
+        if not active:
+            return {burnt: Fraction(1)}
+        q = {}
+        for s, _ in active:
+            for t in neighbours(s):
+                if t in burnt:
+                    continue
+                q[t] = q.get(t, Fraction(1)) * (1 - probs[(s, t)])
+        cands = sorted(q)
+        older = frozenset((s, k - 1) for s, k in active if k > 1)
+        out = {}
+        for m in range(1 << len(cands)):
+            pr = Fraction(1)
+            new = []
+            for i, t in enumerate(cands):
+                if m >> i & 1:
+                    pr *= 1 - q[t]
+                    new.append(t)
+                else:
+                    pr *= q[t]
+                if pr == 0:
+                    break
+            if pr == 0:
+                continue
+            nxt = older | frozenset((t, life[t]) for t in new)
+            sub = go(burnt | frozenset(new), nxt)
+            for k, v in sub.items():
+                out[k] = out.get(k, Fraction(0)) + pr * v
+        return out
+
+    start = tuple(ign)
+    return go(frozenset([start]), frozenset([(start, life[start])]))

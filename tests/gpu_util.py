@@ -28,7 +28,8 @@ def oracle_target(ls, beta, ign, seed=TARGET_SEED, lo=0.0, hi=1.0, tries=200):
     raise RuntimeError("no reference fire in range")
 
 
-def compare_with_oracle(ls, T_oracle, res, maps, sims, seed, ref_bits=None, idx=None):
+def compare_with_oracle(ls, T_oracle, res, maps, sims, seed, ref_bits=None, idx=None,
+                        burn_steps=None):
     """Bit-exact check of GPU results (and maps) against the oracle."""
     veg = ls["veg"]
     H, W = veg.shape
@@ -36,7 +37,8 @@ def compare_with_oracle(ls, T_oracle, res, maps, sims, seed, ref_bits=None, idx=
     for i in idx:
         sd = sims[i]
         o = oracle.simulate(veg, T_oracle[int(sd["param_index"])], (int(sd["ign_x"]), int(sd["ign_y"])),
-                            int(sd["sim_index"]), seed, int(sd["max_steps"]))
+                            int(sd["sim_index"]), seed, int(sd["max_steps"]),
+                            burn_steps=burn_steps)
         got = (int(res["burnt"][i]), int(res["steps"][i]), int(res["trials"][i]))
         want = (o["burnt"], o["steps"], o["trials"])
         assert got == want, (i, got, want)
