@@ -180,6 +180,26 @@ fire_status fire_run(fire_ctx *ctx, const double *betas, int32_t n_params,
                      const uint32_t *thresholds_override, fire_result *out,
                      uint32_t *out_maps, int64_t map_words, void *stream);
 
+/* Per-cell form of the simulation, after the paper's own kernel, kept as
+ * an ablation and paper-style baseline of fire_run (CUDA-implementation
+ * section; Methods, propagation rules): one thread per cell sweeps the
+ * whole lattice every step, a burnable cell unburnt at the start of the
+ * step with burning neighbours evaluates Eq. 1 for each of them (quantised
+ * like an edge threshold), accumulates prod(1 - p_i) in binary64 in
+ * direction order and draws one uniform (word 0 of Philox(sim_index, step,
+ * y*W + x, 2) under `seed`) against 1 - prod; a saturated edge ignites
+ * surely. The law of the burn equals fire_run's; the realisations differ.
+ * Simulations run one after another, one launch per step, the host reading
+ * the count of new cells after each step. trials = per-cell draws.
+ * Arguments as fire_run (betas and sims on the host, out and out_maps on
+ * the device); landscapes with turn-off times are FIRE_E_UNSUPPORTED.
+ * Returns after every simulation's last step has been read back; the
+ * results are written stream-ordered. */
+fire_status fire_run_dense(fire_ctx *ctx, const double *betas, int32_t n_params,
+                           const fire_sim *sims, int32_t n_sims, uint64_t seed,
+                           fire_result *out, uint32_t *out_maps,
+                           int64_t map_words, void *stream);
+
 /* As fire_run, with betas and sims already in device memory (no host
  * staging; usable under stream capture). Descriptors are checked on the
  * device: an invalid one yields {0, 0xFFFFFFFF, 0, NaN} and makes the next

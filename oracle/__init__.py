@@ -19,6 +19,8 @@ Functions and the passages of the paper they follow:
   steps, ignition through independent per-edge coins, a burn duration of one
   step (the paper's setting) or a turn-off time per vegetation type (the
   four-state model of the same section).
+* :func:`simulate_dense` -- the per-target form of the same rule (one uniform per
+  candidate target per step against 1 - prod(1 - p_i)), as the paper's kernel draws it.
 * :func:`fitness` -- Eq. 2.
 * :func:`ga_step` -- Appendix B (elitism, tournament of two, one-point
   crossover, dynamic mutation).
@@ -81,6 +83,12 @@ def _load():
             ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
             ctypes.POINTER(ctypes.c_uint64)]
         lib.oracle_simulate.restype = ctypes.c_int
+        lib.oracle_simulate_dense.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+            ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+            ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+            ctypes.POINTER(ctypes.c_uint64)]
+        lib.oracle_simulate_dense.restype = ctypes.c_int
         lib.oracle_fitness.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_fitness.restype = ctypes.c_double
         lib.oracle_ga_step.argtypes = [
@@ -173,6 +181,26 @@ def simulate(veg: np.ndarray, T: np.ndarray, ign, sim_index: int, seed: int,
                              ctypes.byref(burnt), ctypes.byref(steps), ctypes.byref(trials))
     if rc != 0:
         raise ValueError(f"oracle_simulate failed ({rc})")
+    return {"map": bits, "burnt": burnt.value, "steps": steps.value, "trials": trials.value}
+
+
+def simulate_dense(veg: np.ndarray, T: np.ndarray, ign, sim_index: int, seed: int,
+                   max_steps: int = U32_MAX):
+    """One simulation of the per-target form of the rule (one uniform per
+    candidate target per step). Returns dict(map, burnt, steps, trials)."""
+    lib = _load()
+    veg = np.ascontiguousarray(veg, dtype=np.uint8)
+    H, W = veg.shape
+    T = np.ascontiguousarray(T, dtype=np.uint32)
+    assert T.shape == (H, W, 8)
+    bits = np.zeros((H, words_per_row(W)), dtype=np.uint32)
+    burnt, steps, trials = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+    rc = lib.oracle_simulate_dense(W, H, _ptr(veg), _ptr(T), int(ign[0]), int(ign[1]),
+                                   int(sim_index) & U32_MAX, int(seed) & ((1 << 64) - 1),
+                                   int(max_steps) & U32_MAX, _ptr(bits), ctypes.byref(burnt),
+                                   ctypes.byref(steps), ctypes.byref(trials))
+    if rc != 0:
+        raise ValueError(f"oracle_simulate_dense failed ({rc})")
     return {"map": bits, "burnt": burnt.value, "steps": steps.value, "trials": trials.value}
 
 

@@ -301,6 +301,92 @@ int oracle_simulate(int W, int H, const uint8_t *veg, const uint32_t *T,
 }
 
 /* ---------------------------------------------------------------------- */
+/* The per-target form of the propagation rule (Methods, propagation rules;
+ * CUDA-implementation section): at each step every burnable cell that is
+ * unburnt at the start of the step and has at least one burning neighbour
+ * draws one uniform and ignites with probability 1 - prod_i (1 - p_i) over
+ * its burning neighbours i. Each p_i is the quantised edge probability
+ * T(i -> target) / 2^32 of the table, so the law of the final burn equals
+ * the per-edge model's (independent coins, one per directed edge). The
+ * product runs over the target's neighbours in direction order d = 0..7 in
+ * binary64; a saturated edge (T = 0xFFFFFFFF) makes the probability 1; the
+ * probability is quantised like an edge probability and compared with word 0
+ * of Philox4x32-10(counter = (sim_index, step, target y*W + x, 2), key =
+ * seed). A "trial" here is one such per-target draw. One-step burn.
+ * Arguments and returns as oracle_simulate.                               */
+int oracle_simulate_dense(int W, int H, const uint8_t *veg, const uint32_t *T,
+                          int ign_x, int ign_y, uint32_t sim_index,
+                          uint64_t seed, uint32_t max_steps,
+                          uint32_t *map_bits, uint32_t *out_burnt,
+                          uint32_t *out_steps, uint64_t *out_trials) {
+  if (W <= 0 || H <= 0 || !in_lattice(W, H, ign_x, ign_y)) return -1;
+  long n = (long)W * H;
+  long stride = (W + 31) / 32;
+  if (map_bits) memset(map_bits, 0, sizeof(uint32_t) * stride * H);
+  *out_burnt = 0;
+  *out_steps = 0;
+  *out_trials = 0;
+  long ign = (long)ign_y * W + ign_x;
+  if (veg[ign] == 0) return 0;
+
+  /* 0 unburnt, 1 burning (ignited at the previous step), 2 burnt out */
+  uint8_t *state = calloc(n, 1);
+  uint8_t *next = calloc(n, 1);
+  if (!state || !next) { free(state); free(next); return -2; }
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  state[ign] = 1;
+  uint32_t n_burnt = 1, step = 0;
+  long n_burning = 1;
+  uint64_t trials = 0;
+  while (n_burning > 0 && step < max_steps) {
+    n_burning = 0;
+    for (int y = 0; y < H; ++y) {
+      for (int x = 0; x < W; ++x) {
+        long t = (long)y * W + x;
+        if (state[t] != 0) { next[t] = 2; continue; }
+        next[t] = 0;
+        if (veg[t] == 0) continue;
+        double q = 1.0;
+        int any = 0, sure = 0;
+        for (int d = 0; d < 8; ++d) {
+          int sx = x + DIR_DX[d], sy = y + DIR_DY[d];
+          if (!in_lattice(W, H, sx, sy)) continue;
+          long s = (long)sy * W + sx;
+          if (state[s] != 1) continue;
+          any = 1;
+          uint32_t thr = T[s * 8 + (d + 4) % 8]; /* edge s -> t */
+          if (thr == 0xFFFFFFFFu) sure = 1;
+          q = q * (1.0 - (double)thr * (1.0 / 4294967296.0));
+        }
+        if (!any) continue;
+        trials++;
+        uint32_t ctr[4] = {sim_index, step, (uint32_t)t, 2u}, out[4];
+        oracle_philox4x32_10(ctr, key, out);
+        uint32_t thr_t = sure ? 0xFFFFFFFFu : oracle_quantise_p(1.0 - q);
+        if (thr_t == 0xFFFFFFFFu || out[0] < thr_t) {
+          next[t] = 1;
+          n_burning++;
+        }
+      }
+    }
+    n_burnt += (uint32_t)n_burning;
+    uint8_t *tmp = state; state = next; next = tmp;
+    step++;
+  }
+  if (map_bits)
+    for (long c = 0; c < n; ++c)
+      if (state[c]) {
+        int x = (int)(c % W), y = (int)(c / W);
+        map_bits[(long)y * stride + x / 32] |= 1u << (x % 32);
+      }
+  *out_burnt = n_burnt;
+  *out_steps = step;
+  *out_trials = trials;
+  free(state); free(next);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Eq. 2 fitness: delta = (|A u A*| - |A n A*|) / |A|, A the reference map,
  * A* the simulated one, both packed as in oracle_simulate. Counts are taken
  * cell by cell; returns NaN when the reference is empty.                  */

@@ -72,6 +72,10 @@ struct fire_ctx {
   // GA scratch
   double *d_ga = nullptr;
   size_t ga_bytes = 0;
+  // per-cell ablation path: two state planes, betas, counters, host mirror
+  uint8_t *d_dense = nullptr;
+  size_t dense_bytes = 0;
+  unsigned long long *h_dense = nullptr;
 };
 
 namespace {
@@ -375,6 +379,8 @@ void fire_ctx_destroy(fire_ctx *c) {
   if (c->d_stage) (void)hipFree(c->d_stage);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->d_ga) (void)hipFree(c->d_ga);
+  if (c->d_dense) (void)hipFree(c->d_dense);
+  if (c->h_dense) (void)hipHostFree(c->h_dense);
   if (c->stage_done) (void)hipEventDestroy(c->stage_done);
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   for (int i = 0; i < kMaxClasses; ++i)
@@ -834,6 +840,81 @@ fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
   }
   return launch_run(c, plan, betas_dev, n_params, sims_dev, nullptr, n_sims, seed, tables,
                     tstride, tables ? lid : -1, out, out_maps, map_words, 0, c->d_ovf, st);
+}
+
+fire_status fire_run_dense(fire_ctx *c, const double *betas, int32_t n_params,
+                           const fire_sim *sims, int32_t n_sims, uint64_t seed, fire_result *out,
+                           uint32_t *out_maps, int64_t map_words, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (n_sims < 0 || n_params < 1 || !betas || (n_sims > 0 && (!sims || !out)))
+    return fail(c, FIRE_E_INVALID, "bad sizes or null pointers");
+  for (int64_t i = 0; i < (int64_t)n_params * 5; ++i)
+    if (!std::isfinite(betas[i])) return fail(c, FIRE_E_INVALID, "non-finite beta %lld", (long long)i);
+  if (n_sims == 0) return FIRE_OK;
+  int bw = 0, one_ls = -1;
+  int64_t mc = 1;
+  fire_status st0 = check_sims_host(c, sims, n_sims, n_params, &bw, &mc, &one_ls, map_words,
+                                    out_maps != nullptr);
+  if (st0 != FIRE_OK) return st0;
+  for (int32_t i = 0; i < n_sims; ++i)
+    if (c->ls[sims[i].landscape_id].burn_steps)
+      return fail(c, FIRE_E_UNSUPPORTED, "sim %d: the per-cell path has one-step burns only", i);
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  // scratch: state planes [2][mc] | betas [n_params*5] | counters [2]
+  const size_t o_beta = (2 * (size_t)mc + 255) / 256 * 256;
+  const size_t o_cnt = (o_beta + sizeof(double) * 5 * (size_t)n_params + 255) / 256 * 256;
+  const size_t need = o_cnt + 2 * sizeof(unsigned long long);
+  if (need > c->dense_bytes || !c->d_dense) {
+    HIP_OR_FAIL(c, hipDeviceSynchronize());
+    size_t have = c->dense_bytes;
+    HIP_OR_FAIL(c, ensure((void **)&c->d_dense, &have, need));
+    c->dense_bytes = have;
+  }
+  if (!c->h_dense)
+    HIP_OR_FAIL(c, hipHostMalloc((void **)&c->h_dense, sizeof(unsigned long long)));
+  uint8_t *plane[2] = {c->d_dense, c->d_dense + mc};
+  double *d_beta = (double *)(c->d_dense + o_beta);
+  unsigned long long *d_cnt = (unsigned long long *)(c->d_dense + o_cnt);
+  HIP_OR_FAIL(c, hipMemcpyAsync(d_beta, betas, sizeof(double) * 5 * n_params,
+                                hipMemcpyHostToDevice, st));
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  // one simulation after another, one launch per step, the host reading the
+  // number of cells ignited after every step (the paper's execution style)
+  for (int32_t i = 0; i < n_sims; ++i) {
+    const fire_sim &sd = sims[i];
+    const LandscapeHost &L = c->ls[sd.landscape_id];
+    LandscapeDev D{};
+    D.W = L.W; D.H = L.H; D.stride = L.stride; D.valid = 1;
+    D.rec = L.rec; D.psi = L.psi; D.blocked = L.blocked; D.burn_steps = nullptr;
+    D.forest_class = L.forest;
+    const double *beta = d_beta + 5 * (size_t)sd.param_index;
+    HIP_OR_FAIL(c, launch_dense_init(plane[0], D, sd.ign_x, sd.ign_y, d_cnt, st));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->h_dense, d_cnt, sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(c, hipStreamSynchronize(st));
+    unsigned long long burning = *c->h_dense;
+    uint32_t step = 0;
+    int cur = 0;
+    while (burning > 0 && step < sd.max_steps) {
+      HIP_OR_FAIL(c, launch_fill_u32(reinterpret_cast<uint32_t *>(d_cnt), 0u, 2, st));
+      HIP_OR_FAIL(c, launch_dense_step(plane[cur], plane[cur ^ 1], D, beta, sd.sim_index, step,
+                                       k0, k1, d_cnt, st));
+      HIP_OR_FAIL(c, hipMemcpyAsync(c->h_dense, d_cnt, sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, st));
+      HIP_OR_FAIL(c, hipStreamSynchronize(st));
+      burning = *c->h_dense;
+      cur ^= 1;
+      ++step;
+    }
+    const bool has_t = sd.target_id >= 0;
+    const TargetHost *T = has_t ? &c->tg[sd.target_id] : nullptr;
+    HIP_OR_FAIL(c, launch_dense_result(plane[cur], D, has_t ? T->bits : nullptr,
+                                       has_t ? T->n_ref : 0u, has_t, step, d_cnt, out + i,
+                                       out_maps ? out_maps + (int64_t)i * map_words : nullptr,
+                                       st));
+  }
+  return FIRE_OK;
 }
 
 fire_status fire_set_class_schedule(fire_ctx *c, int64_t max_cells, const fire_schedule *s) {

@@ -70,6 +70,16 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_sim(const SimArgs &a, int threads, bool table, bool dur, int grid,
                       size_t lds_bytes, hipStream_t s);
 hipError_t set_sim_lds_limit(size_t bytes);
+// per-cell (paper-style) ablation path
+hipError_t launch_dense_init(uint8_t *st, const LandscapeDev &L, int ix, int iy,
+                             unsigned long long *counts, hipStream_t s);
+hipError_t launch_dense_step(const uint8_t *cur, uint8_t *nxt, const LandscapeDev &L,
+                             const double *beta, uint32_t sim_index, uint32_t step, uint32_t k0,
+                             uint32_t k1, unsigned long long *counts, hipStream_t s);
+hipError_t launch_dense_result(const uint8_t *st, const LandscapeDev &L, const uint32_t *ref,
+                               uint32_t n_ref, bool has_target, uint32_t steps,
+                               const unsigned long long *counts, fire_result *out,
+                               uint32_t *map, hipStream_t s);
 constexpr int kMaxGenes = 16;
 // per-gene clamp box and mutation half-width
 struct GeneBox {

@@ -692,6 +692,129 @@ __global__ void sims_from_pop_kernel(const double *pop, int P, int G, int R,
 }
 
 // ---------------------------------------------------------------------------
+// Per-cell form of the step (an ablation of sim_kernel after the paper's own
+// kernel): one thread per cell sweeps the whole lattice every step. A cell
+// that is burnable and unburnt at the start of the step and has burning
+// neighbours evaluates Eq. 1 for each of them (quantised like an edge
+// threshold), multiplies (1 - p_i) in binary64 in direction order and draws
+// one uniform, word 0 of Philox(sim_index, step, cell, 2); a saturated edge
+// makes the ignition certain. State bytes: 0 unburnt, 1 burning (ignited at
+// the previous step), 2 burnt out. counts[0] += cells ignited, counts[1] +=
+// draws.
+__global__ void dense_step_kernel(const uint8_t *__restrict__ cur, uint8_t *__restrict__ nxt,
+                                  LandscapeDev L, const double *beta_dev, uint32_t sim_index,
+                                  uint32_t step, uint32_t k0, uint32_t k1,
+                                  unsigned long long *counts) {
+  const int W = L.W, H = L.H;
+  const int64_t n = (int64_t)W * H;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool ignited = false, drew = false;
+  if (t < n) {
+    const uint8_t st = cur[t];
+    uint8_t out = 0;
+    const int x = (int)(t % W), y = (int)(t / W);
+    if (st != 0) {
+      out = 2;
+    } else if (((L.blocked[(int64_t)y * L.stride + (x >> 5)] >> (x & 31)) & 1u) == 0) {
+      uint32_t burning = 0;
+      for (int d = 0; d < 8; ++d) {
+        const int sx = x + dir_dx(d), sy = y + dir_dy(d);
+        if ((unsigned)sx < (unsigned)W && (unsigned)sy < (unsigned)H &&
+            cur[(int64_t)sy * W + sx] == 1)
+          burning |= 1u << d;
+      }
+      if (burning) {
+        double beta[5];
+        for (int k = 0; k < 5; ++k) beta[k] = beta_dev[k];
+        const uint4 rec = load_rec(L.rec, t);
+        const double psi = L.psi[t];
+        double q = 1.0;
+        bool sure = false;
+        for (int d = 0; d < 8; ++d) {
+          if (!((burning >> d) & 1u)) continue;
+          // the edge from the neighbour in direction d points the other way
+          const uint32_t thr = edge_threshold(beta, rec, psi, (d + 4) & 7, L.forest_class);
+          sure = sure || thr == kSaturated;
+          q = q * (1.0 - (double)thr * (1.0 / 4294967296.0));
+        }
+        const Words4 r = philox10(sim_index, step, (uint32_t)t, 2u, k0, k1);
+        const uint32_t thr_t = sure ? kSaturated : quantise(1.0 - q);
+        ignited = thr_t == kSaturated || r.v[0] < thr_t;
+        drew = true;
+        out = ignited ? 1 : 0;
+      }
+    }
+    nxt[t] = out;
+  }
+  const uint64_t bi = __ballot(ignited), bd = __ballot(drew);
+  if ((threadIdx.x & 63) == 0 && (bi | bd)) {
+    if (bi) atomicAdd(&counts[0], (unsigned long long)__popcll(bi));
+    if (bd) atomicAdd(&counts[1], (unsigned long long)__popcll(bd));
+  }
+}
+
+// State of a new simulation: the ignition burning if it is burnable;
+// counts[0] = 1 (or 0 for a non-burnable ignition), counts[1] = 0.
+__global__ void dense_init_kernel(uint8_t *st, LandscapeDev L, int ix, int iy,
+                                  unsigned long long *counts) {
+  const int64_t n = (int64_t)L.W * L.H;
+  const int64_t ign = (int64_t)iy * L.W + ix;
+  const bool ok = ((L.blocked[(int64_t)iy * L.stride + (ix >> 5)] >> (ix & 31)) & 1u) == 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    st[i] = (i == ign && ok) ? 1 : 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    counts[0] = ok ? 1ull : 0ull;
+    counts[1] = 0ull;
+  }
+}
+
+// Result of a finished per-cell simulation: packed map, |A*|, |A n A*| and
+// Eq. 2 (one workgroup of kDenseResThreads threads, fixed-order sums of
+// integers).
+constexpr int kDenseResThreads = 1024;
+__global__ __launch_bounds__(kDenseResThreads) void dense_result_kernel(
+    const uint8_t *st, LandscapeDev L, const uint32_t *ref, uint32_t n_ref, int has_target,
+    uint32_t steps, const unsigned long long *counts, fire_result *out, uint32_t *map) {
+  __shared__ uint32_t sb[kDenseResThreads], si[kDenseResThreads];
+  const int W = L.W, stride = L.stride;
+  const int words = L.H * stride;
+  uint32_t burnt = 0, inter = 0;
+  for (int w = threadIdx.x; w < words; w += kDenseResThreads) {
+    const int y = w / stride, x0 = (w % stride) * 32;
+    uint32_t bits = 0;
+    for (int b = 0; b < 32 && x0 + b < W; ++b)
+      bits |= (st[(int64_t)y * W + x0 + b] != 0 ? 1u : 0u) << b;
+    burnt += __popc(bits);
+    if (has_target) inter += __popc(bits & ref[w]);
+    if (map) map[w] = bits;
+  }
+  sb[threadIdx.x] = burnt;
+  si[threadIdx.x] = inter;
+  __syncthreads();
+  for (int h = kDenseResThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sb[threadIdx.x] += sb[threadIdx.x + h];
+      si[threadIdx.x] += si[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    fire_result r;
+    r.burnt = sb[0];
+    r.steps = steps;
+    r.trials = counts[1];
+    if (has_target) {
+      const int64_t num = (int64_t)n_ref + sb[0] - 2 * (int64_t)si[0];
+      r.fitness = (double)num / (double)n_ref;
+    } else {
+      r.fitness = __builtin_nan("");
+    }
+    *out = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Accepted-ensemble statistics: one workgroup of 1024 threads; every sum is
 // reduced in a fixed tree order, so repeated runs give identical bits.
 constexpr int kRedThreads = 1024;
@@ -848,6 +971,31 @@ hipError_t launch_thresholds(const LandscapeDev *ls_dev_entry, int W, int H,
   const int64_t n = (int64_t)W * H;
   hipLaunchKernelGGL(thresholds_kernel, dim3(grid_for(n, 256)), dim3(256), 0,
                      s, ls_dev_entry, W, H, beta_dev, forest, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_init(uint8_t *st, const LandscapeDev &L, int ix, int iy,
+                             unsigned long long *counts, hipStream_t s) {
+  hipLaunchKernelGGL(dense_init_kernel, dim3(grid_for((int64_t)L.W * L.H, 256)), dim3(256), 0, s,
+                     st, L, ix, iy, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_step(const uint8_t *cur, uint8_t *nxt, const LandscapeDev &L,
+                             const double *beta, uint32_t sim_index, uint32_t step, uint32_t k0,
+                             uint32_t k1, unsigned long long *counts, hipStream_t s) {
+  const int64_t n = (int64_t)L.W * L.H;
+  hipLaunchKernelGGL(dense_step_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cur,
+                     nxt, L, beta, sim_index, step, k0, k1, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_result(const uint8_t *st, const LandscapeDev &L, const uint32_t *ref,
+                               uint32_t n_ref, bool has_target, uint32_t steps,
+                               const unsigned long long *counts, fire_result *out,
+                               uint32_t *map, hipStream_t s) {
+  hipLaunchKernelGGL(dense_result_kernel, dim3(1), dim3(kDenseResThreads), 0, s, st, L, ref, n_ref,
+                     has_target ? 1 : 0, steps, counts, out, map);
   return hipGetLastError();
 }
 

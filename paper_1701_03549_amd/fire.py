@@ -29,7 +29,7 @@ STATUS = {0: "FIRE_OK", -1: "FIRE_E_INVALID", -2: "FIRE_E_OOM", -3: "FIRE_E_DEVI
 EXPORTS = ["fire_ctx_create", "fire_ctx_destroy", "fire_last_error", "fire_sync", "fire_version",
            "fire_landscape_load", "fire_landscape_free", "fire_landscape_set_burn_steps",
            "fire_target_load", "fire_target_free",
-           "fire_thresholds", "fire_run", "fire_run_dev", "fire_set_schedule",
+           "fire_thresholds", "fire_run", "fire_run_dev", "fire_run_dense", "fire_set_schedule",
            "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_step_genes",
            "fire_ga_sims_from_pop", "fire_ga_run", "fire_ga_run_ignition", "fire_ensemble", "fire_scan_reduce"]
 
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "fire_thresholds": (i32, [vp, i32, vp, vp, vp]),
         "fire_run": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_run_dev": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
+        "fire_run_dense": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, i64, vp]),
         "fire_set_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
         "fire_get_schedule": (i32, [vp, i64, i32, ctypes.POINTER(Schedule)]),
         "fire_set_class_schedule": (i32, [vp, i64, ctypes.POINTER(Schedule)]),
@@ -243,6 +244,22 @@ class FireGPU:
         self._check(self.lib.fire_run(self.ctx, b.ctypes.data, len(b), s.ctypes.data, n,
                                       int(seed) & (2 ** 64 - 1), _ptr(override), _ptr(res),
                                       _ptr(maps), mw, _stream(stream)))
+        return res[:n], maps
+
+    def run_dense(self, betas, sims: np.ndarray, seed: int, want_maps: bool = False,
+                  stream=None):
+        """fire_run_dense (per-cell ablation path); returns (results, maps)."""
+        b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64).reshape(-1, 5))
+        s = np.ascontiguousarray(sims, dtype=SIM_DTYPE)
+        n = len(s)
+        res = torch.empty((max(n, 1), 24), dtype=torch.uint8, device=self.device)
+        maps, mw = None, 0
+        if want_maps and n:
+            mw = self.map_words(s)
+            maps = torch.empty((n, mw), dtype=torch.int32, device=self.device)
+        self._check(self.lib.fire_run_dense(self.ctx, b.ctypes.data, len(b), s.ctypes.data, n,
+                                            int(seed) & (2 ** 64 - 1), _ptr(res), _ptr(maps), mw,
+                                            _stream(stream)))
         return res[:n], maps
 
     def run_dev(self, betas_dev: torch.Tensor, sims_dev: torch.Tensor, n_sims: int, seed: int,
