@@ -184,6 +184,59 @@ def run_ignition_ga(g, lid, tid, centre, ref_bits):
             "best_ignition_error_cells": float(np.hypot(bp[5] - centre[0], bp[6] - centre[1]))}
 
 
+def run_dense(g, lid, tid, centre, frontier_sims_per_s):
+    """The per-cell ablation path (fire_run_dense: one launch per step over
+    the whole lattice, host-polled, one simulation after another, as the
+    paper runs them) on 32 replicates of the calibration batch."""
+    import torch
+    from paper_1701_03549_amd import fire
+    n = 32
+    sims = fire.make_sims(n, lid, tid, centre)
+    g.run_dense(np.array([BETA_STAR]), sims[:2], SIM_SEED)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, _ = g.run_dense(np.array([BETA_STAR]), sims, SIM_SEED)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = fire.results_to_numpy(res)
+    steps = int(r["steps"].sum())
+    log(f"per-cell path: {n} sims in {dt:.3f} s ({dt / steps * 1e6:.1f} us per step)")
+    return {"sims": n, "wall_s": dt, "sims_per_s": n / dt, "steps": steps,
+            "us_per_step": dt / steps * 1e6, "mean_burnt": float(r["burnt"].mean()),
+            "frontier_over_dense": frontier_sims_per_s / (n / dt),
+            "state_bytes_per_step": 2 * W * H}
+
+
+def run_turn_off(g, lid, tid, centre, d_sims, reps=10):
+    """The calibration batch (1280 replicates at 512x512) with turn-off times
+    of 2 steps for forest and 3 for the other vegetation (the turn-off-time
+    kernel), against the same batch with one-step burns."""
+    import torch
+    from paper_1701_03549_amd import fire
+    d_beta = torch.tensor([BETA_STAR], dtype=torch.float64, device="cuda")
+    out = torch.empty((N_SIMS, 24), dtype=torch.uint8, device="cuda")
+    bs = np.full(256, 3, dtype=np.uint8)
+    bs[1] = 2
+    g.set_burn_steps(lid, bs)
+    try:
+        g.run_dev(d_beta, d_sims, N_SIMS, SIM_SEED, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.run_dev(d_beta, d_sims, N_SIMS, SIM_SEED, out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+    finally:
+        g.set_burn_steps(lid, None)
+    r = fire.results_to_numpy(out)
+    trials = int(r["trials"].sum())
+    log(f"turn-off times: {dt * 1e3:.2f} ms per batch, mean burnt {r['burnt'].mean():.0f}")
+    return {"burn_steps": {"forest": 2, "other": 3}, "ms_per_batch": dt * 1e3,
+            "sims_per_s": N_SIMS / dt, "trials_per_s": trials / dt,
+            "mean_burnt": float(r["burnt"].mean()), "mean_steps": float(r["steps"].mean()),
+            "mean_fitness": float(np.nanmean(r["fitness"]))}
+
+
 def run_scan(log_fn):
     """Ignition-point scan on the 1024x1024 landscape (seed 103, smooth wind):
     256 candidate cells on a 4-cell grid around the true ignition x 32
@@ -450,6 +503,11 @@ def main():
         result["mc"] = run_mc(g, lid, tid, centre, result["ga"]["batched_sims_per_s"])
         log("7-gene GA ...")
         result["ignition_ga"] = run_ignition_ga(g, lid, tid, centre, ref)
+    if not args.no_extra:
+        log("per-cell path ...")
+        result["dense"] = run_dense(g, lid, tid, centre, sims_per_s)
+        log("turn-off times ...")
+        result["turn_off"] = run_turn_off(g, lid, tid, centre, d_sims)
     g.close()
     if not args.no_extra:
         log("ignition scan ...")
