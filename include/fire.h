@@ -219,6 +219,15 @@ typedef struct {
   int32_t table_mode;    /* 1: precomputed threshold table per parameter,
                             0: thresholds evaluated per trial             */
   int32_t wg_per_cu;     /* persistent workgroups per compute unit (>=1)  */
+  int32_t window;        /* -1: built-in choice; 0: every simulation keeps
+                            the whole lattice's burn bitset in LDS; a
+                            multiple of 32 in [64, 4096]: each simulation
+                            first runs in an LDS window of that many cells
+                            a side around its ignition, and one whose fire
+                            comes within a cell of a window edge inside the
+                            lattice is run again over the whole lattice
+                            (same coins, so the same result); smaller LDS
+                            footprints keep more simulations resident     */
 } fire_schedule;
 
 /* Fix the schedule used by later fire_run/fire_run_dev calls; NULL
@@ -231,10 +240,12 @@ fire_status fire_set_schedule(fire_ctx *ctx, const fire_schedule *s);
  * autotuner. */
 fire_status fire_set_class_schedule(fire_ctx *ctx, int64_t max_cells,
                                     const fire_schedule *s);
-/* The schedule the next run on landscapes of up to `max_cells` cells and
- * `n_params` parameter vectors would use. */
+/* The schedule a batch of `n_sims` simulations with `n_params` parameter
+ * vectors on a square lattice of `max_cells` cells would use (window: the
+ * LDS window side of its first launch, 0 for none). */
 fire_status fire_get_schedule(fire_ctx *ctx, int64_t max_cells,
-                              int32_t n_params, fire_schedule *out);
+                              int32_t n_params, int32_t n_sims,
+                              fire_schedule *out);
 
 /* ---- genetic algorithm (Appendix B) ----------------------------------- */
 

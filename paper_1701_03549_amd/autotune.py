@@ -38,7 +38,7 @@ def cells_bucket(cells: int) -> int:
 
 
 def candidates(table_ok: bool):
-    for threads, wg, qcap in itertools.product((256, 512, 1024), (1, 2, 4, 8), (1024, 4096)):
+    for threads, wg, qcap in itertools.product((128, 256, 512, 1024), (1, 2, 4, 8), (1024, 4096)):
         for table in ((0, 1) if table_ok else (0,)):
             yield {"threads": threads, "queue_cap": qcap, "table_mode": table, "wg_per_cu": wg}
 
@@ -106,7 +106,7 @@ def workloads():
     contained parameter vector and random parameter vectors from the
     search box, on the synthetic landscapes of the benchmark configs."""
     rng = np.random.default_rng(7)
-    beta_star = np.array([[-1.15, -0.5, 0.3, 0.8, 1.0]])
+    beta_star = np.array([[-3.0, -0.5, 6.0, 1.0, 2.0]])
     for W, H, seed in ((128, 128, 101), (256, 256, 102), (512, 512, 102), (1024, 768, 104),
                        (1024, 1024, 103)):
         yield (W, H, seed, beta_star, 1280)
@@ -127,7 +127,7 @@ def main():
     for W, H, seed, betas, n in workloads():
         ls = synth.make_landscape(W, H, seed)
         lid = g.load_landscape(ls)
-        c = synth.nearest_burnable(ls["veg"], W // 2, H // 2)
+        c = synth.ignition_site(ls)
         sims = fire.make_sims(n, lid, -1, c, param_index=np.arange(n) % len(betas))
         log(f"{W}x{H}, {len(betas)} parameter vector(s), {n} simulations")
         best, rows = tune(g, lid, sims, betas, 0x5EED0001, log=log)

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,11 @@ struct LandscapeHost {
   double *psi = nullptr;
   uint32_t *blocked = nullptr;
   uint8_t *burn_steps = nullptr;  // device [256], NULL = one step for every type
+  // observed share of simulations that left their LDS window (moving
+  // average over window runs; windows are not used while it exceeds
+  // kWindowRetryMax)
+  float win_frac = 0.f;
+  int win_obs = 0;
 };
 
 struct TargetHost {
@@ -52,6 +58,22 @@ struct fire_ctx {
   uint32_t *d_work = nullptr;   // [0..kMaxClasses) work counters, [kErrWord] error flag
   uint32_t *d_ovf = nullptr;
   size_t ovf_words = 0;
+  uint32_t *d_retry = nullptr;  // window runs: per launch, count + simulation list
+  size_t retry_words = 0;
+  // retry counts of window runs, copied back without waiting: slot i holds
+  // the count of a launch on landscape stat_ls[i] of stat_n[i] simulations
+  static constexpr int kStatSlots = 16;
+  uint32_t *h_stat = nullptr;
+  hipEvent_t stat_ev[kStatSlots] = {};
+  int stat_ls[kStatSlots] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+  int stat_n[kStatSlots] = {};
+  // workgroups of each simulation-kernel variant resident per CU as far as
+  // registers allow ([threads 64..1024][table][turn-off times][window];
+  // 0 = unknown)
+  int reg_blocks[5][2][2][2] = {};
+  // resident workgroups per CU of (variant, dynamic LDS bytes), as the
+  // runtime computes them (allocation granularity included)
+  std::map<std::pair<int, size_t>, int> occ_cache;
   uint32_t *d_tables = nullptr;
   size_t tables_words = 0;
   // staging of host descriptors for fire_run
@@ -167,6 +189,8 @@ fire_status sync_tables(fire_ctx *c) {
   return FIRE_OK;
 }
 
+bool valid_window(int w) { return w == -1 || w == 0 || (w >= 64 && w <= 4096 && w % 32 == 0); }
+
 bool valid_threads(int t) {
   return t == 64 || t == 128 || t == 256 || t == 512 || t == 1024;
 }
@@ -186,31 +210,81 @@ int queue_cap_for(size_t bytes, int bitset_words, bool dur) {
   return (int)((bytes - fixed) / (dur ? 10 : 8));
 }
 
-// Built-in schedule for landscapes of up to max_cells cells: threads grow
-// with the lattice; the LDS queues take what the bitset leaves of a budget
-// chosen so that several workgroups share a compute unit.
-fire_schedule default_schedule(const fire_ctx *c, int64_t max_cells,
-                               int bitset_words, int32_t n_params, bool dur = false) {
-  fire_schedule s{};
-  s.threads = max_cells <= 4096 ? 256 : 512;
-  s.table_mode = n_params <= 8 ? 1 : 0;
-  size_t budget = c->max_lds;  // per CU
-  int per_cu = 1;
-  for (int k = 8; k >= 1; --k) {
-    size_t slot = budget / k;
-    if (slot >= lds_bytes_for(bitset_words, 256, dur) && slot <= c->max_lds) {
-      per_cu = k;
-      break;
+constexpr int kMaxPerCu = 16;  // built-in workgroups per compute unit, at most
+// LDS per workgroup left unused by the built-in queue sizing: with every
+// byte of an equal share taken, gfx950 kept one workgroup fewer resident
+// than the runtime's occupancy figure (measured: 5 x 32.4 KiB ran 4 per CU)
+constexpr size_t kLdsMargin = 1024;
+
+int threads_index(int t) { return t == 64 ? 0 : t == 128 ? 1 : t == 256 ? 2 : t == 512 ? 3 : 4; }
+
+// Workgroups of a simulation-kernel variant resident per CU as far as its
+// registers allow (queried once per variant; LDS is accounted separately).
+int reg_blocks(fire_ctx *c, int threads, bool table, bool dur, bool win) {
+  int &v = c->reg_blocks[threads_index(threads)][table ? 1 : 0][dur ? 1 : 0][win ? 1 : 0];
+  if (v == 0) {
+    v = sim_occupancy(threads, table, dur, win, 0);
+    if (v <= 0) v = 1;
+  }
+  return v;
+}
+
+// Workgroups of a variant resident per CU with `lds` bytes of dynamic LDS.
+int resident(fire_ctx *c, int threads, bool table, bool dur, bool win, size_t lds) {
+  const int key = threads_index(threads) * 8 + (table ? 4 : 0) + (dur ? 2 : 0) + (win ? 1 : 0);
+  auto it = c->occ_cache.find({key, lds});
+  if (it != c->occ_cache.end()) return it->second;
+  int v = sim_occupancy(threads, table, dur, win, lds);
+  if (v < 0) v = 0;
+  c->occ_cache[{key, lds}] = v;
+  return v;
+}
+
+// Built-in schedule for landscapes of up to max_cells cells. A simulation
+// runs in one workgroup, so what bounds a batch is how many simulations are
+// resident at once: for each workgroup size the LDS queues take what the
+// bitset leaves of an equal share of the compute unit's LDS, the resident
+// count is the smaller of that share count and the kernel's register
+// occupancy, and the size that keeps the most simulations of the batch
+// resident wins (ties: the larger workgroup, whose lanes cover larger
+// fronts in one pass).
+fire_schedule default_schedule(fire_ctx *c, int64_t max_cells,
+                               int bitset_words, int32_t n_params, bool dur = false,
+                               int64_t n_sims = (int64_t)1 << 30, bool win = false) {
+  fire_schedule best{};
+  int64_t best_conc = -1;
+  const bool table = n_params <= 8;
+  for (int threads : {1024, 512, 256, 128}) {
+    int per_cu = 0;
+    for (int k = kMaxPerCu; k >= 1; --k) {
+      const size_t slot = c->max_lds / k;
+      if (slot >= lds_bytes_for(bitset_words, 256, dur)) {
+        per_cu = k;
+        break;
+      }
+    }
+    if (per_cu == 0) per_cu = 1;
+    // the resident workgroups share the LDS; queues take what is left (less
+    // what allocation granularity takes, as the runtime reports it)
+    const int res = std::min(per_cu, reg_blocks(c, threads, table, dur, win));
+    int qcap = queue_cap_for(c->max_lds / res - kLdsMargin, bitset_words, dur);
+    if (qcap > 16384) qcap = 16384;
+    while (qcap > 64 &&
+           resident(c, threads, table, dur, win, lds_bytes_for(bitset_words, qcap, dur)) < res)
+      qcap -= 64;
+    if (qcap < 64) qcap = 64;
+    const int64_t conc = std::min<int64_t>((int64_t)res * c->num_cu, n_sims);
+    if (conc > best_conc) {
+      best_conc = conc;
+      best.threads = threads;
+      best.queue_cap = qcap;
+      best.table_mode = table ? 1 : 0;
+      best.wg_per_cu = res;
     }
   }
-  size_t slot = budget / per_cu;
-  if (slot > c->max_lds) slot = c->max_lds;
-  int qcap = queue_cap_for(slot, bitset_words, dur);
-  if (qcap > 16384) qcap = 16384;
-  if (qcap < 64) qcap = 64;
-  s.queue_cap = qcap;
-  s.wg_per_cu = per_cu;
-  return s;
+  best.window = 0;
+  (void)max_cells;
+  return best;
 }
 
 struct RunPlan {
@@ -220,12 +294,54 @@ struct RunPlan {
   int64_t max_cells;
   size_t lds;
   int grid;
+  // Window runs: the first launch gives each simulation an LDS window of
+  // `win` cells a side around its ignition; the simulations whose fire
+  // reaches the window edge run again in a second launch over the whole
+  // lattice, with the plan below.
+  int win;
+  fire_schedule s2;
+  int bitset_words2;
+  size_t lds2;
+  int grid2;
 };
 
-fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells,
-                     int32_t n_params, int32_t n_sims, bool table_allowed,
-                     RunPlan *out, bool dur = false) {
-  fire_schedule s = default_schedule(c, max_cells, bitset_words, n_params, dur);
+// Built-in windows only while no window run on the landscape has had to
+// repeat a simulation: the repeats run after the window launch, so even a
+// few of them cost a whole simulation's latency.
+constexpr float kWindowRetryMax = 0.0f;
+constexpr int kMinAutoQueue = 1024;      // LDS queue entries a built-in window should leave
+
+// LDS, queue and residency of one launch shape; false if it cannot fit.
+bool shape_launch(fire_ctx *c, fire_schedule &s, int bitset_words, bool dur, bool win,
+                  int32_t n_sims, size_t *lds_out, int *grid_out) {
+  if (dur && lds_bytes_for(bitset_words, s.queue_cap, true) > c->max_lds) {
+    // a schedule tuned without life bytes: shrink the LDS queues to fit
+    // (results do not depend on the queue capacity)
+    const int q = queue_cap_for(c->max_lds, bitset_words, true);
+    if (q >= 64) s.queue_cap = q;
+  }
+  const size_t lds = lds_bytes_for(bitset_words, s.queue_cap, dur);
+  if (lds > c->max_lds) return false;
+  // workgroups that fit at once (registers, LDS and its granularity)
+  const int fit = resident(c, s.threads, s.table_mode != 0, dur, win, lds);
+  int per_cu = s.wg_per_cu < fit ? s.wg_per_cu : fit;
+  if (per_cu < 1) per_cu = 1;
+  int64_t grid = (int64_t)per_cu * c->num_cu;
+  if (grid > n_sims) grid = n_sims;
+  if (grid < 1) grid = 1;
+  *lds_out = lds;
+  *grid_out = (int)grid;
+  return true;
+}
+
+// Launch plan for simulations on landscapes of at most max_h rows of
+// max_stride bitset words (bitset_words = the largest H * stride) and
+// max_cells cells.
+fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h,
+                     int max_stride, int32_t n_params, int32_t n_sims, bool table_allowed,
+                     RunPlan *out, bool dur = false, float win_frac = 0.f) {
+  fire_schedule s = default_schedule(c, max_cells, bitset_words, n_params, dur, n_sims);
+  s.window = -1;  // built-in: decide below
   if (c->sched_fixed) {
     s = c->sched;
   } else {
@@ -234,40 +350,101 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells,
       if (e.first == b) s = e.second;
   }
   if (!table_allowed) s.table_mode = 0;
-  if (dur && lds_bytes_for(bitset_words, s.queue_cap, true) > c->max_lds) {
-    // a schedule tuned without life bytes: shrink the LDS queues to fit
-    // (results do not depend on the queue capacity)
-    const int q = queue_cap_for(c->max_lds, bitset_words, true);
-    if (q >= 64) s.queue_cap = q;
-  }
-  size_t lds = lds_bytes_for(bitset_words, s.queue_cap, dur);
-  if (lds > c->max_lds)
+  fire_schedule full = s;
+  size_t lds = 0;
+  int grid = 0;
+  if (!shape_launch(c, full, bitset_words, dur, false, n_sims, &lds, &grid))
     return fail(c, FIRE_E_UNSUPPORTED,
                 "LDS needed (%zu B: %d bitset words + 2x%d queue entries) "
                 "exceeds the device limit of %zu B",
-                lds, bitset_words, s.queue_cap, c->max_lds);
-  int per_cu_lds = (int)(c->max_lds / lds);
-  int per_cu = s.wg_per_cu < per_cu_lds ? s.wg_per_cu : per_cu_lds;
-  if (per_cu < 1) per_cu = 1;
-  int64_t grid = (int64_t)per_cu * c->num_cu;
-  if (grid > n_sims) grid = n_sims;
-  if (grid < 1) grid = 1;
-  out->s = s;
+                lds_bytes_for(bitset_words, full.queue_cap, dur), bitset_words, full.queue_cap,
+                c->max_lds);
+  full.window = 0;
+  out->s = full;
   out->dur = dur;
   out->bitset_words = bitset_words;
   out->max_cells = max_cells;
   out->lds = lds;
-  out->grid = (int)grid;
+  out->grid = grid;
+  out->win = 0;
+  // window: asked for by the schedule, or (built-in) the largest one that
+  // keeps as many simulations of the batch resident as any window can, when
+  // that is more than whole-lattice bitsets allow and recent window runs on
+  // these landscapes rarely had to be repeated
+  auto window_words = [&](int side) {
+    return std::min(side, max_h) * std::min(side / 32, max_stride);
+  };
+  auto shape_for = [&](int side, fire_schedule &ws, size_t *wl, int *wg) -> bool {
+    const int wbw = window_words(side);
+    ws = s.window < 0 ? default_schedule(c, max_cells, wbw, n_params, dur, n_sims, true) : s;
+    ws.table_mode = full.table_mode;
+    return shape_launch(c, ws, wbw, dur, true, n_sims, wl, wg);
+  };
+  int win = 0;
+  if (s.window > 0) {
+    win = s.window;
+  } else if (s.window < 0 && win_frac <= kWindowRetryMax) {
+    // most resident simulations first; among those, the largest window
+    // whose LDS queues keep kMinAutoQueue entries (fronts then stay in LDS),
+    // else the one with the longest queues
+    const int top = std::max(max_h, 32 * max_stride);
+    int best_conc = grid;  // a window has to beat whole-lattice bitsets
+    int best_q = 0;
+    for (int side = 64; side < top; side += 32) {
+      fire_schedule ws;
+      size_t wl;
+      int wg;
+      if (window_words(side) >= bitset_words || !shape_for(side, ws, &wl, &wg)) continue;
+      const int q = std::min(ws.queue_cap, kMinAutoQueue);
+      if (wg > best_conc || (wg == best_conc && win > 0 && q >= best_q)) {
+        best_conc = wg;
+        best_q = q;
+        win = side;
+      }
+    }
+  }
+  if (win <= 0 || window_words(win) >= bitset_words) return FIRE_OK;
+  fire_schedule ws;
+  size_t wlds = 0;
+  int wgrid = 0;
+  if (!shape_for(win, ws, &wlds, &wgrid)) return FIRE_OK;
+  ws.window = win;
+  out->s2 = full;
+  out->bitset_words2 = bitset_words;
+  out->lds2 = lds;
+  out->grid2 = grid;
+  out->s = ws;
+  out->bitset_words = window_words(win);
+  out->lds = wlds;
+  out->grid = wgrid;
+  out->win = win;
   return FIRE_OK;
 }
 
 // Spill words of a launch: 2 * ovf_cap entries per workgroup, then (with
-// turn-off times) as many remaining-life bytes.
-int64_t spill_words(const RunPlan &p) {
-  int64_t ovf_cap = p.max_cells - p.s.queue_cap;
+// turn-off times) as many remaining-life bytes; a window plan's two
+// launches run one after the other and share the area.
+int64_t spill_words_one(int64_t max_cells, int queue_cap, int grid, bool dur) {
+  int64_t ovf_cap = max_cells - queue_cap;
   if (ovf_cap < 1) ovf_cap = 1;
-  const int64_t entries = (int64_t)p.grid * 2 * ovf_cap;
-  return entries + (p.dur ? (entries + 3) / 4 : 0);
+  const int64_t entries = (int64_t)grid * 2 * ovf_cap;
+  return entries + (dur ? (entries + 3) / 4 : 0);
+}
+
+int64_t spill_words(const RunPlan &p) {
+  int64_t w = spill_words_one(p.max_cells, p.s.queue_cap, p.grid, p.dur);
+  if (p.win > 0) w = std::max(w, spill_words_one(p.max_cells, p.s2.queue_cap, p.grid2, p.dur));
+  return w;
+}
+
+// Retry lists of window runs: `words` words (waits for the device when it grows).
+fire_status ensure_retry(fire_ctx *c, int64_t words) {
+  if ((size_t)words <= c->retry_words && c->d_retry) return FIRE_OK;
+  HIP_OR_FAIL(c, hipDeviceSynchronize());
+  size_t have = c->retry_words * sizeof(uint32_t);
+  HIP_OR_FAIL(c, ensure((void **)&c->d_retry, &have, (size_t)words * sizeof(uint32_t)));
+  c->retry_words = have / sizeof(uint32_t);
+  return FIRE_OK;
 }
 
 // Make the spill area hold `words` entries (waits for the device when it grows).
@@ -280,16 +457,56 @@ fire_status ensure_spill(fire_ctx *c, int64_t words) {
   return FIRE_OK;
 }
 
+// Fold finished retry-count copies into the landscapes' re-run shares.
+void harvest_stats(fire_ctx *c) {
+  for (int i = 0; i < fire_ctx::kStatSlots; ++i) {
+    const int l = c->stat_ls[i];
+    if (l < 0 || hipEventQuery(c->stat_ev[i]) != hipSuccess) continue;
+    (void)hipGetLastError();
+    if (l < (int)c->ls.size() && c->ls[l].live && c->stat_n[i] > 0) {
+      LandscapeHost &L = c->ls[l];
+      const float f = (float)c->h_stat[i] / (float)c->stat_n[i];
+      L.win_frac = L.win_obs ? 0.5f * L.win_frac + 0.5f * f : f;
+      ++L.win_obs;
+    }
+    c->stat_ls[i] = -1;
+  }
+}
+
+// Copy a window launch's retry count back without waiting (not under
+// stream capture; skipped when every slot is still in flight).
+void record_stat(fire_ctx *c, const uint32_t *retry, int lid, int32_t n, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return;
+  }
+  harvest_stats(c);
+  for (int i = 0; i < fire_ctx::kStatSlots; ++i) {
+    if (c->stat_ls[i] >= 0) continue;
+    if (hipMemcpyAsync(c->h_stat + i, retry, sizeof(uint32_t), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipEventRecord(c->stat_ev[i], st) != hipSuccess) {
+      (void)hipGetLastError();
+      return;
+    }
+    c->stat_ls[i] = lid;
+    c->stat_n[i] = n;
+    return;
+  }
+}
+
 // One persistent launch over n_sims descriptors (or over `order`, a list of
-// n_sims indices into sims_dev), with its own work counter and spill area.
-fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
-                       int32_t n_params, const fire_sim *sims_dev,
-                       const uint32_t *order, int32_t n_sims, uint64_t seed,
-                       const uint32_t *tables, int64_t table_stride,
-                       int32_t table_ls, fire_result *out, uint32_t *out_maps,
-                       int64_t map_words, int counter, uint32_t *spill,
-                       hipStream_t st) {
-  int64_t ovf_cap = p.max_cells - p.s.queue_cap;
+// n_sims indices into sims_dev), with its own work counter and spill area;
+// a window plan adds the second launch over the simulations listed in
+// `retry` (device, 1 + n_sims words).
+SimArgs sim_args(fire_ctx *c, const double *betas_dev, int32_t n_params,
+                 const fire_sim *sims_dev, const uint32_t *order, int32_t n_sims,
+                 uint64_t seed, const uint32_t *tables, int64_t table_stride, int32_t table_ls,
+                 fire_result *out, uint32_t *out_maps, int64_t map_words, int64_t max_cells,
+                 int queue_cap, int grid, bool dur, int bitset_words, uint32_t *work,
+                 uint32_t *spill) {
+  int64_t ovf_cap = max_cells - queue_cap;
   if (ovf_cap < 1) ovf_cap = 1;
   SimArgs a{};
   a.ls = c->d_ls; a.n_ls = (int32_t)c->ls.size();
@@ -299,12 +516,42 @@ fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
   a.key0 = (uint32_t)seed; a.key1 = (uint32_t)(seed >> 32);
   a.tables = tables; a.table_stride = table_stride; a.table_ls = table_ls;
   a.out = out; a.maps = out_maps; a.map_words = map_words;
-  a.work = c->d_work + counter; a.error_flag = c->d_work + kErrWord;
+  a.work = work; a.error_flag = c->d_work + kErrWord;
   a.ovf = spill; a.ovf_cap = ovf_cap;
-  a.ovf_life = p.dur ? reinterpret_cast<uint8_t *>(spill + (int64_t)p.grid * 2 * ovf_cap) : nullptr;
-  a.queue_cap = p.s.queue_cap; a.bitset_words = p.bitset_words;
+  a.ovf_life = dur ? reinterpret_cast<uint8_t *>(spill + (int64_t)grid * 2 * ovf_cap) : nullptr;
+  a.queue_cap = queue_cap; a.bitset_words = bitset_words;
+  a.win = 0; a.retry = nullptr; a.n_dev = nullptr;
+  return a;
+}
+
+fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
+                       int32_t n_params, const fire_sim *sims_dev,
+                       const uint32_t *order, int32_t n_sims, uint64_t seed,
+                       const uint32_t *tables, int64_t table_stride,
+                       int32_t table_ls, fire_result *out, uint32_t *out_maps,
+                       int64_t map_words, int counter, uint32_t *spill, uint32_t *retry,
+                       hipStream_t st, int stat_lid = -1) {
+  SimArgs a = sim_args(c, betas_dev, n_params, sims_dev, order, n_sims, seed, tables,
+                       table_stride, table_ls, out, out_maps, map_words, p.max_cells,
+                       p.s.queue_cap, p.grid, p.dur, p.bitset_words, c->d_work + counter, spill);
+  if (p.win > 0) {
+    if (!retry) return fail(c, FIRE_E_INVALID, "window plan without a retry list");
+    a.win = p.win;
+    a.retry = retry;
+    HIP_OR_FAIL(c, launch_fill_u32(retry, 0u, 1, st));
+  }
   HIP_OR_FAIL(c, launch_fill_u32(a.work, 0u, 1, st));
   HIP_OR_FAIL(c, launch_sim(a, p.s.threads, tables != nullptr, p.dur, p.grid, p.lds, st));
+  if (p.win > 0 && stat_lid >= 0) record_stat(c, retry, stat_lid, n_sims, st);
+  if (p.win > 0) {
+    SimArgs b = sim_args(c, betas_dev, n_params, sims_dev, retry + 1, n_sims, seed, tables,
+                         table_stride, table_ls, out, out_maps, map_words, p.max_cells,
+                         p.s2.queue_cap, p.grid2, p.dur, p.bitset_words2,
+                         c->d_work + counter + kMaxClasses, spill);
+    b.n_dev = retry;
+    HIP_OR_FAIL(c, launch_fill_u32(b.work, 0u, 1, st));
+    HIP_OR_FAIL(c, launch_sim(b, p.s2.threads, tables != nullptr, p.dur, p.grid2, p.lds2, st));
+  }
   return FIRE_OK;
 }
 
@@ -348,9 +595,12 @@ fire_status fire_ctx_create(int device, fire_ctx **out) {
   bool ev_ok = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess;
   for (int i = 0; i < kMaxClasses && ev_ok; ++i)
     ev_ok = hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < fire_ctx::kStatSlots && ev_ok; ++i)
+    ev_ok = hipEventCreateWithFlags(&c->stat_ev[i], hipEventDisableTiming) == hipSuccess;
   if (!ev_ok || hipMalloc(&c->d_work, kWorkWords * sizeof(uint32_t)) != hipSuccess ||
       hipMemset(c->d_work, 0, kWorkWords * sizeof(uint32_t)) != hipSuccess ||
       hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_stat, sizeof(uint32_t) * fire_ctx::kStatSlots) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     fire_ctx_destroy(c);
     return FIRE_E_DEVICE;
@@ -375,6 +625,10 @@ void fire_ctx_destroy(fire_ctx *c) {
   if (c->d_tg) (void)hipFree(c->d_tg);
   if (c->d_work) (void)hipFree(c->d_work);
   if (c->d_ovf) (void)hipFree(c->d_ovf);
+  if (c->d_retry) (void)hipFree(c->d_retry);
+  if (c->h_stat) (void)hipHostFree(c->h_stat);
+  for (int i = 0; i < fire_ctx::kStatSlots; ++i)
+    if (c->stat_ev[i]) (void)hipEventDestroy(c->stat_ev[i]);
   if (c->d_tables) (void)hipFree(c->d_tables);
   if (c->d_stage) (void)hipFree(c->d_stage);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
@@ -504,6 +758,8 @@ fire_status fire_landscape_set_burn_steps(fire_ctx *c, int32_t id, const uint8_t
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   HIP_OR_FAIL(c, hipDeviceSynchronize());
   LandscapeHost &L = c->ls[id];
+  L.win_frac = 0.f;  // fire sizes change with the turn-off times
+  L.win_obs = 0;
   if (!steps || all_one) {
     if (L.burn_steps) HIP_OR_FAIL(c, hipFree(L.burn_steps));
     L.burn_steps = nullptr;
@@ -680,7 +936,7 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
   // persistent launch with LDS sized for that class.
   std::vector<int> cls_of_ls(c->ls.size(), -1);
   std::vector<int64_t> cls_cells;
-  std::vector<int> cls_words;
+  std::vector<int> cls_words, cls_h, cls_stride;
   std::vector<char> cls_dur;
   std::vector<int> ls_ids;
   for (int32_t i = 0; i < n_sims; ++i) {
@@ -692,16 +948,23 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
       cls_of_ls[l] = (int)cls_cells.size();
       cls_cells.push_back((int64_t)c->ls[l].W * c->ls[l].H);
       cls_words.push_back(c->ls[l].H * c->ls[l].stride);
+      cls_h.push_back(c->ls[l].H);
+      cls_stride.push_back(c->ls[l].stride);
       cls_dur.push_back(c->ls[l].burn_steps != nullptr);
     }
   } else {
     bool any = false;
+    int mh = 1, ms = 1;
     for (int l : ls_ids) {
       cls_of_ls[l] = 0;
       any = any || c->ls[l].burn_steps != nullptr;
+      mh = std::max(mh, c->ls[l].H);
+      ms = std::max(ms, c->ls[l].stride);
     }
     cls_cells.push_back(mc);
     cls_words.push_back(bw);
+    cls_h.push_back(mh);
+    cls_stride.push_back(ms);
     cls_dur.push_back(any);
   }
   const int n_cls = (int)cls_cells.size();
@@ -710,15 +973,32 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
     members[cls_of_ls[sims[i].landscape_id]].push_back((uint32_t)i);
   std::vector<RunPlan> plans(n_cls);
   int64_t spill_total = 0;
+  harvest_stats(c);
+  std::vector<float> cls_frac(n_cls, 0.f);
+  std::vector<int> cls_lid(n_cls, -1);
+  for (int l : ls_ids) {
+    const int k = cls_of_ls[l];
+    cls_frac[k] = std::max(cls_frac[k], c->ls[l].win_frac);
+    cls_lid[k] = (int)ls_ids.size() <= kMaxClasses ? l : -1;
+  }
   for (int k = 0; k < n_cls; ++k) {
-    fire_status ps = plan_run(c, cls_words[k], cls_cells[k], n_params,
+    fire_status ps = plan_run(c, cls_words[k], cls_cells[k], cls_h[k], cls_stride[k], n_params,
                               (int32_t)members[k].size(), one_ls >= 0, &plans[k],
-                              cls_dur[k] != 0);
+                              cls_dur[k] != 0, cls_frac[k]);
     if (ps != FIRE_OK) return ps;
     spill_total += spill_words(plans[k]);
   }
   fire_status ss = ensure_spill(c, spill_total);
   if (ss != FIRE_OK) return ss;
+  // retry lists: class k at retry_start[k], 1 + |class| words
+  std::vector<int64_t> retry_start(n_cls, 0);
+  int64_t retry_total = 0;
+  for (int k = 0; k < n_cls; ++k) {
+    retry_start[k] = retry_total;
+    retry_total += 1 + (int64_t)members[k].size();
+  }
+  fire_status rs = ensure_retry(c, retry_total);
+  if (rs != FIRE_OK) return rs;
 
   // stage descriptors, parameters and class member lists
   const size_t bbytes = sizeof(double) * 5 * (size_t)n_params;
@@ -764,7 +1044,8 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
   }
   if (n_cls == 1)
     return launch_run(c, plans[0], d_betas, n_params, d_sims, nullptr, n_sims, seed, tables,
-                      tstride, tables ? one_ls : -1, out, out_maps, map_words, 0, c->d_ovf, st);
+                      tstride, tables ? one_ls : -1, out, out_maps, map_words, 0, c->d_ovf,
+                      c->d_retry, st, cls_lid[0]);
 
   // fork the classes onto side streams, join back to the caller's stream
   for (int k = 0; k < n_cls - 1; ++k)
@@ -786,7 +1067,8 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
     order_off = order_start[k];
     fire_status ls_ = launch_run(c, plans[k], d_betas, n_params, d_sims, d_order + order_off,
                                  (int32_t)members[k].size(), seed, nullptr, 0, -1, out,
-                                 out_maps, map_words, k, c->d_ovf + spill_off, ks);
+                                 out_maps, map_words, k, c->d_ovf + spill_off,
+                                 c->d_retry + retry_start[k], ks, cls_lid[k]);
     if (ls_ != FIRE_OK) return ls_;
     spill_off += spill_words(plans[k]);
     if (r > 0) {
@@ -806,15 +1088,20 @@ fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
     return fail(c, FIRE_E_INVALID, "bad sizes or null pointers");
   if (n_sims == 0) return FIRE_OK;
   // sized for every loaded landscape (the descriptors stay on the device)
-  int bw = 0, nlive = 0, lid = -1;
+  int bw = 0, nlive = 0, lid = -1, mh = 1, ms = 1;
   int64_t mc = 1;
   bool any_dur = false;
+  float frac = 0.f;
+  harvest_stats(c);
   for (size_t i = 0; i < c->ls.size(); ++i) {
     const LandscapeHost &L = c->ls[i];
     if (!L.live) continue;
     ++nlive;
     lid = (int)i;
     any_dur = any_dur || L.burn_steps != nullptr;
+    mh = std::max(mh, L.H);
+    ms = std::max(ms, L.stride);
+    frac = std::max(frac, L.win_frac);
     if (L.H * L.stride > bw) bw = L.H * L.stride;
     if ((int64_t)L.W * L.H > mc) mc = (int64_t)L.W * L.H;
   }
@@ -826,10 +1113,13 @@ fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   RunPlan plan;
-  fire_status ps = plan_run(c, bw, mc, n_params, n_sims, nlive == 1, &plan, any_dur);
+  fire_status ps =
+      plan_run(c, bw, mc, mh, ms, n_params, n_sims, nlive == 1, &plan, any_dur, frac);
   if (ps != FIRE_OK) return ps;
   fire_status ss = ensure_spill(c, spill_words(plan));
   if (ss != FIRE_OK) return ss;
+  fire_status rs = ensure_retry(c, 1 + (int64_t)n_sims);
+  if (rs != FIRE_OK) return rs;
   const uint32_t *tables = override_T;
   int64_t tstride = 0;
   if (override_T) {
@@ -839,7 +1129,8 @@ fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
     if (tsx != FIRE_OK) return tsx;
   }
   return launch_run(c, plan, betas_dev, n_params, sims_dev, nullptr, n_sims, seed, tables,
-                    tstride, tables ? lid : -1, out, out_maps, map_words, 0, c->d_ovf, st);
+                    tstride, tables ? lid : -1, out, out_maps, map_words, 0, c->d_ovf,
+                    c->d_retry, st, nlive == 1 ? lid : -1);
 }
 
 fire_status fire_run_dense(fire_ctx *c, const double *betas, int32_t n_params,
@@ -932,7 +1223,7 @@ fire_status fire_set_class_schedule(fire_ctx *c, int64_t max_cells, const fire_s
       s->threads != 1024)
     return fail(c, FIRE_E_INVALID, "threads must be 64, 128, 256, 512 or 1024");
   if (s->queue_cap < 64 || s->wg_per_cu < 1 || s->wg_per_cu > 32 ||
-      (s->table_mode != 0 && s->table_mode != 1))
+      (s->table_mode != 0 && s->table_mode != 1) || !valid_window(s->window))
     return fail(c, FIRE_E_INVALID, "schedule field out of range");
   c->class_sched.push_back({b, *s});
   return FIRE_OK;
@@ -945,7 +1236,8 @@ fire_status fire_set_schedule(fire_ctx *c, const fire_schedule *s) {
     return FIRE_OK;
   }
   if (!valid_threads(s->threads) || s->queue_cap < 64 || s->wg_per_cu < 1 ||
-      s->wg_per_cu > 32 || (s->table_mode != 0 && s->table_mode != 1))
+      s->wg_per_cu > 32 || (s->table_mode != 0 && s->table_mode != 1) ||
+      !valid_window(s->window))
     return fail(c, FIRE_E_INVALID, "schedule field out of range");
   if (lds_bytes_for(0, s->queue_cap) > c->max_lds)
     return fail(c, FIRE_E_INVALID, "queue_cap %d does not fit LDS", s->queue_cap);
@@ -955,17 +1247,22 @@ fire_status fire_set_schedule(fire_ctx *c, const fire_schedule *s) {
 }
 
 fire_status fire_get_schedule(fire_ctx *c, int64_t max_cells, int32_t n_params,
-                              fire_schedule *out) {
+                              int32_t n_sims, fire_schedule *out) {
   if (!c) return FIRE_E_INVALID;
-  if (!out || max_cells < 1) return fail(c, FIRE_E_INVALID, "bad arguments");
+  if (!out || max_cells < 1 || n_sims < 1) return fail(c, FIRE_E_INVALID, "bad arguments");
   if (c->sched_fixed) {
     *out = c->sched;
     return FIRE_OK;
   }
-  // bitset words of a square-ish lattice of max_cells cells
-  int64_t side = (int64_t)std::ceil(std::sqrt((double)max_cells));
-  int bw = (int)(side * ((side + 31) / 32));
-  *out = default_schedule(c, max_cells, bw, n_params);
+  // the plan of n_sims simulations on a square lattice of max_cells cells
+  const int side = (int)std::ceil(std::sqrt((double)max_cells));
+  const int stride = (side + 31) / 32;
+  RunPlan plan;
+  fire_status ps = plan_run(c, side * stride, max_cells, side, stride, n_params, n_sims,
+                            n_params <= 8, &plan);
+  if (ps != FIRE_OK) return ps;
+  *out = plan.s;
+  out->window = plan.win;
   return FIRE_OK;
 }
 
@@ -1090,26 +1387,14 @@ static fire_status ga_run_graph(fire_ctx *c, int32_t lid, int32_t tid, int32_t i
   // plan the simulation launch for this landscape only (on-the-fly thresholds,
   // since the parameters change every generation)
   RunPlan plan;
-  fire_status ps = plan_run(c, L.H * L.stride, (int64_t)L.W * L.H, P, n, false, &plan,
-                            L.burn_steps != nullptr);
+  harvest_stats(c);
+  fire_status ps = plan_run(c, L.H * L.stride, (int64_t)L.W * L.H, L.H, L.stride, P, n, false,
+                            &plan, L.burn_steps != nullptr, L.win_frac);
   if (ps != FIRE_OK) return ps;
-  int64_t ovf_cap = plan.max_cells - plan.s.queue_cap;
-  if (ovf_cap < 1) ovf_cap = 1;
   fire_status ss = ensure_spill(c, spill_words(plan));
   if (ss != FIRE_OK) return ss;
-  SimArgs a{};
-  a.ls = c->d_ls; a.n_ls = (int32_t)c->ls.size();
-  a.tg = c->d_tg; a.n_tg = (int32_t)c->tg.size();
-  a.betas = ign_genes ? d_beta : d_pop; a.n_params = P;
-  a.sims = d_sims; a.n_sims = n;
-  a.key0 = (uint32_t)sim_seed; a.key1 = (uint32_t)(sim_seed >> 32);
-  a.tables = nullptr; a.table_stride = 0; a.table_ls = -1;
-  a.out = d_res; a.maps = nullptr; a.map_words = 0;
-  a.work = c->d_work; a.error_flag = c->d_work + kErrWord;
-  a.ovf = c->d_ovf; a.ovf_cap = ovf_cap;
-  a.ovf_life = plan.dur ? reinterpret_cast<uint8_t *>(c->d_ovf + (int64_t)plan.grid * 2 * ovf_cap)
-                        : nullptr;
-  a.queue_cap = plan.s.queue_cap; a.bitset_words = plan.bitset_words;
+  fire_status rs = ensure_retry(c, 1 + (int64_t)n);
+  if (rs != FIRE_OK) return rs;
 
   // capture one generation
   hipStream_t cap = nullptr;
@@ -1120,7 +1405,10 @@ static fire_status ga_run_graph(fire_ctx *c, int32_t lid, int32_t tid, int32_t i
   if (e == hipSuccess) e = launch_ga_prepare(d_gen, d_sims, P, R, c->d_work, d_pop, G, hist_pop, cap);
   if (e == hipSuccess && ign_genes)
     e = launch_sims_from_pop(d_pop, P, G, R, lid, tid, L.W, L.H, 0u, d_gen, d_sims, d_beta, cap);
-  if (e == hipSuccess) e = launch_sim(a, plan.s.threads, false, plan.dur, plan.grid, plan.lds, cap);
+  if (e == hipSuccess &&
+      launch_run(c, plan, ign_genes ? d_beta : d_pop, P, d_sims, nullptr, n, sim_seed, nullptr, 0,
+                 -1, d_res, nullptr, 0, 0, c->d_ovf, c->d_retry, cap) != FIRE_OK)
+    e = hipErrorLaunchFailure;
   if (e == hipSuccess) e = launch_ga_gather(d_gen, d_res, P, R, d_fit, hist_fit, cap);
   if (e == hipSuccess)
     e = launch_ga_step(d_pop, d_fit, nullptr, P, G, R, elite, pm0, box, 0u, d_gen, generations,

@@ -55,6 +55,11 @@ struct SimArgs {
   int64_t ovf_cap;
   int32_t queue_cap;       // frontier entries per queue held in LDS
   int32_t bitset_words;    // LDS words reserved for the burn bitset
+  int32_t win;             // 0, or the side (cells, multiple of 32) of the
+                           // LDS window a simulation runs in
+  uint32_t *retry;         // window runs: [0] count, [1..] simulations whose
+                           // fire reached the window edge
+  const uint32_t *n_dev;   // NULL, or the device count of simulations (else n_sims)
 };
 
 // Launchers (fire_kernels.hip). Each returns the hipError_t of its launch.
@@ -70,6 +75,9 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_sim(const SimArgs &a, int threads, bool table, bool dur, int grid,
                       size_t lds_bytes, hipStream_t s);
 hipError_t set_sim_lds_limit(size_t bytes);
+// workgroups of the simulation kernel resident per compute unit for this
+// launch shape (registers and LDS), 0 if unknown
+int sim_occupancy(int threads, bool table, bool dur, bool win, size_t lds_bytes);
 // per-cell (paper-style) ablation path
 hipError_t launch_dense_init(uint8_t *st, const LandscapeDev &L, int ix, int iy,
                              unsigned long long *counts, hipStream_t s);

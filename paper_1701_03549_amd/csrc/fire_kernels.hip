@@ -9,6 +9,8 @@
 // another IEEE implementation come from exp and cos.
 
 #include <hip/hip_runtime.h>
+
+#include <climits>
 #include <math.h>
 #include <stdint.h>
 
@@ -171,16 +173,18 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
 //   * the cells that ignited at the previous step form the frontier queue,
 //     entries x | y << 12 (the top byte is scratch), held in LDS up to
 //     queue_cap entries and in a per-workgroup global spill area beyond;
-//   * work is spread one lane per directed edge (frontier cell, direction),
-//     so a small front still fills a wave and every lane's dependent chain
-//     is one bitset read, one 4-byte threshold and one Philox call;
+//   * work is spread one lane per (frontier cell, group of four directions):
+//     the four edges of a group take their coins from the four words of one
+//     Philox call, which is most of the arithmetic of a step, so each call
+//     is made once; a lane reads its four thresholds with one 16-byte load;
 //   * each step runs in two phases separated by barriers. Phase 1 only
 //     reads the bitset, so eligibility is judged against the burn state at
-//     the start of the step; it draws the coins of the eligible edges and a
-//     wave ballot gathers each cell's 8 outcomes into the entry's top byte.
-//     Phase 2 sets the bits of the successful targets with atomic ORs; the
-//     lane whose OR flipped a bit owns that new cell and appends it to the
-//     next frontier (ballot + prefix count, one LDS atomic per wave).
+//     the start of the step; it draws the coins of the eligible edges (small
+//     fronts keep the 4-bit outcome in registers, larger ones merge the two
+//     nibbles of a cell into its entry's top byte). Phase 2 sets the bits of
+//     the successful targets with atomic ORs; the lane whose OR flipped a bit
+//     owns that new cell and appends it to the next frontier (bit-sliced
+//     ballot prefix of the per-lane counts, one LDS atomic per wave).
 // Every coin is a pure function of (sim_index, step, source cell, direction)
 // and ignition is an OR, so the burnt set, step count, trial count and
 // fitness do not depend on thread order or on the schedule.
@@ -200,6 +204,12 @@ typedef const __attribute__((address_space(1))) double gmem_cf64;
 typedef __attribute__((address_space(1))) uint8_t gmem_u8;
 typedef const __attribute__((address_space(1))) uint8_t gmem_cu8;
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) u32x4 gmem_cu32x4;
+
+// Four consecutive 32-bit words from a 16-byte aligned global address.
+__device__ __forceinline__ u32x4 load_x4(gmem_cu32 *q) { return *(gmem_cu32x4 *)q; }
+
 __device__ __forceinline__ uint4 load_rec(const uint4 *base, int64_t t) {
   gmem_cu32 *q = (gmem_cu32 *)(base + t);
   return make_uint4(q[0], q[1], q[2], q[3]);
@@ -215,13 +225,13 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t ballot) {
 }
 
 enum CtlSlot { kSim = 0, kLen0 = 1, kTrials = 4, kNew = 5, kInter = 6, kRowLo = 7, kRowHi = 8,
-               kCtlWords = 16 };
+               kAbort = 9, kCtlWords = 16 };
 
 // register-resident rounds of the small-front step (fronts of up to
-// kRegRounds * BLOCK / 8 cells)
+// kRegRounds * BLOCK / 2 cells held in the LDS queue)
 constexpr int kRegRounds = 4;
 
-template <int BLOCK, bool TABLE, bool DUR>
+template <int BLOCK, bool TABLE, bool DUR, bool WIN>
 __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
   extern __shared__ uint32_t lds[];
   const int bw = a.bitset_words;
@@ -257,7 +267,8 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
   for (;;) {
     if (tid == 0) {
       const uint32_t k = atomicAdd(a.work, 1u);
-      ctl[kSim] = k < (uint32_t)a.n_sims ? (a.order ? a.order[k] : k) : 0xFFFFFFFFu;
+      const uint32_t n = a.n_dev ? *a.n_dev : (uint32_t)a.n_sims;
+      ctl[kSim] = k < n ? (a.order ? a.order[k] : k) : 0xFFFFFFFFu;
     }
     __syncthreads();
     const uint32_t sim = ctl[kSim];
@@ -271,7 +282,9 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     if (ok) {
       L = a.ls[sd.landscape_id];
       ok = L.valid && sd.ign_x >= 0 && sd.ign_x < L.W && sd.ign_y >= 0 &&
-           sd.ign_y < L.H && L.H * L.stride <= a.bitset_words &&
+           sd.ign_y < L.H &&
+           (WIN ? min(a.win, L.H) * min(a.win >> 5, L.stride) : L.H * L.stride) <=
+               a.bitset_words &&
            (a.maps == nullptr || (int64_t)L.H * L.stride <= a.map_words) &&
            (a.tables == nullptr || a.table_ls == sd.landscape_id);
     }
@@ -319,12 +332,39 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       continue;
     }
 
+    // -- window: the LDS bitset covers rows [wy0, wy0 + wh) and words
+    //    [wx0w, wx0w + ws) of each row, placed around the ignition (the whole
+    //    lattice without a window). A cell that would start burning within
+    //    one cell of a window edge that is not a lattice edge aborts the run,
+    //    which is then repeated without a window: a burning cell's
+    //    neighbours therefore always lie in the window.
+    const int ws = WIN ? min(a.win >> 5, stride) : stride;
+    const int wh = WIN ? min(a.win, H) : H;
+    const int wx0w = WIN ? min(max((ix >> 5) - ws / 2, 0), stride - ws) : 0;
+    const int wy0 = WIN ? min(max(iy - wh / 2, 0), H - wh) : 0;
+    // cells a burning cell may occupy: one cell inside every window edge
+    // that lies inside the lattice
+    const int x_lo = wx0w > 0 ? 32 * wx0w + 1 : INT_MIN;
+    const int x_hi = wx0w + ws < stride ? 32 * (wx0w + ws) - 2 : INT_MAX;
+    const int y_lo = wy0 > 0 ? wy0 + 1 : INT_MIN;
+    const int y_hi = wy0 + wh < H ? wy0 + wh - 2 : INT_MAX;
+    auto near_edge = [&](int x, int y) -> bool {
+      return WIN && (x < x_lo || x > x_hi || y < y_lo || y > y_hi);
+    };
+    // LDS word of cell (x, y) inside the window
+    const int w_off = wy0 * ws + wx0w;
+    auto bw_of = [&](int x, int y) -> int { return y * ws + (x >> 5) - w_off; };
+    // global word of window word w
+    auto gw_of = [&](int w) -> int { return (wy0 + w / ws) * stride + wx0w + w % ws; };
+    const int wwords = wh * ws;
+
     // -- init: bitset = non-burnable map, ignition burnt -------------------
-    for (int w = tid; w < words; w += BLOCK) bits[w] = blocked[w];
+    for (int w = tid; w < wwords; w += BLOCK) bits[w] = blocked[gw_of(w)];
     if (tid == 0) {
       ctl[kLen0 + 0] = 1; ctl[kLen0 + 1] = 0; ctl[kLen0 + 2] = 0;
       ctl[kTrials] = 0; ctl[kNew] = 0; ctl[kInter] = 0;
       ctl[kRowLo] = (uint32_t)iy; ctl[kRowHi] = (uint32_t)iy;
+      ctl[kAbort] = near_edge(ix, iy) ? 1u : 0u;
     }
     __syncthreads();
     gmem_cu8 *const bsteps = DUR ? (gmem_cu8 *)L.burn_steps : nullptr;
@@ -334,7 +374,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       return bsteps[load_rec(L.rec, (int64_t)y * W + x).w & 0xFFu];
     };
     if (tid == 0) {
-      bits[iy * stride + (ix >> 5)] |= 1u << (ix & 31);
+      bits[bw_of(ix, iy)] |= 1u << (ix & 31);
       q_store(0, 0, (uint32_t)ix | ((uint32_t)iy << 12));
       if (DUR) l_store(0, 0, life_of(ix, iy));
     }
@@ -356,125 +396,175 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     // frontier length of step k lives in ctl[kLen0 + k % 3]
     int slot = 0;
 
-    // Phase 1 for one directed edge j of the current frontier: whether the
-    // edge is tried (target inside, burnable, unburnt at step start) and
-    // whether its coin succeeds.
-    auto edge_outcome = [&](uint32_t e, int d, bool &tried, int &tx, int &ty) -> bool {
+    // Phase 1 for one unit: frontier entry e and direction group g (edges
+    // d = 4g .. 4g+3, whose coins are the four words of one Philox call
+    // (sim_index, step, source, g)). An edge is tried when its target is
+    // inside, burnable and unburnt at the start of the step. Returns the
+    // 4-bit mask of tried edges whose coin succeeds; n_tried counts the
+    // tried edges.
+    auto unit_outcome = [&](uint32_t e, uint32_t g, uint32_t &n_tried) -> uint32_t {
       const int x = (int)(e & 0xFFFu), y = (int)((e >> 12) & 0xFFFu);
       const uint32_t s_lin = (uint32_t)(y * W + x);
-      uint32_t thr = 0;
-      if (TABLE) thr = table[(int64_t)s_lin * 8 + d];
-      tx = x + dir_dx(d);
-      ty = y + dir_dy(d);
-      const bool inside = (unsigned)tx < (unsigned)W && (unsigned)ty < (unsigned)H;
-      const int cx = inside ? tx : x, cy = inside ? ty : y;
-      const uint32_t word = bits[cy * stride + (cx >> 5)];
-      tried = inside && ((word >> (cx & 31)) & 1u) == 0;
-      const Words4 r = philox10(sim_index, step, s_lin, (uint32_t)(d >> 2), a.key0, a.key1);
-      const int k = d & 3;
-      const uint32_t coin = k == 0 ? r.v[0] : k == 1 ? r.v[1] : k == 2 ? r.v[2] : r.v[3];
-      if (!tried) return false;
-      if (!TABLE) {
-        const int64_t t = (int64_t)ty * W + tx;
-        thr = edge_threshold(beta, load_rec(L.rec, t), ((gmem_cf64 *)L.psi)[t], d,
-                             L.forest_class);
+      uint32_t thr[4] = {0u, 0u, 0u, 0u};
+      if (TABLE) {
+        // the 8 thresholds of a source are 32 contiguous bytes; group g is
+        // the 16-byte half g (tables are 16-byte aligned)
+        const u32x4 t4 = load_x4(table + (int64_t)s_lin * 8 + 4 * g);
+        thr[0] = t4.x; thr[1] = t4.y; thr[2] = t4.z; thr[3] = t4.w;
       }
-      return thr == kSaturated || coin < thr;
+      uint32_t elig = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int d = 4 * (int)g + k;
+        const int tx = x + dir_dx(d), ty = y + dir_dy(d);
+        const bool inside = (unsigned)tx < (unsigned)W && (unsigned)ty < (unsigned)H;
+        const int cx = inside ? tx : x, cy = inside ? ty : y;
+        const uint32_t word = bits[bw_of(cx, cy)];
+        elig |= (inside && ((word >> (cx & 31)) & 1u) == 0) ? (1u << k) : 0u;
+      }
+      n_tried = __popc(elig);
+      // not gated on elig: the rounds then overlap the bitset and table reads
+      const Words4 r = philox10(sim_index, step, s_lin, g, a.key0, a.key1);
+      uint32_t hit = 0;
+      if (TABLE) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (((elig >> k) & 1u) && (thr[k] == kSaturated || r.v[k] < thr[k])) hit |= 1u << k;
+      } else {
+        // one Eq. 1 evaluation at a time keeps the binary64 temporaries of
+        // a single edge live
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+          if (!((elig >> k) & 1u)) continue;
+          const int d = 4 * (int)g + k;
+          const int64_t tl = (int64_t)(y + dir_dy(d)) * W + (x + dir_dx(d));
+          const uint32_t t = edge_threshold(beta, load_rec(L.rec, tl), ((gmem_cf64 *)L.psi)[tl],
+                                            d, L.forest_class);
+          const uint32_t coin = k == 0 ? r.v[0] : k == 1 ? r.v[1] : k == 2 ? r.v[2] : r.v[3];
+          if (t == kSaturated || coin < t) hit |= 1u << k;
+        }
+      }
+      return hit;
+    };
+
+    // Phase 2 for one unit: set the bits of the hit targets; returns the
+    // mask of targets whose bit this lane flipped (cells it now owns).
+    auto unit_ignite = [&](uint32_t e, uint32_t g, uint32_t hit) -> uint32_t {
+      uint32_t fresh = 0;
+      const int x = (int)(e & 0xFFFu), y = (int)((e >> 12) & 0xFFFu);
+      // branch-free: an edge that did not hit ORs 0 into its source's own
+      // word, so the four atomics issue back to back
+      uint32_t old[4], bitv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int d = 4 * (int)g + k;
+        const bool h = (hit >> k) & 1u;
+        const int tx = h ? x + dir_dx(d) : x, ty = h ? y + dir_dy(d) : y;
+        bitv[k] = h ? 1u << (tx & 31) : 0u;
+        old[k] = atomicOr(&bits[bw_of(tx, ty)], bitv[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (bitv[k] && (old[k] & bitv[k]) == 0) fresh |= 1u << k;
+      return fresh;
+    };
+
+    // Append each lane's fresh cells to the next frontier: a wave-wide
+    // exclusive prefix of the per-lane counts (0..4) from three bit-sliced
+    // ballots, one LDS atomic per wave. `direct`: the queue slot is known to
+    // lie in LDS.
+    auto append = [&](uint32_t e, uint32_t g, uint32_t fresh, int nslot, bool direct) {
+      const uint32_t cnt = __popc(fresh);
+      const uint64_t b0 = __ballot(cnt & 1u), b1 = __ballot(cnt & 2u), b2 = __ballot(cnt & 4u);
+      const uint32_t total = (uint32_t)(__popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2));
+      if (total == 0) return;
+      uint32_t wbase = 0;
+      if (lane == 0) wbase = atomicAdd(&ctl[kLen0 + nslot], total);
+      wbase = __builtin_amdgcn_readfirstlane(wbase);
+      if (!fresh) return;
+      uint32_t idx = wbase + lane_prefix(b0) + 2 * lane_prefix(b1) + 4 * lane_prefix(b2);
+      const int x = (int)(e & 0xFFFu), y = (int)((e >> 12) & 0xFFFu);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (!((fresh >> k) & 1u)) continue;
+        const int d = 4 * (int)g + k;
+        const int tx = x + dir_dx(d), ty = y + dir_dy(d);
+        const uint32_t v = (uint32_t)tx | ((uint32_t)ty << 12);
+        if (direct) {
+          lds[bw + (cq ^ 1u) * cap + idx] = v;
+          if (DUR) life_lds[(cq ^ 1u) * cap + idx] = (uint8_t)life_of(tx, ty);
+        } else {
+          q_store(cq ^ 1u, idx, v);
+          if (DUR) l_store(cq ^ 1u, idx, life_of(tx, ty));
+        }
+        ++idx;
+        ++my_new;
+        row_lo = min(row_lo, (uint32_t)ty);
+        row_hi = max(row_hi, (uint32_t)ty);
+        if (near_edge(tx, ty)) ctl[kAbort] = 1u;
+      }
     };
 
     for (;; ++step) {
       // the frontier length and this lane's first entry are read together
       const uint32_t n_cur = ctl[kLen0 + slot];
-      const uint32_t e_first = lds[bw + cq * cap + min((uint32_t)tid >> 3, cap - 1)];
-      if (n_cur == 0 || step >= max_steps) break;
+      const uint32_t e_first = lds[bw + cq * cap + min((uint32_t)tid >> 1, cap - 1)];
+      if (n_cur == 0 || step >= max_steps || ctl[kAbort] != 0u) break;
       const int nslot = slot == 2 ? 0 : slot + 1;
       if (tid == 0) ctl[kLen0 + nslot] = 0;
-      const uint32_t n_edges = 8 * n_cur;
+      const uint32_t n_units = 2 * n_cur;
 
-      if (n_edges <= (uint32_t)(kRegRounds * BLOCK) && n_edges <= cap) {
-        // -- small front: outcomes stay in registers between the phases,
-        //    and both queues live in LDS ---------------------------------
-        bool hit[kRegRounds];
-        int htx[kRegRounds], hty[kRegRounds];
+      if (n_units <= (uint32_t)(kRegRounds * BLOCK) && n_cur <= cap) {
+        // -- small front: outcomes stay in registers between the phases and
+        //    the current queue is in LDS; new cells go straight to LDS when
+        //    they cannot outgrow it (8 per entry), else through q_store --
+        const bool direct = 8 * n_cur <= cap;
+        uint32_t hit[kRegRounds], ent[kRegRounds];
 #pragma unroll
         for (int rr = 0; rr < kRegRounds; ++rr) {
-          hit[rr] = false;
-          htx[rr] = 0;
-          hty[rr] = 0;
+          hit[rr] = 0;
+          ent[rr] = 0;
           const uint32_t j = (uint32_t)(tid + rr * BLOCK);
-          if (rr * BLOCK < (int)n_edges && j < n_edges) {
-            const uint32_t e = rr == 0 ? e_first : lds[bw + cq * cap + (j >> 3)];
-            bool tried;
-            hit[rr] = edge_outcome(e, (int)(j & 7u), tried, htx[rr], hty[rr]);
-            my_trials += tried ? 1u : 0u;
+          if (rr * BLOCK < (int)n_units && j < n_units) {
+            const uint32_t e = rr == 0 ? e_first : lds[bw + cq * cap + (j >> 1)];
+            ent[rr] = e;
+            uint32_t nt;
+            hit[rr] = unit_outcome(e, j & 1u, nt);
+            my_trials += nt;
           }
         }
         __syncthreads();
 #pragma unroll
         for (int rr = 0; rr < kRegRounds; ++rr) {
-          if (rr * BLOCK >= (int)n_edges) break;
-          bool fresh = false;
-          if (hit[rr]) {
-            const uint32_t bit = 1u << (htx[rr] & 31);
-            fresh = (atomicOr(&bits[hty[rr] * stride + (htx[rr] >> 5)], bit) & bit) == 0;
-          }
-          const uint64_t bal = __ballot(fresh);
-          if (bal != 0) {
-            uint32_t wbase = 0;
-            if (lane == 0) wbase = atomicAdd(&ctl[kLen0 + nslot], (uint32_t)__popcll(bal));
-            wbase = __builtin_amdgcn_readfirstlane(wbase);
-            if (fresh) {
-              const uint32_t idx = wbase + lane_prefix(bal);
-              lds[bw + (cq ^ 1u) * cap + idx] = (uint32_t)htx[rr] | ((uint32_t)hty[rr] << 12);
-              if (DUR) life_lds[(cq ^ 1u) * cap + idx] = (uint8_t)life_of(htx[rr], hty[rr]);
-              ++my_new;
-              row_lo = min(row_lo, (uint32_t)hty[rr]);
-              row_hi = max(row_hi, (uint32_t)hty[rr]);
-            }
-          }
+          if (rr * BLOCK >= (int)n_units) break;
+          const uint32_t g = (uint32_t)tid & 1u;
+          const uint32_t fresh = hit[rr] ? unit_ignite(ent[rr], g, hit[rr]) : 0u;
+          append(ent[rr], g, fresh, nslot, direct);
         }
       } else {
-        // -- general front: outcomes gathered into each entry's top byte;
-        //    queues spill to global memory past queue_cap ----------------
-        for (uint32_t j = tid; j < n_edges; j += BLOCK) {
-          const uint32_t e = q_load(cq, j >> 3);
-          bool tried;
-          int tx, ty;
-          const bool hit = edge_outcome(e, (int)(j & 7u), tried, tx, ty);
-          my_trials += tried ? 1u : 0u;
-          const uint64_t bal = __ballot(hit);
-          const uint32_t m8 = (uint32_t)(bal >> (lane & 56)) & 0xFFu;
-          if ((j & 7u) == 0 && m8 != 0) q_store(cq, j >> 3, e | (m8 << 24));
+        // -- general front: the two units of an entry merge their outcome
+        //    nibbles into the entry's top byte; queues spill to global
+        //    memory past queue_cap ----------------------------------------
+        for (uint32_t j = tid; j < n_units; j += BLOCK) {
+          const uint32_t e = q_load(cq, j >> 1);
+          uint32_t nt;
+          const uint32_t m = unit_outcome(e, j & 1u, nt);
+          my_trials += nt;
+          const uint32_t other = (uint32_t)__shfl_xor((int)m, 1);
+          const uint32_t m8 = (j & 1u) ? 0u : (m | (other << 4));
+          if (m8 != 0) q_store(cq, j >> 1, e | (m8 << 24));
         }
         __syncthreads();
-        for (uint32_t base = 0; base < n_edges; base += BLOCK) {
+        for (uint32_t base = 0; base < n_units; base += BLOCK) {
           const uint32_t j = base + (uint32_t)tid;
-          bool fresh = false;
-          int tx = 0, ty = 0;
-          if (j < n_edges) {
-            const uint32_t e = q_load(cq, j >> 3);
-            const int d = (int)(j & 7u);
-            if ((e >> (24 + d)) & 1u) {
-              tx = (int)(e & 0xFFFu) + dir_dx(d);
-              ty = (int)((e >> 12) & 0xFFFu) + dir_dy(d);
-              const uint32_t bit = 1u << (tx & 31);
-              fresh = (atomicOr(&bits[ty * stride + (tx >> 5)], bit) & bit) == 0;
-            }
+          const uint32_t g = j & 1u;
+          uint32_t e = 0, fresh = 0;
+          if (j < n_units) {
+            e = q_load(cq, j >> 1);
+            const uint32_t hit = (e >> (24 + 4 * g)) & 0xFu;
+            if (hit) fresh = unit_ignite(e, g, hit);
           }
-          const uint64_t bal = __ballot(fresh);
-          if (bal != 0) {
-            uint32_t wbase = 0;
-            if (lane == 0) wbase = atomicAdd(&ctl[kLen0 + nslot], (uint32_t)__popcll(bal));
-            wbase = __builtin_amdgcn_readfirstlane(wbase);
-            if (fresh) {
-              const uint32_t idx = wbase + lane_prefix(bal);
-              q_store(cq ^ 1u, idx, (uint32_t)tx | ((uint32_t)ty << 12));
-              if (DUR) l_store(cq ^ 1u, idx, life_of(tx, ty));
-              ++my_new;
-              row_lo = min(row_lo, (uint32_t)ty);
-              row_hi = max(row_hi, (uint32_t)ty);
-            }
-          }
+          append(e, g, fresh, nslot, false);
         }
       }
       if (DUR) {
@@ -506,6 +596,14 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       cq ^= 1u;
     }
 
+    if (ctl[kAbort] != 0u) {
+      // the fire reached the window edge: queue the simulation for a run
+      // without a window (every lane has read kAbort after the last barrier)
+      __syncthreads();
+      if (tid == 0) a.retry[1 + atomicAdd(a.retry, 1u)] = sim;
+      continue;
+    }
+
     // -- result: counts, Eq. 2 over the rows the fire reached, map ---------
     if (my_trials) atomicAdd(&ctl[kTrials], my_trials);
     if (my_new) {
@@ -517,9 +615,12 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     if (has_target) {
       // |A n A*| = popcount(burnt & reference) over the burnt rows
       gmem_cu32 *const ref = (gmem_cu32 *)tg.bits;
-      const int w0 = (int)ctl[kRowLo] * stride, w1 = ((int)ctl[kRowHi] + 1) * stride;
+      const int w0 = ((int)ctl[kRowLo] - wy0) * ws, w1 = ((int)ctl[kRowHi] + 1 - wy0) * ws;
       uint32_t inter = 0;
-      for (int w = w0 + tid; w < w1; w += BLOCK) inter += __popc(bits[w] & ~blocked[w] & ref[w]);
+      for (int w = w0 + tid; w < w1; w += BLOCK) {
+        const int gw = gw_of(w);
+        inter += __popc(bits[w] & ~blocked[gw] & ref[gw]);
+      }
       if (inter) atomicAdd(&ctl[kInter], inter);
       __syncthreads();
     }
@@ -538,7 +639,11 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     }
     if (a.maps != nullptr) {
       uint32_t *m = a.maps + (int64_t)sim * a.map_words;
-      for (int w = tid; w < words; w += BLOCK) m[w] = bits[w] & ~blocked[w];
+      for (int w = tid; w < words; w += BLOCK) {
+        const int y = w / stride, xw = w % stride;
+        const bool in = y >= wy0 && y < wy0 + wh && xw >= wx0w && xw < wx0w + ws;
+        m[w] = in ? bits[(y - wy0) * ws + (xw - wx0w)] & ~blocked[w] : 0u;
+      }
     }
     __syncthreads();
   }
@@ -1005,26 +1110,65 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int BLOCK, bool TABLE, bool DUR>
+static void launch_one(const SimArgs &a, bool win, int grid, size_t lds, hipStream_t s) {
+  if (win)
+    hipLaunchKernelGGL((sim_kernel<BLOCK, TABLE, DUR, true>), dim3(grid), dim3(BLOCK), lds, s, a);
+  else
+    hipLaunchKernelGGL((sim_kernel<BLOCK, TABLE, DUR, false>), dim3(grid), dim3(BLOCK), lds, s, a);
+}
+
 template <int BLOCK>
 static hipError_t launch_sim_block(const SimArgs &a, bool table, bool dur, int grid,
                                    size_t lds, hipStream_t s) {
+  const bool win = a.win > 0;
   if (dur) {
-    if (table)
-      hipLaunchKernelGGL((sim_kernel<BLOCK, true, true>), dim3(grid), dim3(BLOCK), lds, s, a);
-    else
-      hipLaunchKernelGGL((sim_kernel<BLOCK, false, true>), dim3(grid), dim3(BLOCK), lds, s, a);
+    if (table) launch_one<BLOCK, true, true>(a, win, grid, lds, s);
+    else launch_one<BLOCK, false, true>(a, win, grid, lds, s);
   } else {
-    if (table)
-      hipLaunchKernelGGL((sim_kernel<BLOCK, true, false>), dim3(grid), dim3(BLOCK), lds, s, a);
-    else
-      hipLaunchKernelGGL((sim_kernel<BLOCK, false, false>), dim3(grid), dim3(BLOCK), lds, s, a);
+    if (table) launch_one<BLOCK, true, false>(a, win, grid, lds, s);
+    else launch_one<BLOCK, false, false>(a, win, grid, lds, s);
   }
   return hipGetLastError();
+}
+
+template <int BLOCK, bool TABLE, bool DUR>
+static int occupancy_one(size_t lds, bool win) {
+  int n = 0;
+  hipError_t e = win ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &n, sim_kernel<BLOCK, TABLE, DUR, true>, BLOCK, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &n, sim_kernel<BLOCK, TABLE, DUR, false>, BLOCK, lds);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+template <int BLOCK>
+static int occupancy_block(bool table, bool dur, bool win, size_t lds) {
+  if (dur) return table ? occupancy_one<BLOCK, true, true>(lds, win)
+                        : occupancy_one<BLOCK, false, true>(lds, win);
+  return table ? occupancy_one<BLOCK, true, false>(lds, win)
+               : occupancy_one<BLOCK, false, false>(lds, win);
+}
+
+int sim_occupancy(int threads, bool table, bool dur, bool win, size_t lds_bytes) {
+  switch (threads) {
+    case 64: return occupancy_block<64>(table, dur, win, lds_bytes);
+    case 128: return occupancy_block<128>(table, dur, win, lds_bytes);
+    case 256: return occupancy_block<256>(table, dur, win, lds_bytes);
+    case 512: return occupancy_block<512>(table, dur, win, lds_bytes);
+    case 1024: return occupancy_block<1024>(table, dur, win, lds_bytes);
+    default: return 0;
+  }
 }
 
 hipError_t launch_sim(const SimArgs &a, int threads, bool table, bool dur, int grid,
                       size_t lds_bytes, hipStream_t s) {
   if (dur && a.ovf_life == nullptr) return hipErrorInvalidValue;
+  if (a.win > 0 && a.retry == nullptr) return hipErrorInvalidValue;
   switch (threads) {
     case 64: return launch_sim_block<64>(a, table, dur, grid, lds_bytes, s);
     case 128: return launch_sim_block<128>(a, table, dur, grid, lds_bytes, s);
@@ -1037,7 +1181,11 @@ hipError_t launch_sim(const SimArgs &a, int threads, bool table, bool dur, int g
 
 template <int BLOCK, bool TABLE, bool DUR>
 static hipError_t set_limit_one(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR>),
+  hipError_t e = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, false>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, true>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 

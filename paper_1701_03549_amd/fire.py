@@ -50,7 +50,8 @@ class LandscapeDesc(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
-                ("table_mode", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+                ("table_mode", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("window", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -91,7 +92,7 @@ def load_library(path: str = LIB_PATH):
         "fire_run_dev": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_run_dense": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, i64, vp]),
         "fire_set_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
-        "fire_get_schedule": (i32, [vp, i64, i32, ctypes.POINTER(Schedule)]),
+        "fire_get_schedule": (i32, [vp, i64, i32, i32, ctypes.POINTER(Schedule)]),
         "fire_set_class_schedule": (i32, [vp, i64, ctypes.POINTER(Schedule)]),
         "fire_ga_step": (i32, [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(GACfg), u32, u64, vp]),
         "fire_ga_step_genes": (i32, [vp, vp, vp, vp, i32, i32, i32, i32, dbl, vp, vp, vp, u32, u32,
@@ -273,11 +274,13 @@ class FireGPU:
 
     # -- schedule ------------------------------------------------------------
     def set_schedule(self, threads=None, queue_cap=None, table_mode=None, wg_per_cu=None,
-                     reset=False):
+                     window=0, reset=False):
+        """Fix the schedule (window: 0 = whole-lattice bitsets, -1 = built-in
+        choice, else the LDS window side in cells)."""
         if reset:
             self._check(self.lib.fire_set_schedule(self.ctx, None))
             return
-        s = Schedule(int(threads), int(queue_cap), int(table_mode), int(wg_per_cu))
+        s = Schedule(int(threads), int(queue_cap), int(table_mode), int(wg_per_cu), int(window))
         self._check(self.lib.fire_set_schedule(self.ctx, ctypes.byref(s)))
 
     def set_class_schedule(self, max_cells: int, sched: dict | None):
@@ -286,13 +289,14 @@ class FireGPU:
             self._check(self.lib.fire_set_class_schedule(self.ctx, int(max_cells), None))
             return
         s = Schedule(int(sched["threads"]), int(sched["queue_cap"]), int(sched["table_mode"]),
-                     int(sched["wg_per_cu"]))
+                     int(sched["wg_per_cu"]), int(sched.get("window", -1)))
         self._check(self.lib.fire_set_class_schedule(self.ctx, int(max_cells), ctypes.byref(s)))
 
-    def get_schedule(self, max_cells: int, n_params: int = 1) -> dict:
+    def get_schedule(self, max_cells: int, n_params: int = 1, n_sims: int = 1 << 20) -> dict:
+        """The schedule a batch of n_sims simulations would use."""
         s = Schedule()
         self._check(self.lib.fire_get_schedule(self.ctx, int(max_cells), int(n_params),
-                                               ctypes.byref(s)))
+                                               int(n_sims), ctypes.byref(s)))
         return s.as_dict()
 
     # -- GA, ensemble, scan --------------------------------------------------

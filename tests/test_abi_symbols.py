@@ -58,3 +58,16 @@ def test_nn_library_exports():
     assert sorted(nn.EXPORTS) == declared
     lib = ctypes.CDLL(LIB)
     assert all(hasattr(lib, n) for n in declared)
+
+
+def test_library_has_no_undefined_internal_symbols():
+    """Every symbol of the library's own namespaces is defined in it."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-C", "--undefined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    bad = [l for l in out.splitlines() if "firegpu::" in l or "firenn::" in l]
+    assert not bad, bad
