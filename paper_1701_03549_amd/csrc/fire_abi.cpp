@@ -264,9 +264,11 @@ fire_schedule default_schedule(fire_ctx *c, int64_t max_cells,
       }
     }
     if (per_cu == 0) per_cu = 1;
-    // the resident workgroups share the LDS; queues take what is left (less
-    // what allocation granularity takes, as the runtime reports it)
-    const int res = std::min(per_cu, reg_blocks(c, threads, table, dur, win));
+    // the resident workgroups (no more than the batch fills) share the LDS;
+    // queues take what is left (less a margin the hardware needs)
+    const int64_t need = std::max<int64_t>(1, (n_sims + c->num_cu - 1) / c->num_cu);
+    const int res = (int)std::min<int64_t>(std::min(per_cu, reg_blocks(c, threads, table, dur, win)),
+                                           need);
     int qcap = queue_cap_for(c->max_lds / res - kLdsMargin, bitset_words, dur);
     if (qcap > 16384) qcap = 16384;
     while (qcap > 64 &&
@@ -1255,11 +1257,16 @@ fire_status fire_get_schedule(fire_ctx *c, int64_t max_cells, int32_t n_params,
     return FIRE_OK;
   }
   // the plan of n_sims simulations on a square lattice of max_cells cells
+  // (window re-run statistics: the worst of the loaded landscapes)
   const int side = (int)std::ceil(std::sqrt((double)max_cells));
   const int stride = (side + 31) / 32;
+  harvest_stats(c);
+  float frac = 0.f;
+  for (const auto &L : c->ls)
+    if (L.live) frac = std::max(frac, L.win_frac);
   RunPlan plan;
   fire_status ps = plan_run(c, side * stride, max_cells, side, stride, n_params, n_sims,
-                            n_params <= 8, &plan);
+                            n_params <= 8, &plan, false, frac);
   if (ps != FIRE_OK) return ps;
   *out = plan.s;
   out->window = plan.win;

@@ -334,22 +334,24 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
 
     // -- window: the LDS bitset covers rows [wy0, wy0 + wh) and words
     //    [wx0w, wx0w + ws) of each row, placed around the ignition (the whole
-    //    lattice without a window). A cell that would start burning within
-    //    one cell of a window edge that is not a lattice edge aborts the run,
-    //    which is then repeated without a window: a burning cell's
-    //    neighbours therefore always lie in the window.
+    //    lattice without a window). A burning cell within one cell of a
+    //    window edge that is not a lattice edge aborts the run before its
+    //    neighbours are read (its edges are not tried), and the run is then
+    //    repeated without a window; every neighbour that is read lies in the
+    //    window.
     const int ws = WIN ? min(a.win >> 5, stride) : stride;
     const int wh = WIN ? min(a.win, H) : H;
     const int wx0w = WIN ? min(max((ix >> 5) - ws / 2, 0), stride - ws) : 0;
     const int wy0 = WIN ? min(max(iy - wh / 2, 0), H - wh) : 0;
-    // cells a burning cell may occupy: one cell inside every window edge
-    // that lies inside the lattice
-    const int x_lo = wx0w > 0 ? 32 * wx0w + 1 : INT_MIN;
-    const int x_hi = wx0w + ws < stride ? 32 * (wx0w + ws) - 2 : INT_MAX;
-    const int y_lo = wy0 > 0 ? wy0 + 1 : INT_MIN;
-    const int y_hi = wy0 + wh < H ? wy0 + wh - 2 : INT_MAX;
+    // cells whose edges may be tried: one cell inside every window edge
+    // that lies inside the lattice (x in [x_lo, x_lo + x_span], same for y;
+    // coordinates are below 4096, so the spans of an uncut axis cover all)
+    const int x_lo = wx0w > 0 ? 32 * wx0w + 1 : 0;
+    const uint32_t x_span = (uint32_t)((wx0w + ws < stride ? 32 * (wx0w + ws) - 2 : 8191) - x_lo);
+    const int y_lo = wy0 > 0 ? wy0 + 1 : 0;
+    const uint32_t y_span = (uint32_t)((wy0 + wh < H ? wy0 + wh - 2 : 8191) - y_lo);
     auto near_edge = [&](int x, int y) -> bool {
-      return WIN && (x < x_lo || x > x_hi || y < y_lo || y > y_hi);
+      return WIN && ((uint32_t)(x - x_lo) > x_span || (uint32_t)(y - y_lo) > y_span);
     };
     // LDS word of cell (x, y) inside the window
     const int w_off = wy0 * ws + wx0w;
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       ctl[kLen0 + 0] = 1; ctl[kLen0 + 1] = 0; ctl[kLen0 + 2] = 0;
       ctl[kTrials] = 0; ctl[kNew] = 0; ctl[kInter] = 0;
       ctl[kRowLo] = (uint32_t)iy; ctl[kRowHi] = (uint32_t)iy;
-      ctl[kAbort] = near_edge(ix, iy) ? 1u : 0u;
+      ctl[kAbort] = 0u;
     }
     __syncthreads();
     gmem_cu8 *const bsteps = DUR ? (gmem_cu8 *)L.burn_steps : nullptr;
@@ -405,6 +407,9 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     auto unit_outcome = [&](uint32_t e, uint32_t g, uint32_t &n_tried) -> uint32_t {
       const int x = (int)(e & 0xFFFu), y = (int)((e >> 12) & 0xFFFu);
       const uint32_t s_lin = (uint32_t)(y * W + x);
+      // a source at a window edge: abort, and read none of its neighbours
+      const bool edge = near_edge(x, y);
+      if (WIN && edge) ctl[kAbort] = 1u;
       uint32_t thr[4] = {0u, 0u, 0u, 0u};
       if (TABLE) {
         // the 8 thresholds of a source are 32 contiguous bytes; group g is
@@ -417,7 +422,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       for (int k = 0; k < 4; ++k) {
         const int d = 4 * (int)g + k;
         const int tx = x + dir_dx(d), ty = y + dir_dy(d);
-        const bool inside = (unsigned)tx < (unsigned)W && (unsigned)ty < (unsigned)H;
+        const bool inside = (unsigned)tx < (unsigned)W && (unsigned)ty < (unsigned)H && !edge;
         const int cx = inside ? tx : x, cy = inside ? ty : y;
         const uint32_t word = bits[bw_of(cx, cy)];
         elig |= (inside && ((word >> (cx & 31)) & 1u) == 0) ? (1u << k) : 0u;
@@ -501,7 +506,6 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         ++my_new;
         row_lo = min(row_lo, (uint32_t)ty);
         row_hi = max(row_hi, (uint32_t)ty);
-        if (near_edge(tx, ty)) ctl[kAbort] = 1u;
       }
     };
 
