@@ -224,12 +224,12 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t ballot) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
 }
 
-enum CtlSlot { kSim = 0, kLen0 = 1, kTrials = 4, kNew = 5, kInter = 6, kRowLo = 7, kRowHi = 8,
-               kAbort = 9, kCtlWords = 16 };
+enum CtlSlot { kSim = 0, kLen0 = 1, kTrials = 4, kNew = 5, kInter = 6, kAbort = 7,
+               kCtlWords = 16 };
 
 // register-resident rounds of the small-front step (fronts of up to
 // kRegRounds * BLOCK / 2 cells held in the LDS queue)
-constexpr int kRegRounds = 4;
+constexpr int kRegRounds = 2;
 
 template <int BLOCK, bool TABLE, bool DUR, bool WIN>
 __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
@@ -365,7 +365,6 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     if (tid == 0) {
       ctl[kLen0 + 0] = 1; ctl[kLen0 + 1] = 0; ctl[kLen0 + 2] = 0;
       ctl[kTrials] = 0; ctl[kNew] = 0; ctl[kInter] = 0;
-      ctl[kRowLo] = (uint32_t)iy; ctl[kRowHi] = (uint32_t)iy;
       ctl[kAbort] = 0u;
     }
     __syncthreads();
@@ -392,7 +391,6 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
 
     uint32_t cq = 0, step = 0;
     uint32_t my_trials = 0, my_new = 0;
-    uint32_t row_lo = (uint32_t)iy, row_hi = (uint32_t)iy;
     const uint32_t max_steps = sd.max_steps;
     const uint32_t sim_index = sd.sim_index;
     // frontier length of step k lives in ctl[kLen0 + k % 3]
@@ -504,8 +502,6 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         }
         ++idx;
         ++my_new;
-        row_lo = min(row_lo, (uint32_t)ty);
-        row_hi = max(row_hi, (uint32_t)ty);
       }
     };
 
@@ -610,18 +606,13 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
 
     // -- result: counts, Eq. 2 over the rows the fire reached, map ---------
     if (my_trials) atomicAdd(&ctl[kTrials], my_trials);
-    if (my_new) {
-      atomicAdd(&ctl[kNew], my_new);
-      atomicMin(&ctl[kRowLo], row_lo);
-      atomicMax(&ctl[kRowHi], row_hi);
-    }
+    if (my_new) atomicAdd(&ctl[kNew], my_new);
     __syncthreads();
     if (has_target) {
-      // |A n A*| = popcount(burnt & reference) over the burnt rows
+      // |A n A*| = popcount(burnt & reference) over the bitset
       gmem_cu32 *const ref = (gmem_cu32 *)tg.bits;
-      const int w0 = ((int)ctl[kRowLo] - wy0) * ws, w1 = ((int)ctl[kRowHi] + 1 - wy0) * ws;
       uint32_t inter = 0;
-      for (int w = w0 + tid; w < w1; w += BLOCK) {
+      for (int w = tid; w < wwords; w += BLOCK) {
         const int gw = gw_of(w);
         inter += __popc(bits[w] & ~blocked[gw] & ref[gw]);
       }
