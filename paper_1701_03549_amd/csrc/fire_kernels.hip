@@ -415,15 +415,20 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         const u32x4 t4 = load_x4(table + (int64_t)s_lin * 8 + 4 * g);
         thr[0] = t4.x; thr[1] = t4.y; thr[2] = t4.z; thr[3] = t4.w;
       }
+      // neighbour words from the source's: one row is ws words, and a
+      // column step crosses a word boundary only at bit 0 or 31
+      const int base = bw_of(x, y), xb = x & 31;
       uint32_t elig = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int d = 4 * (int)g + k;
-        const int tx = x + dir_dx(d), ty = y + dir_dy(d);
-        const bool inside = (unsigned)tx < (unsigned)W && (unsigned)ty < (unsigned)H && !edge;
-        const int cx = inside ? tx : x, cy = inside ? ty : y;
-        const uint32_t word = bits[bw_of(cx, cy)];
-        elig |= (inside && ((word >> (cx & 31)) & 1u) == 0) ? (1u << k) : 0u;
+        const int dx = dir_dx(d), dy = dir_dy(d);
+        const bool inside =
+            (unsigned)(x + dx) < (unsigned)W && (unsigned)(y + dy) < (unsigned)H && !edge;
+        const int row = dy < 0 ? -ws : (dy > 0 ? ws : 0);
+        const int w = inside ? base + row + ((xb + dx) >> 5) : base;
+        const int b = inside ? (xb + dx) & 31 : xb;
+        elig |= (inside && ((bits[w] >> b) & 1u) == 0) ? (1u << k) : 0u;
       }
       n_tried = __popc(elig);
       // not gated on elig: the rounds then overlap the bitset and table reads
@@ -457,14 +462,17 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       const int x = (int)(e & 0xFFFu), y = (int)((e >> 12) & 0xFFFu);
       // branch-free: an edge that did not hit ORs 0 into its source's own
       // word, so the four atomics issue back to back
+      const int base = bw_of(x, y), xb = x & 31;
       uint32_t old[4], bitv[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int d = 4 * (int)g + k;
+        const int dx = dir_dx(d), dy = dir_dy(d);
         const bool h = (hit >> k) & 1u;
-        const int tx = h ? x + dir_dx(d) : x, ty = h ? y + dir_dy(d) : y;
-        bitv[k] = h ? 1u << (tx & 31) : 0u;
-        old[k] = atomicOr(&bits[bw_of(tx, ty)], bitv[k]);
+        const int row = dy < 0 ? -ws : (dy > 0 ? ws : 0);
+        const int w = h ? base + row + ((xb + dx) >> 5) : base;
+        bitv[k] = h ? 1u << ((xb + dx) & 31) : 0u;
+        old[k] = atomicOr(&bits[w], bitv[k]);
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k)
