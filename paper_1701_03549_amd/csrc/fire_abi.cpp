@@ -211,6 +211,7 @@ int queue_cap_for(size_t bytes, int bitset_words, bool dur) {
 }
 
 constexpr int kMaxPerCu = 16;  // built-in workgroups per compute unit, at most
+constexpr int64_t kTableBudget = (int64_t)2 << 30;  // bytes of threshold tables per run
 // LDS per workgroup left unused by the built-in queue sizing: with every
 // byte of an equal share taken, gfx950 kept one workgroup fewer resident
 // than the runtime's occupancy figure (measured: 5 x 32.4 KiB ran 4 per CU)
@@ -253,7 +254,11 @@ fire_schedule default_schedule(fire_ctx *c, int64_t max_cells,
                                int64_t n_sims = (int64_t)1 << 30, bool win = false) {
   fire_schedule best{};
   int64_t best_conc = -1;
-  const bool table = n_params <= 8;
+  // a table per parameter vector pays off once each serves a few
+  // simulations (the per-trial Eq. 1 evaluation costs several times a
+  // 4-byte table read), while the tables fit the budget
+  const bool table = n_params <= 8 || (n_sims >= 8 * (int64_t)n_params &&
+                                       (int64_t)n_params * max_cells * 32 <= kTableBudget);
   for (int threads : {1024, 512, 256, 128}) {
     int per_cu = 0;
     for (int k = kMaxPerCu; k >= 1; --k) {
@@ -285,7 +290,6 @@ fire_schedule default_schedule(fire_ctx *c, int64_t max_cells,
     }
   }
   best.window = 0;
-  (void)max_cells;
   return best;
 }
 
@@ -414,7 +418,9 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
   out->s2 = full;
   out->bitset_words2 = bitset_words;
   out->lds2 = lds;
-  out->grid2 = grid;
+  // the re-run launch usually finds nothing to do: one workgroup per CU
+  // keeps its cost small
+  out->grid2 = std::min(grid, c->num_cu);
   out->s = ws;
   out->bitset_words = window_words(win);
   out->lds = wlds;
@@ -890,22 +896,32 @@ static fire_status check_sims_host(fire_ctx *c, const fire_sim *sims, int32_t n,
 
 // Table-mode thresholds: one table per parameter vector into context
 // scratch, computed on the stream right before the simulations.
-static fire_status build_tables(fire_ctx *c, int lid, const double *betas_dev,
-                                int32_t n_params, hipStream_t st,
-                                const uint32_t **tables, int64_t *stride) {
+// Room for n_params threshold tables of landscape lid (waits for the device
+// when it grows).
+static fire_status ensure_tables(fire_ctx *c, int lid, int32_t n_params) {
   const LandscapeHost &L = c->ls[lid];
   const int64_t per = (int64_t)L.W * L.H * 8;
   const size_t need = sizeof(uint32_t) * (size_t)per * n_params;
   if (need > c->tables_words * sizeof(uint32_t)) {
-    HIP_OR_FAIL(c, hipStreamSynchronize(st));
     HIP_OR_FAIL(c, hipDeviceSynchronize());
     size_t have = c->tables_words * sizeof(uint32_t);
     HIP_OR_FAIL(c, ensure((void **)&c->d_tables, &have, need));
     c->tables_words = have / sizeof(uint32_t);
   }
-  for (int32_t p = 0; p < n_params; ++p)
-    HIP_OR_FAIL(c, launch_thresholds(c->d_ls + lid, L.W, L.H, betas_dev + 5 * p,
-                                     L.forest, c->d_tables + per * p, st));
+  return FIRE_OK;
+}
+
+// Table-mode thresholds: one table per parameter vector into context
+// scratch, computed on the stream right before the simulations.
+static fire_status build_tables(fire_ctx *c, int lid, const double *betas_dev,
+                                int32_t n_params, hipStream_t st,
+                                const uint32_t **tables, int64_t *stride) {
+  fire_status es = ensure_tables(c, lid, n_params);
+  if (es != FIRE_OK) return es;
+  const LandscapeHost &L = c->ls[lid];
+  const int64_t per = (int64_t)L.W * L.H * 8;
+  HIP_OR_FAIL(c, launch_thresholds_multi(c->d_ls + lid, L.W, L.H, betas_dev, n_params, L.forest,
+                                         c->d_tables, per, st));
   *tables = c->d_tables;
   *stride = per;
   return FIRE_OK;
@@ -1265,8 +1281,8 @@ fire_status fire_get_schedule(fire_ctx *c, int64_t max_cells, int32_t n_params,
   for (const auto &L : c->ls)
     if (L.live) frac = std::max(frac, L.win_frac);
   RunPlan plan;
-  fire_status ps = plan_run(c, side * stride, max_cells, side, stride, n_params, n_sims,
-                            n_params <= 8, &plan, false, frac);
+  fire_status ps = plan_run(c, side * stride, max_cells, side, stride, n_params, n_sims, true,
+                            &plan, false, frac);
   if (ps != FIRE_OK) return ps;
   *out = plan.s;
   out->window = plan.win;
@@ -1395,9 +1411,17 @@ static fire_status ga_run_graph(fire_ctx *c, int32_t lid, int32_t tid, int32_t i
   // since the parameters change every generation)
   RunPlan plan;
   harvest_stats(c);
-  fire_status ps = plan_run(c, L.H * L.stride, (int64_t)L.W * L.H, L.H, L.stride, P, n, false,
+  fire_status ps = plan_run(c, L.H * L.stride, (int64_t)L.W * L.H, L.H, L.stride, P, n, true,
                             &plan, L.burn_steps != nullptr, L.win_frac);
   if (ps != FIRE_OK) return ps;
+  // table mode: every generation first writes one threshold table per
+  // individual (inside the captured graph)
+  const bool tables = plan.s.table_mode != 0;
+  const int64_t per = (int64_t)L.W * L.H * 8;
+  if (tables) {
+    fire_status ts = ensure_tables(c, lid, P);
+    if (ts != FIRE_OK) return ts;
+  }
   fire_status ss = ensure_spill(c, spill_words(plan));
   if (ss != FIRE_OK) return ss;
   fire_status rs = ensure_retry(c, 1 + (int64_t)n);
@@ -1412,9 +1436,14 @@ static fire_status ga_run_graph(fire_ctx *c, int32_t lid, int32_t tid, int32_t i
   if (e == hipSuccess) e = launch_ga_prepare(d_gen, d_sims, P, R, c->d_work, d_pop, G, hist_pop, cap);
   if (e == hipSuccess && ign_genes)
     e = launch_sims_from_pop(d_pop, P, G, R, lid, tid, L.W, L.H, 0u, d_gen, d_sims, d_beta, cap);
+  const double *betas = ign_genes ? d_beta : d_pop;
+  if (e == hipSuccess && tables)
+    e = launch_thresholds_multi(c->d_ls + lid, L.W, L.H, betas, P, L.forest, c->d_tables, per,
+                                cap);
   if (e == hipSuccess &&
-      launch_run(c, plan, ign_genes ? d_beta : d_pop, P, d_sims, nullptr, n, sim_seed, nullptr, 0,
-                 -1, d_res, nullptr, 0, 0, c->d_ovf, c->d_retry, cap) != FIRE_OK)
+      launch_run(c, plan, betas, P, d_sims, nullptr, n, sim_seed, tables ? c->d_tables : nullptr,
+                 tables ? per : 0, tables ? lid : -1, d_res, nullptr, 0, 0, c->d_ovf, c->d_retry,
+                 cap) != FIRE_OK)
     e = hipErrorLaunchFailure;
   if (e == hipSuccess) e = launch_ga_gather(d_gen, d_res, P, R, d_fit, hist_fit, cap);
   if (e == hipSuccess)

@@ -71,6 +71,11 @@ hipError_t launch_preprocess(const uint8_t *veg, const float *elev,
 hipError_t launch_thresholds(const LandscapeDev *ls_dev_entry, int W, int H,
                              const double *beta_dev, uint32_t forest,
                              uint32_t *out, hipStream_t s);
+// one table per parameter vector (betas_dev [n_params][5]), table p at
+// out + p * out_stride
+hipError_t launch_thresholds_multi(const LandscapeDev *ls_dev_entry, int W, int H,
+                                   const double *betas_dev, int n_params, uint32_t forest,
+                                   uint32_t *out, int64_t out_stride, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_sim(const SimArgs &a, int threads, bool table, bool dur, int grid,
                       size_t lds_bytes, hipStream_t s);

@@ -130,11 +130,13 @@ __global__ void preprocess_kernel(const uint8_t *veg, const float *elev,
 // One thread per source cell writes its 8 thresholds (two 16-byte stores).
 __global__ void thresholds_kernel(const LandscapeDev *lsd, int W, int H,
                                   const double *beta_dev, uint32_t forest,
-                                  uint32_t *out) {
+                                  uint32_t *out_base, int64_t out_stride) {
+  // parameter vector blockIdx.y, its table at out_base + blockIdx.y * out_stride
   const LandscapeDev L = *lsd;
   double beta[5];
 #pragma unroll
-  for (int i = 0; i < 5; ++i) beta[i] = beta_dev[i];
+  for (int i = 0; i < 5; ++i) beta[i] = beta_dev[5 * (int64_t)blockIdx.y + i];
+  uint32_t *const out = out_base + (int64_t)blockIdx.y * out_stride;
   const int64_t n = (int64_t)W * H;
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * blockDim.x) {
@@ -439,17 +441,16 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         for (int k = 0; k < 4; ++k)
           if (((elig >> k) & 1u) && (thr[k] == kSaturated || r.v[k] < thr[k])) hit |= 1u << k;
       } else {
-        // one Eq. 1 evaluation at a time keeps the binary64 temporaries of
-        // a single edge live
-#pragma unroll 1
+        // the four Eq. 1 evaluations are independent: evaluated together
+        // (ineligible edges read their source's own record) they overlap
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
-          if (!((elig >> k) & 1u)) continue;
           const int d = 4 * (int)g + k;
-          const int64_t tl = (int64_t)(y + dir_dy(d)) * W + (x + dir_dx(d));
+          const bool el = (elig >> k) & 1u;
+          const int64_t tl = el ? (int64_t)(y + dir_dy(d)) * W + (x + dir_dx(d)) : (int64_t)s_lin;
           const uint32_t t = edge_threshold(beta, load_rec(L.rec, tl), ((gmem_cf64 *)L.psi)[tl],
                                             d, L.forest_class);
-          const uint32_t coin = k == 0 ? r.v[0] : k == 1 ? r.v[1] : k == 2 ? r.v[2] : r.v[3];
-          if (t == kSaturated || coin < t) hit |= 1u << k;
+          if (el && (t == kSaturated || r.v[k] < t)) hit |= 1u << k;
         }
       }
       return hit;
@@ -1076,9 +1077,15 @@ hipError_t launch_preprocess(const uint8_t *veg, const float *elev,
 hipError_t launch_thresholds(const LandscapeDev *ls_dev_entry, int W, int H,
                              const double *beta_dev, uint32_t forest,
                              uint32_t *out, hipStream_t s) {
+  return launch_thresholds_multi(ls_dev_entry, W, H, beta_dev, 1, forest, out, 0, s);
+}
+
+hipError_t launch_thresholds_multi(const LandscapeDev *ls_dev_entry, int W, int H,
+                                   const double *betas_dev, int n_params, uint32_t forest,
+                                   uint32_t *out, int64_t out_stride, hipStream_t s) {
   const int64_t n = (int64_t)W * H;
-  hipLaunchKernelGGL(thresholds_kernel, dim3(grid_for(n, 256)), dim3(256), 0,
-                     s, ls_dev_entry, W, H, beta_dev, forest, out);
+  hipLaunchKernelGGL(thresholds_kernel, dim3(grid_for(n, 256), n_params), dim3(256), 0, s,
+                     ls_dev_entry, W, H, betas_dev, forest, out, out_stride);
   return hipGetLastError();
 }
 
