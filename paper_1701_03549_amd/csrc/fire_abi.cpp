@@ -220,12 +220,15 @@ constexpr size_t kLdsMargin = 1024;
 int threads_index(int t) { return t == 64 ? 0 : t == 128 ? 1 : t == 256 ? 2 : t == 512 ? 3 : 4; }
 
 // Workgroups of a simulation-kernel variant resident per CU as far as its
-// registers allow (queried once per variant; LDS is accounted separately).
+// registers allow (queried once per variant; LDS is accounted separately),
+// negated for a variant whose registers spill to scratch.
 int reg_blocks(fire_ctx *c, int threads, bool table, bool dur, bool win) {
   int &v = c->reg_blocks[threads_index(threads)][table ? 1 : 0][dur ? 1 : 0][win ? 1 : 0];
   if (v == 0) {
     v = sim_occupancy(threads, table, dur, win, 0);
     if (v <= 0) v = 1;
+    // a variant that spills registers to scratch is not a built-in choice
+    if (sim_scratch_bytes(threads, table, dur, win) > 0) v = -v;
   }
   return v;
 }
@@ -272,8 +275,9 @@ fire_schedule default_schedule(fire_ctx *c, int64_t max_cells,
     // the resident workgroups (no more than the batch fills) share the LDS;
     // queues take what is left (less a margin the hardware needs)
     const int64_t need = std::max<int64_t>(1, (n_sims + c->num_cu - 1) / c->num_cu);
-    const int res = (int)std::min<int64_t>(std::min(per_cu, reg_blocks(c, threads, table, dur, win)),
-                                           need);
+    const int rb = reg_blocks(c, threads, table, dur, win);
+    if (rb < 0 && threads > 128) continue;  // spills; 128 threads is the fallback
+    const int res = (int)std::min<int64_t>(std::min(per_cu, rb < 0 ? -rb : rb), need);
     int qcap = queue_cap_for(c->max_lds / res - kLdsMargin, bitset_words, dur);
     if (qcap > 16384) qcap = 16384;
     while (qcap > 64 &&

@@ -83,6 +83,8 @@ hipError_t set_sim_lds_limit(size_t bytes);
 // workgroups of the simulation kernel resident per compute unit for this
 // launch shape (registers and LDS), 0 if unknown
 int sim_occupancy(int threads, bool table, bool dur, bool win, size_t lds_bytes);
+// per-lane scratch (register spills) of a simulation-kernel variant, bytes
+size_t sim_scratch_bytes(int threads, bool table, bool dur, bool win);
 // per-cell (paper-style) ablation path
 hipError_t launch_dense_init(uint8_t *st, const LandscapeDev &L, int ix, int iy,
                              unsigned long long *counts, hipStream_t s);

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <type_traits>
 #include <math.h>
 #include <stdint.h>
 
@@ -404,7 +405,11 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     // inside, burnable and unburnt at the start of the step. Returns the
     // 4-bit mask of tried edges whose coin succeeds; n_tried counts the
     // tried edges.
-    auto unit_outcome = [&](uint32_t e, uint32_t g, uint32_t &n_tried) -> uint32_t {
+    // `overlap` (per-trial thresholds only): evaluate the four edges'
+    // Eq. 1 together, eligible or not, which shortens the step on small
+    // fronts; large fronts evaluate only the eligible edges, one at a time.
+    auto unit_outcome = [&](auto overlap, uint32_t e, uint32_t g,
+                            uint32_t &n_tried) -> uint32_t {
       const int x = (int)(e & 0xFFFu), y = (int)((e >> 12) & 0xFFFu);
       const uint32_t s_lin = (uint32_t)(y * W + x);
       // a source at a window edge: abort, and read none of its neighbours
@@ -440,7 +445,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
           if (((elig >> k) & 1u) && (thr[k] == kSaturated || r.v[k] < thr[k])) hit |= 1u << k;
-      } else {
+      } else if (decltype(overlap)::value) {
         // the four Eq. 1 evaluations are independent: evaluated together
         // (ineligible edges read their source's own record) they overlap
 #pragma unroll
@@ -451,6 +456,17 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
           const uint32_t t = edge_threshold(beta, load_rec(L.rec, tl), ((gmem_cf64 *)L.psi)[tl],
                                             d, L.forest_class);
           if (el && (t == kSaturated || r.v[k] < t)) hit |= 1u << k;
+        }
+      } else {
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+          if (!((elig >> k) & 1u)) continue;
+          const int d = 4 * (int)g + k;
+          const int64_t tl = (int64_t)(y + dir_dy(d)) * W + (x + dir_dx(d));
+          const uint32_t t = edge_threshold(beta, load_rec(L.rec, tl), ((gmem_cf64 *)L.psi)[tl],
+                                            d, L.forest_class);
+          const uint32_t coin = k == 0 ? r.v[0] : k == 1 ? r.v[1] : k == 2 ? r.v[2] : r.v[3];
+          if (t == kSaturated || coin < t) hit |= 1u << k;
         }
       }
       return hit;
@@ -538,7 +554,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
             const uint32_t e = rr == 0 ? e_first : lds[bw + cq * cap + (j >> 1)];
             ent[rr] = e;
             uint32_t nt;
-            hit[rr] = unit_outcome(e, j & 1u, nt);
+            hit[rr] = unit_outcome(std::true_type{}, e, j & 1u, nt);
             my_trials += nt;
           }
         }
@@ -557,7 +573,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         for (uint32_t j = tid; j < n_units; j += BLOCK) {
           const uint32_t e = q_load(cq, j >> 1);
           uint32_t nt;
-          const uint32_t m = unit_outcome(e, j & 1u, nt);
+          const uint32_t m = unit_outcome(std::false_type{}, e, j & 1u, nt);
           my_trials += nt;
           const uint32_t other = (uint32_t)__shfl_xor((int)m, 1);
           const uint32_t m8 = (j & 1u) ? 0u : (m | (other << 4));
@@ -1162,6 +1178,37 @@ static int occupancy_block(bool table, bool dur, bool win, size_t lds) {
                         : occupancy_one<BLOCK, false, true>(lds, win);
   return table ? occupancy_one<BLOCK, true, false>(lds, win)
                : occupancy_one<BLOCK, false, false>(lds, win);
+}
+
+template <int BLOCK, bool TABLE, bool DUR>
+static size_t scratch_one(bool win) {
+  hipFuncAttributes at{};
+  hipError_t e = win ? hipFuncGetAttributes(
+                           &at, reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, true>))
+                     : hipFuncGetAttributes(
+                           &at, reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, false>));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return at.localSizeBytes;
+}
+
+template <int BLOCK>
+static size_t scratch_block(bool table, bool dur, bool win) {
+  if (dur) return table ? scratch_one<BLOCK, true, true>(win) : scratch_one<BLOCK, false, true>(win);
+  return table ? scratch_one<BLOCK, true, false>(win) : scratch_one<BLOCK, false, false>(win);
+}
+
+size_t sim_scratch_bytes(int threads, bool table, bool dur, bool win) {
+  switch (threads) {
+    case 64: return scratch_block<64>(table, dur, win);
+    case 128: return scratch_block<128>(table, dur, win);
+    case 256: return scratch_block<256>(table, dur, win);
+    case 512: return scratch_block<512>(table, dur, win);
+    case 1024: return scratch_block<1024>(table, dur, win);
+    default: return 0;
+  }
 }
 
 int sim_occupancy(int threads, bool table, bool dur, bool win, size_t lds_bytes) {
