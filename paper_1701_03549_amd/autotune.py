@@ -37,10 +37,17 @@ def cells_bucket(cells: int) -> int:
     return b
 
 
-def candidates(table_ok: bool):
-    for threads, wg, qcap in itertools.product((128, 256, 512, 1024), (1, 2, 4, 8), (1024, 4096)):
+def candidates(table_ok: bool, side: int = 0):
+    """Schedules to time: workgroup size x workgroups per CU x LDS queue
+    capacity x threshold mode x LDS window (none, or a quarter, half and
+    three quarters of the lattice side, when that is at least 64 cells)."""
+    windows = [0] + sorted({w for w in (side // 4, side // 2, 3 * side // 4)
+                            if w >= 64 and w % 32 == 0 and w < side})
+    for threads, wg, qcap, win in itertools.product((128, 256, 512, 1024), (1, 2, 4, 5, 8),
+                                                    (1024, 4096), windows):
         for table in ((0, 1) if table_ok else (0,)):
-            yield {"threads": threads, "queue_cap": qcap, "table_mode": table, "wg_per_cu": wg}
+            yield {"threads": threads, "queue_cap": qcap, "table_mode": table, "wg_per_cu": wg,
+                   "window": win}
 
 
 def time_schedule(g: fire.FireGPU, sched, d_beta, d_sims, n, seed, out, reps=3):
@@ -67,7 +74,8 @@ def tune(g: fire.FireGPU, lid: int, sims: np.ndarray, betas: np.ndarray, seed: i
     out = torch.empty((n, 24), dtype=torch.uint8, device=g.device)
     ref = None
     rows = []
-    for sched in candidates(table_ok=len(betas) <= 8):
+    side = max(g.dims[lid])
+    for sched in candidates(table_ok=len(betas) <= 8, side=side):
         try:
             ms = time_schedule(g, sched, d_beta, d_sims, n, seed, out)
         except fire.FireError as e:  # LDS budget exceeded for this shape
