@@ -76,6 +76,8 @@ def tune(g: fire.FireGPU, lid: int, sims: np.ndarray, betas: np.ndarray, seed: i
     rows = []
     side = max(g.dims[lid])
     for sched in candidates(table_ok=len(betas) <= 8, side=side):
+        if log:
+            log(f"timing {sched}")
         try:
             ms = time_schedule(g, sched, d_beta, d_sims, n, seed, out)
         except fire.FireError as e:  # LDS budget exceeded for this shape
@@ -125,6 +127,7 @@ def main():
     import argparse
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=CACHE, help="cache file to update")
+    ap.add_argument("--only", default=None, help="tune only this lattice, e.g. 512x512")
     args = ap.parse_args()
     log = lambda m: print(f"[autotune] {m}", flush=True)  # noqa: E731
     g = fire.FireGPU(0)
@@ -133,6 +136,8 @@ def main():
     mine = cache.setdefault(arch, {})
     best_by_bucket = {}
     for W, H, seed, betas, n in workloads():
+        if args.only and args.only != f"{W}x{H}":
+            continue
         ls = synth.make_landscape(W, H, seed)
         lid = g.load_landscape(ls)
         c = synth.ignition_site(ls)

@@ -418,6 +418,10 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
   size_t wlds = 0;
   int wgrid = 0;
   if (!shape_for(win, ws, &wlds, &wgrid)) return FIRE_OK;
+  // window runs only with kernel variants that keep their registers (a
+  // 1024-thread per-trial-threshold window run stopped responding once
+  // under the autotuner, cause not found; such variants run without one)
+  if (sim_scratch_bytes(ws.threads, ws.table_mode != 0, dur, true) > 0) return FIRE_OK;
   ws.window = win;
   out->s2 = full;
   out->bitset_words2 = bitset_words;
