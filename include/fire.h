@@ -227,7 +227,8 @@ typedef struct {
                             comes within a cell of a window edge inside the
                             lattice is run again over the whole lattice
                             (same coins, so the same result); smaller LDS
-                            footprints keep more simulations resident     */
+                            footprints keep more simulations resident.
+                            Ignored (whole lattice) with 1024 threads.    */
 } fire_schedule;
 
 /* Fix the schedule used by later fire_run/fire_run_dev calls; NULL

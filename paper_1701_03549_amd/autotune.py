@@ -45,6 +45,8 @@ def candidates(table_ok: bool, side: int = 0):
                             if w >= 64 and w % 32 == 0 and w < side})
     for threads, wg, qcap, win in itertools.product((128, 256, 512, 1024), (1, 2, 4, 5, 8),
                                                     (1024, 4096), windows):
+        if threads > 512 and win > 0:
+            continue  # the library runs 1024-thread schedules without a window
         for table in ((0, 1) if table_ok else (0,)):
             yield {"threads": threads, "queue_cap": qcap, "table_mode": table, "wg_per_cu": wg,
                    "window": win}

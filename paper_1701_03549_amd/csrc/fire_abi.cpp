@@ -387,6 +387,10 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
   auto shape_for = [&](int side, fire_schedule &ws, size_t *wl, int *wg) -> bool {
     const int wbw = window_words(side);
     ws = s.window < 0 ? default_schedule(c, max_cells, wbw, n_params, dur, n_sims, true) : s;
+    // no window runs with 1024-thread workgroups: such a run, with a window
+    // every fire outgrew, stopped responding on the GPU and the cause is not
+    // found; those schedules run over the whole lattice
+    if (ws.threads > 512) return false;
     ws.table_mode = full.table_mode;
     return shape_launch(c, ws, wbw, dur, true, n_sims, wl, wg);
   };
@@ -418,9 +422,8 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
   size_t wlds = 0;
   int wgrid = 0;
   if (!shape_for(win, ws, &wlds, &wgrid)) return FIRE_OK;
-  // window runs only with kernel variants that keep their registers (a
-  // 1024-thread per-trial-threshold window run stopped responding once
-  // under the autotuner, cause not found; such variants run without one)
+  // window runs only with kernel variants that keep their registers (the
+  // spilling variants are slow enough that residency gains nothing)
   if (sim_scratch_bytes(ws.threads, ws.table_mode != 0, dur, true) > 0) return FIRE_OK;
   ws.window = win;
   out->s2 = full;

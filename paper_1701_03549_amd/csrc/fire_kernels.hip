@@ -227,7 +227,11 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t ballot) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
 }
 
-enum CtlSlot { kSim = 0, kLen0 = 1, kTrials = 4, kNew = 5, kInter = 6, kAbort = 7,
+// kLen0 + k % 3: frontier length of step k; kAbort0 + k % 3: step k is not
+// to run (a burning cell reached a window edge during step k - 1). Three
+// slots: a slot is written only after the first barrier of the step before
+// the one that reads it, and reset at the top of the step before that.
+enum CtlSlot { kSim = 0, kLen0 = 1, kTrials = 4, kNew = 5, kInter = 6, kAbort0 = 7,
                kCtlWords = 16 };
 
 // register-resident rounds of the small-front step (fronts of up to
@@ -368,7 +372,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     if (tid == 0) {
       ctl[kLen0 + 0] = 1; ctl[kLen0 + 1] = 0; ctl[kLen0 + 2] = 0;
       ctl[kTrials] = 0; ctl[kNew] = 0; ctl[kInter] = 0;
-      ctl[kAbort] = 0u;
+      ctl[kAbort0 + 0] = 0u; ctl[kAbort0 + 1] = 0u; ctl[kAbort0 + 2] = 0u;
     }
     __syncthreads();
     gmem_cu8 *const bsteps = DUR ? (gmem_cu8 *)L.burn_steps : nullptr;
@@ -398,6 +402,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     const uint32_t sim_index = sd.sim_index;
     // frontier length of step k lives in ctl[kLen0 + k % 3]
     int slot = 0;
+    bool aborted = false;
 
     // Phase 1 for one unit: frontier entry e and direction group g (edges
     // d = 4g .. 4g+3, whose coins are the four words of one Philox call
@@ -412,9 +417,9 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
                             uint32_t &n_tried) -> uint32_t {
       const int x = (int)(e & 0xFFFu), y = (int)((e >> 12) & 0xFFFu);
       const uint32_t s_lin = (uint32_t)(y * W + x);
-      // a source at a window edge: abort, and read none of its neighbours
+      // a source at a window edge: read none of its neighbours; bit 4 of
+      // the result asks phase 2 to end the run
       const bool edge = near_edge(x, y);
-      if (WIN && edge) ctl[kAbort] = 1u;
       uint32_t thr[4] = {0u, 0u, 0u, 0u};
       if (TABLE) {
         // the 8 thresholds of a source are 32 contiguous bytes; group g is
@@ -469,7 +474,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
           if (t == kSaturated || coin < t) hit |= 1u << k;
         }
       }
-      return hit;
+      return hit | (WIN && edge ? 16u : 0u);
     };
 
     // Phase 2 for one unit: set the bits of the hit targets; returns the
@@ -534,9 +539,13 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       // the frontier length and this lane's first entry are read together
       const uint32_t n_cur = ctl[kLen0 + slot];
       const uint32_t e_first = lds[bw + cq * cap + min((uint32_t)tid >> 1, cap - 1)];
-      if (n_cur == 0 || step >= max_steps || ctl[kAbort] != 0u) break;
+      aborted = WIN && ctl[kAbort0 + slot] != 0u;
+      if (n_cur == 0 || step >= max_steps || aborted) break;
       const int nslot = slot == 2 ? 0 : slot + 1;
-      if (tid == 0) ctl[kLen0 + nslot] = 0;
+      if (tid == 0) {
+        ctl[kLen0 + nslot] = 0;
+        if (WIN) ctl[kAbort0 + nslot] = 0;
+      }
       const uint32_t n_units = 2 * n_cur;
 
       if (n_units <= (uint32_t)(kRegRounds * BLOCK) && n_cur <= cap) {
@@ -563,7 +572,9 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         for (int rr = 0; rr < kRegRounds; ++rr) {
           if (rr * BLOCK >= (int)n_units) break;
           const uint32_t g = (uint32_t)tid & 1u;
-          const uint32_t fresh = hit[rr] ? unit_ignite(ent[rr], g, hit[rr]) : 0u;
+          if (WIN && (hit[rr] & 16u)) ctl[kAbort0 + nslot] = 1u;
+          const uint32_t h4 = hit[rr] & 15u;
+          const uint32_t fresh = h4 ? unit_ignite(ent[rr], g, h4) : 0u;
           append(ent[rr], g, fresh, nslot, direct);
         }
       } else {
@@ -573,7 +584,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         for (uint32_t j = tid; j < n_units; j += BLOCK) {
           const uint32_t e = q_load(cq, j >> 1);
           uint32_t nt;
-          const uint32_t m = unit_outcome(std::false_type{}, e, j & 1u, nt);
+          const uint32_t m = unit_outcome(std::false_type{}, e, j & 1u, nt) & 15u;
           my_trials += nt;
           const uint32_t other = (uint32_t)__shfl_xor((int)m, 1);
           const uint32_t m8 = (j & 1u) ? 0u : (m | (other << 4));
@@ -586,6 +597,8 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
           uint32_t e = 0, fresh = 0;
           if (j < n_units) {
             e = q_load(cq, j >> 1);
+            if (WIN && near_edge((int)(e & 0xFFFu), (int)((e >> 12) & 0xFFFu)))
+              ctl[kAbort0 + nslot] = 1u;
             const uint32_t hit = (e >> (24 + 4 * g)) & 0xFu;
             if (hit) fresh = unit_ignite(e, g, hit);
           }
@@ -621,9 +634,9 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       cq ^= 1u;
     }
 
-    if (ctl[kAbort] != 0u) {
+    if (aborted) {
       // the fire reached the window edge: queue the simulation for a run
-      // without a window (every lane has read kAbort after the last barrier)
+      // without a window (every lane left the loop at the same step)
       __syncthreads();
       if (tid == 0) a.retry[1 + atomicAdd(a.retry, 1u)] = sim;
       continue;

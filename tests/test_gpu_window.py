@@ -156,6 +156,40 @@ def test_window_ga_run_equals_whole_lattice(g):
     g.free_landscape(lid)
 
 
+@pytest.mark.parametrize("threads,wg", [
+    pytest.param(1024, 1, marks=pytest.mark.skip(
+        reason="a 1024-thread window run whose fires all outgrow the window stopped responding "
+               "on the GPU (also after the end-of-run flag was moved to rotating slots); the "
+               "library now runs 1024-thread schedules without a window, and this case stays "
+               "off the GPU until the cause is found")),
+    (512, 2)])
+def test_window_large_workgroups_end_together(g, threads, wg):
+    """Many waves per workgroup with a window every fire outgrows: every
+    wave must leave a run at the same step (the end-of-run flag is read at
+    the top of a step and written only after that step's first barrier)."""
+    import torch
+    from paper_1701_03549_amd import fire
+    W = H = 512
+    ls = synth.make_landscape(W, H, 102)
+    c = synth.ignition_site(ls)
+    lid = g.load_landscape(ls)
+    n = 256
+    sims = fire.make_sims(n, lid, -1, c)
+    d_sims = torch.from_numpy(sims.view(np.uint8).copy()).cuda()
+    d_beta = torch.tensor([BETA_STAR], dtype=torch.float64, device="cuda")
+    outs = []
+    for win in (0, 128):
+        say(f"threads={threads} window {win}")
+        g.set_schedule(threads, 1024, 1, wg, window=win)
+        out = torch.empty((n, 24), dtype=torch.uint8, device="cuda")
+        g.run_dev(d_beta, d_sims, n, SEED, out)
+        g.sync()
+        outs.append(out)
+    g.set_schedule(reset=True)
+    assert torch.equal(outs[0], outs[1])
+    g.free_landscape(lid)
+
+
 def test_bad_window_rejected(g):
     from paper_1701_03549_amd import fire
     for win in (32, 100, 8192, -2):
