@@ -492,27 +492,20 @@ void harvest_stats(fire_ctx *c) {
   }
 }
 
-// Copy a window launch's retry count back without waiting (not under
-// stream capture; skipped when every slot is still in flight).
-void record_stat(fire_ctx *c, const uint32_t *retry, int lid, int32_t n, hipStream_t st) {
+// A free statistics slot for a window launch's retry count (not under
+// stream capture; -1 when every slot is still in flight). The re-run launch
+// writes the count into the slot's host-mapped word and an event recorded
+// after it tells when the word is final.
+int stat_slot(fire_ctx *c, hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
     (void)hipGetLastError();
-    return;
+    return -1;
   }
   harvest_stats(c);
-  for (int i = 0; i < fire_ctx::kStatSlots; ++i) {
-    if (c->stat_ls[i] >= 0) continue;
-    if (hipMemcpyAsync(c->h_stat + i, retry, sizeof(uint32_t), hipMemcpyDeviceToHost, st) !=
-            hipSuccess ||
-        hipEventRecord(c->stat_ev[i], st) != hipSuccess) {
-      (void)hipGetLastError();
-      return;
-    }
-    c->stat_ls[i] = lid;
-    c->stat_n[i] = n;
-    return;
-  }
+  for (int i = 0; i < fire_ctx::kStatSlots; ++i)
+    if (c->stat_ls[i] < 0) return i;
+  return -1;
 }
 
 // One persistent launch over n_sims descriptors (or over `order`, a list of
@@ -539,7 +532,7 @@ SimArgs sim_args(fire_ctx *c, const double *betas_dev, int32_t n_params,
   a.ovf = spill; a.ovf_cap = ovf_cap;
   a.ovf_life = dur ? reinterpret_cast<uint8_t *>(spill + (int64_t)grid * 2 * ovf_cap) : nullptr;
   a.queue_cap = queue_cap; a.bitset_words = bitset_words;
-  a.win = 0; a.retry = nullptr; a.n_dev = nullptr;
+  a.win = 0; a.retry = nullptr; a.n_dev = nullptr; a.stat_out = nullptr;
   return a;
 }
 
@@ -553,23 +546,31 @@ fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
   SimArgs a = sim_args(c, betas_dev, n_params, sims_dev, order, n_sims, seed, tables,
                        table_stride, table_ls, out, out_maps, map_words, p.max_cells,
                        p.s.queue_cap, p.grid, p.dur, p.bitset_words, c->d_work + counter, spill);
+  if (p.win > 0 && !retry) return fail(c, FIRE_E_INVALID, "window plan without a retry list");
+  uint32_t *const work2 = p.win > 0 ? c->d_work + counter + kMaxClasses : nullptr;
+  // the launches' work counters and the retry count, in one launch
+  HIP_OR_FAIL(c, launch_zero_words(a.work, work2, p.win > 0 ? retry : nullptr, st));
   if (p.win > 0) {
-    if (!retry) return fail(c, FIRE_E_INVALID, "window plan without a retry list");
     a.win = p.win;
     a.retry = retry;
-    HIP_OR_FAIL(c, launch_fill_u32(retry, 0u, 1, st));
   }
-  HIP_OR_FAIL(c, launch_fill_u32(a.work, 0u, 1, st));
   HIP_OR_FAIL(c, launch_sim(a, p.s.threads, tables != nullptr, p.dur, p.grid, p.lds, st));
-  if (p.win > 0 && stat_lid >= 0) record_stat(c, retry, stat_lid, n_sims, st);
   if (p.win > 0) {
     SimArgs b = sim_args(c, betas_dev, n_params, sims_dev, retry + 1, n_sims, seed, tables,
                          table_stride, table_ls, out, out_maps, map_words, p.max_cells,
-                         p.s2.queue_cap, p.grid2, p.dur, p.bitset_words2,
-                         c->d_work + counter + kMaxClasses, spill);
+                         p.s2.queue_cap, p.grid2, p.dur, p.bitset_words2, work2, spill);
     b.n_dev = retry;
-    HIP_OR_FAIL(c, launch_fill_u32(b.work, 0u, 1, st));
+    const int slot = stat_lid >= 0 ? stat_slot(c, st) : -1;
+    if (slot >= 0) b.stat_out = c->h_stat + slot;
     HIP_OR_FAIL(c, launch_sim(b, p.s2.threads, tables != nullptr, p.dur, p.grid2, p.lds2, st));
+    if (slot >= 0) {
+      if (hipEventRecord(c->stat_ev[slot], st) == hipSuccess) {
+        c->stat_ls[slot] = stat_lid;
+        c->stat_n[slot] = n_sims;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
   }
   return FIRE_OK;
 }

@@ -60,6 +60,7 @@ struct SimArgs {
   uint32_t *retry;         // window runs: [0] count, [1..] simulations whose
                            // fire reached the window edge
   const uint32_t *n_dev;   // NULL, or the device count of simulations (else n_sims)
+  uint32_t *stat_out;      // NULL, or a host-mapped word that receives *n_dev
 };
 
 // Launchers (fire_kernels.hip). Each returns the hipError_t of its launch.
@@ -77,6 +78,7 @@ hipError_t launch_thresholds_multi(const LandscapeDev *ls_dev_entry, int W, int 
                                    const double *betas_dev, int n_params, uint32_t forest,
                                    uint32_t *out, int64_t out_stride, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_zero_words(uint32_t *p0, uint32_t *p1, uint32_t *p2, hipStream_t s);
 hipError_t launch_sim(const SimArgs &a, int threads, bool table, bool dur, int grid,
                       size_t lds_bytes, hipStream_t s);
 hipError_t set_sim_lds_limit(size_t bytes);

@@ -159,6 +159,15 @@ __global__ void thresholds_kernel(const LandscapeDev *lsd, int W, int H,
   }
 }
 
+// Zero up to three counters in one launch (NULL entries are skipped).
+__global__ void zero_words_kernel(uint32_t *p0, uint32_t *p1, uint32_t *p2) {
+  if (threadIdx.x == 0) {
+    if (p0) *p0 = 0u;
+    if (p1) *p1 = 0u;
+    if (p2) *p2 = 0u;
+  }
+}
+
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -270,6 +279,10 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     if (i < cap) lds[bw + q * cap + i] = v;
     else spill_base[(int64_t)q * a.ovf_cap + (i - cap)] = v;
   };
+
+  // the count of simulations this launch runs, for the host's statistics
+  if (a.stat_out != nullptr && a.n_dev != nullptr && blockIdx.x == 0 && tid == 0)
+    *a.stat_out = *a.n_dev;
 
   for (;;) {
     if (tid == 0) {
@@ -1140,6 +1153,11 @@ hipError_t launch_dense_result(const uint8_t *st, const LandscapeDev &L, const u
                                uint32_t *map, hipStream_t s) {
   hipLaunchKernelGGL(dense_result_kernel, dim3(1), dim3(kDenseResThreads), 0, s, st, L, ref, n_ref,
                      has_target ? 1 : 0, steps, counts, out, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_words(uint32_t *p0, uint32_t *p1, uint32_t *p2, hipStream_t s) {
+  hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, p0, p1, p2);
   return hipGetLastError();
 }
 

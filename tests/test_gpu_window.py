@@ -190,6 +190,48 @@ def test_window_large_workgroups_end_together(g, threads, wg):
     g.free_landscape(lid)
 
 
+def test_auto_window_turns_off_after_repeats():
+    """The built-in plan gives a 512x512 batch an LDS window; when the fires
+    outgrow it (every simulation is run again), the re-run count reported by
+    the second launch turns windows off for that landscape, and results
+    equal whole-lattice runs throughout."""
+    import torch
+    from paper_1701_03549_amd import fire
+    W = H = 512
+    n = 1280
+    ctx = fire.FireGPU(0)
+    try:
+        ls = synth.make_landscape(W, H, 102)
+        c = synth.ignition_site(ls)
+        lid = ctx.load_landscape(ls)
+        sims = fire.make_sims(n, lid, -1, c)
+        d_sims = torch.from_numpy(sims.view(np.uint8).copy()).cuda()
+        # a large intercept: fires reach the whole burnable lattice
+        d_beta = torch.tensor([[6.0, 0.0, 0.0, 0.0, 0.0]], dtype=torch.float64, device="cuda")
+        before = ctx.get_schedule(W * H, 1, n)
+        assert before["window"] > 0
+        outs = []
+        for label in ("auto, window", "auto, after repeats"):
+            say(f"512x512 {label}")
+            out = torch.empty((n, 24), dtype=torch.uint8, device="cuda")
+            ctx.run_dev(d_beta, d_sims, n, SEED, out)
+            ctx.sync()
+            outs.append(out)
+        assert ctx.get_schedule(W * H, 1, n)["window"] == 0
+        say("512x512 whole lattice")
+        ctx.set_schedule(before["threads"], before["queue_cap"], before["table_mode"],
+                         before["wg_per_cu"], window=0)
+        out = torch.empty((n, 24), dtype=torch.uint8, device="cuda")
+        ctx.run_dev(d_beta, d_sims, n, SEED, out)
+        ctx.sync()
+        for o in outs:
+            assert torch.equal(o, out)
+        r = fire.results_to_numpy(out)
+        assert r["burnt"].min() > W * H // 4
+    finally:
+        ctx.close()
+
+
 def test_bad_window_rejected(g):
     from paper_1701_03549_amd import fire
     for win in (32, 100, 8192, -2):
