@@ -74,7 +74,8 @@ fire_status fire_nn_set_params(fire_nn *nn, const float *in, void *stream);
 
 /* Forward pass for B <= max_batch candidates. x: [B][7] fp32 raw inputs
  * (beta[5], ignition x, y in cells); out_t: [B] fp32 predicted log(1+delta);
- * out_map: NULL or [B][128][128] fp32 burn probabilities. */
+ * out_map: NULL (the decoder is then not run) or [B][128][128] fp32 burn
+ * probabilities. */
 fire_status fire_nn_forward(fire_nn *nn, const float *x, int32_t B,
                             float *out_t, float *out_map, void *stream);
 

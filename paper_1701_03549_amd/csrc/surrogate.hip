@@ -492,7 +492,9 @@ hipError_t refresh_bf16(fire_nn *nn, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t forward(fire_nn *nn, const float *x, int B, hipStream_t s) {
+// Forward pass; the decoder (dense layer and upsampling convolutions) runs
+// only when `want_map` (the fitness head does not depend on it).
+hipError_t forward(fire_nn *nn, const float *x, int B, hipStream_t s, bool want_map) {
   const Layout &L = nn->L;
   hipError_t e;
   hipLaunchKernelGGL(prep_input_kernel, dim3(blocks_for((int64_t)B * 16)), dim3(256), 0, s, x, B,
@@ -508,6 +510,7 @@ hipError_t forward(fire_nn *nn, const float *x, int B, hipStream_t s) {
                 nn->h3b, s)) != hipSuccess) return e;
   if ((e = gemm(B, 1, kH, nn->h3b, kH, 1, wb + L.Wf.off, 1, 1, nn->t, 1, w + L.cf.off, 0, 0,
                 nullptr, s)) != hipSuccess) return e;
+  if (!want_map) return hipSuccess;
   if ((e = gemm(B, kDec, kH, nn->h3b, kH, 1, wb + L.Wd.off, kDec, 1, nn->d0, kDec, w + L.cd.off,
                 1, 0, nn->d0b, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(upconv_fwd_kernel, dim3(blocks_for((int64_t)B * kD0C * 32 * 32)), dim3(256),
@@ -709,7 +712,7 @@ fire_status fire_nn_forward(fire_nn *nn, const float *x, int32_t B, float *out_t
     return nn_fail(nn, FIRE_E_INVALID, "bad batch (1..%d) or null pointer", nn->cfg.max_batch);
   NN_HIP(nn, hipSetDevice(nn->device));
   hipStream_t s = (hipStream_t)stream;
-  NN_HIP(nn, forward(nn, x, B, s));
+  NN_HIP(nn, forward(nn, x, B, s, out_map != nullptr));
   NN_HIP(nn, hipMemcpyAsync(out_t, nn->t, sizeof(float) * B, hipMemcpyDeviceToDevice, s));
   if (out_map) {
     hipLaunchKernelGGL(sigmoid_kernel, dim3(blocks_for((int64_t)B * kP)), dim3(256), 0, s, nn->z,
@@ -726,7 +729,7 @@ fire_status fire_nn_gradients(fire_nn *nn, const float *x, const float *y_t, con
     return nn_fail(nn, FIRE_E_INVALID, "bad batch (1..%d) or null pointer", nn->cfg.max_batch);
   NN_HIP(nn, hipSetDevice(nn->device));
   hipStream_t s = (hipStream_t)stream;
-  NN_HIP(nn, forward(nn, x, B, s));
+  NN_HIP(nn, forward(nn, x, B, s, y_map != nullptr && nn->cfg.w_map > 0.0f));
   NN_HIP(nn, backward(nn, y_t, y_map, B, s));
   NN_HIP(nn, hipMemcpyAsync(out_loss, nn->loss, 2 * sizeof(float), hipMemcpyDeviceToDevice, s));
   if (out_grads)
@@ -742,7 +745,7 @@ fire_status fire_nn_train_step(fire_nn *nn, const float *x, const float *y_t, co
     return nn_fail(nn, FIRE_E_INVALID, "bad batch, step or learning rate");
   NN_HIP(nn, hipSetDevice(nn->device));
   hipStream_t s = (hipStream_t)stream;
-  NN_HIP(nn, forward(nn, x, B, s));
+  NN_HIP(nn, forward(nn, x, B, s, y_map != nullptr && nn->cfg.w_map > 0.0f));
   NN_HIP(nn, backward(nn, y_t, y_map, B, s));
   const float c1 = 1.0f - powf(nn->cfg.adam_b1, (float)step);
   const float c2 = 1.0f - powf(nn->cfg.adam_b2, (float)step);

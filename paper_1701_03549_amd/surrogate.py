@@ -110,15 +110,19 @@ def run_ga(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=
     hist_pop = torch.empty((generations, P, 5), dtype=torch.float64, device=dev)
     hist_fit = torch.empty((generations, P, R), dtype=torch.float64, device=dev)
     res = torch.empty((P * R, 24), dtype=torch.uint8, device=dev)
-    base = fire.make_sims(P * R, lid, tid, ign, param_index=np.repeat(np.arange(P), R))
+    # every generation's descriptors, on the device before the first one runs
+    sims = fire.make_sims(generations * P * R, lid, tid, ign,
+                          param_index=np.tile(np.repeat(np.arange(P), R), generations))
+    d_sims_all = torch.from_numpy(sims.view(np.uint8).copy()).to(dev).reshape(-1, 28)
     t_sim = t_nn = 0.0
     bank_x = torch.empty((generations * P * R, 7), dtype=torch.float32, device=dev)
     bank_y = torch.empty(generations * P * R, dtype=torch.float32, device=dev)
-    gen_rng = torch.Generator(device="cpu").manual_seed(seed)
+    # minibatch indices are drawn on the device, so queuing a generation's
+    # work never waits for the GPU
+    gen_rng = torch.Generator(device=dev)
+    gen_rng.manual_seed(seed)
     for gen in range(generations):
-        sims = base.copy()
-        sims["sim_index"] = (gen * P * R + np.arange(P * R)).astype(np.uint32)
-        d_sims = torch.from_numpy(sims.view(np.uint8).copy()).to(dev)
+        d_sims = d_sims_all[gen * P * R:(gen + 1) * P * R]
         hist_pop[gen].copy_(pop)
         t0 = time.perf_counter()
         g.run_dev(pop, d_sims, P * R, sim_seed, res, stream=stream)
@@ -138,8 +142,8 @@ def run_ga(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=
             bank_y[k0:k0 + P * R] = torch.log1p(fit.reshape(-1)).float()
             n_bank = k0 + P * R
             for _ in range(online_steps):
-                idx = torch.randint(0, n_bank, (min(net.max_batch, n_bank),), generator=gen_rng)
-                idx = idx.to(dev)
+                idx = torch.randint(0, n_bank, (min(net.max_batch, n_bank),), generator=gen_rng,
+                                    device=dev)
                 net.train_step(bank_x[idx], bank_y[idx], None, lr=online_lr)
         keep = E + ((P - E) // 2 if unscreened is None else unscreened)
         sets = []
