@@ -25,7 +25,7 @@ struct LandscapeHost {
   int W = 0, H = 0, stride = 0;
   uint8_t forest = 1;
   uint4 *rec = nullptr;
-  double *psi = nullptr;
+  double *cov = nullptr;  // [H*W][2] psi, slope/100, then [H*W][8] omega
   uint32_t *blocked = nullptr;
   uint8_t *burn_steps = nullptr;  // device [256], NULL = one step for every type
   // observed share of simulations that left their LDS window (moving
@@ -152,7 +152,9 @@ fire_status sync_tables(fire_ctx *c) {
     const LandscapeHost &L = c->ls[i];
     LandscapeDev d{};
     d.W = L.W; d.H = L.H; d.stride = L.stride; d.valid = L.live ? 1 : 0;
-    d.rec = L.rec; d.psi = L.psi; d.blocked = L.blocked;
+    d.rec = L.rec; d.ps = L.cov;
+    d.omega = L.cov ? L.cov + 2 * (int64_t)L.W * L.H : nullptr;
+    d.blocked = L.blocked;
     d.burn_steps = L.burn_steps;
     d.forest_class = L.forest;
     hl[i] = d;
@@ -320,6 +322,11 @@ struct RunPlan {
 // few of them cost a whole simulation's latency.
 constexpr float kWindowRetryMax = 0.0f;
 constexpr int kMinAutoQueue = 1024;      // LDS queue entries a built-in window should leave
+// Built-in windows only for batches of replicates (at most this many
+// parameter vectors): with many different vectors (a GA population, Monte
+// Carlo draws) some fires outgrow any window and their repeats, which start
+// only after the window launch ends, cost more than the residency gains.
+constexpr int kWindowMaxParams = 8;
 
 // LDS, queue and residency of one launch shape; false if it cannot fit.
 bool shape_launch(fire_ctx *c, fire_schedule &s, int bitset_words, bool dur, bool win,
@@ -397,7 +404,7 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
   int win = 0;
   if (s.window > 0) {
     win = s.window;
-  } else if (s.window < 0 && win_frac <= kWindowRetryMax) {
+  } else if (s.window < 0 && win_frac <= kWindowRetryMax && n_params <= kWindowMaxParams) {
     // most resident simulations first; among those, the largest window
     // whose LDS queues keep kMinAutoQueue entries (fronts then stay in LDS),
     // else the one with the longest queues
@@ -635,7 +642,7 @@ void fire_ctx_destroy(fire_ctx *c) {
   (void)hipDeviceSynchronize();
   for (auto &L : c->ls) {
     if (L.rec) (void)hipFree(L.rec);
-    if (L.psi) (void)hipFree(L.psi);
+    if (L.cov) (void)hipFree(L.cov);
     if (L.blocked) (void)hipFree(L.blocked);
     if (L.burn_steps) (void)hipFree(L.burn_steps);
   }
@@ -714,7 +721,7 @@ fire_status fire_landscape_load(fire_ctx *c, const fire_landscape_desc *d,
   uint8_t *d_veg = nullptr;
   float *d_f = nullptr;
   hipError_t e = hipMalloc(&L.rec, sizeof(uint4) * n);
-  if (e == hipSuccess) e = hipMalloc(&L.psi, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&L.cov, sizeof(double) * 10 * n);
   if (e == hipSuccess) e = hipMalloc(&L.blocked, sizeof(uint32_t) * H * stride);
   if (e == hipSuccess) e = hipMalloc(&d_veg, n);
   if (e == hipSuccess) e = hipMalloc(&d_f, sizeof(float) * 4 * n);
@@ -723,13 +730,13 @@ fire_status fire_landscape_load(fire_ctx *c, const fire_landscape_desc *d,
     e = hipMemcpy(d_f + k * n, layers[k].data(), n * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = launch_preprocess(d_veg, d_f, d_f + n, d_f + 2 * n, d_f + 3 * n, W, H,
-                          stride, L.rec, L.psi, L.blocked, nullptr);
+                          stride, L.rec, L.cov, L.cov + 2 * n, L.blocked, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (d_veg) (void)hipFree(d_veg);
   if (d_f) (void)hipFree(d_f);
   if (e != hipSuccess) {
     if (L.rec) (void)hipFree(L.rec);
-    if (L.psi) (void)hipFree(L.psi);
+    if (L.cov) (void)hipFree(L.cov);
     if (L.blocked) (void)hipFree(L.blocked);
     if (L.burn_steps) (void)hipFree(L.burn_steps);
     return fail(c, e == hipErrorOutOfMemory ? FIRE_E_OOM : FIRE_E_DEVICE,
@@ -754,7 +761,7 @@ fire_status fire_landscape_free(fire_ctx *c, int32_t id) {
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   HIP_OR_FAIL(c, hipDeviceSynchronize());
   LandscapeHost &L = c->ls[id];
-  (void)hipFree(L.rec); (void)hipFree(L.psi); (void)hipFree(L.blocked);
+  (void)hipFree(L.rec); (void)hipFree(L.cov); (void)hipFree(L.blocked);
   if (L.burn_steps) (void)hipFree(L.burn_steps);
   L = LandscapeHost();
   for (auto &T : c->tg)
@@ -1207,7 +1214,9 @@ fire_status fire_run_dense(fire_ctx *c, const double *betas, int32_t n_params,
     const LandscapeHost &L = c->ls[sd.landscape_id];
     LandscapeDev D{};
     D.W = L.W; D.H = L.H; D.stride = L.stride; D.valid = 1;
-    D.rec = L.rec; D.psi = L.psi; D.blocked = L.blocked; D.burn_steps = nullptr;
+    D.rec = L.rec; D.ps = L.cov;
+    D.omega = L.cov ? L.cov + 2 * (int64_t)L.W * L.H : nullptr;
+    D.blocked = L.blocked; D.burn_steps = nullptr;
     D.forest_class = L.forest;
     const double *beta = d_beta + 5 * (size_t)sd.param_index;
     HIP_OR_FAIL(c, launch_dense_init(plane[0], D, sd.ign_x, sd.ign_y, d_cnt, st));

@@ -16,7 +16,9 @@ struct LandscapeDev {
   int32_t W, H, stride, valid;  // stride = ceil(W/32) words per bitset row
   const uint4 *rec;             // [H*W] {slope f32, aspect f32, wind f32,
                                 //        veg | up_mask << 8}
-  const double *psi;            // [H*W] aspect covariate (binary64)
+  const double *ps;             // [H*W][2] binary64: psi, slope / 100 of each cell
+  const double *omega;          // [H*W][8] binary64: omega of each cell as the
+                                // target of an edge in direction 0..7
   const uint32_t *blocked;      // [H*stride] 1 = non-burnable or padding
   const uint8_t *burn_steps;    // NULL (one step for every type) or [256]
                                 // active steps of a burning cell by veg value
@@ -67,7 +69,7 @@ struct SimArgs {
 hipError_t launch_preprocess(const uint8_t *veg, const float *elev,
                              const float *slope, const float *aspect,
                              const float *wind, int W, int H, int stride,
-                             uint4 *rec, double *psi, uint32_t *blocked,
+                             uint4 *rec, double *ps, double *omega, uint32_t *blocked,
                              hipStream_t s);
 hipError_t launch_thresholds(const LandscapeDev *ls_dev_entry, int W, int H,
                              const double *beta_dev, uint32_t forest,

@@ -59,9 +59,11 @@ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1,
 // ---------------------------------------------------------------------------
 // Eq. 1 for the directed edge into target t in direction d, quantised to a
 // 32-bit threshold. All covariates belong to the target: I_f from its
-// vegetation, psi precomputed from its slope and aspect, omega from its wind
-// direction against the edge's compass angle, sigma from its slope when it
-// lies strictly higher than the source (bit d of its up mask).
+// vegetation, psi from its slope and aspect, omega from its wind direction
+// against the edge's compass angle, sigma from its slope when it lies
+// strictly higher than the source (bit d of its up mask). psi and slope/100
+// (ps[2t], ps[2t+1]) and the eight omegas (omega[8t + d]) do not depend on
+// beta and are computed once per landscape.
 __device__ __forceinline__ uint32_t quantise(double p) {
   if (!(p < 1.0)) return kSaturated;
   if (!(p > 0.0)) return 0u;
@@ -70,23 +72,30 @@ __device__ __forceinline__ uint32_t quantise(double p) {
   return (uint32_t)scaled;
 }
 
-__device__ __forceinline__ uint32_t edge_threshold(const double *beta,
-                                                   uint4 rec_t, double psi_t,
-                                                   int d, uint32_t forest) {
-  const uint32_t veg = rec_t.w & 0xFFu;
-  if (veg == 0) return 0u;
-  const bool up = ((rec_t.w >> (8 + d)) & 1u) != 0;
-  const double slope = (double)__uint_as_float(rec_t.x);
-  const double wind = (double)__uint_as_float(rec_t.z);
-  const double i_f = veg == forest ? 1.0 : 0.0;
-  const double omega = cos((wind - 45.0 * (double)d) * kDegToRad);
-  const double sigma = up ? slope / 100.0 : 0.0;
+__device__ __forceinline__ double omega_of(float wind_deg, int d) {
+  return cos(((double)wind_deg - 45.0 * (double)d) * kDegToRad);
+}
+
+__device__ __forceinline__ uint32_t logistic_threshold(const double *beta, double i_f, double psi,
+                                                       double omega, double sigma) {
   double x = beta[0];
   x = x + beta[1] * i_f;
-  x = x + beta[2] * psi_t;
+  x = x + beta[2] * psi;
   x = x + beta[3] * omega;
   x = x + beta[4] * sigma;
   return quantise(1.0 / (1.0 + exp(-x)));
+}
+
+// The threshold from the landscape's precomputed covariates (F: pointer type
+// of the binary64 arrays).
+template <typename F>
+__device__ __forceinline__ uint32_t edge_threshold(const double *beta, uint32_t vu_t, F ps, F omega,
+                                                   int64_t t, int d, uint32_t forest) {
+  const uint32_t veg = vu_t & 0xFFu;
+  if (veg == 0) return 0u;
+  const bool up = ((vu_t >> (8 + d)) & 1u) != 0;
+  return logistic_threshold(beta, veg == forest ? 1.0 : 0.0, ps[2 * t], omega[8 * t + d],
+                            up ? ps[2 * t + 1] : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -95,7 +104,8 @@ __device__ __forceinline__ uint32_t edge_threshold(const double *beta,
 __global__ void preprocess_kernel(const uint8_t *veg, const float *elev,
                                   const float *slope, const float *aspect,
                                   const float *wind, int W, int H, int stride,
-                                  uint4 *rec, double *psi, uint32_t *blocked) {
+                                  uint4 *rec, double *ps, double *omega,
+                                  uint32_t *blocked) {
   const int64_t n = (int64_t)W * H;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
        c += (int64_t)gridDim.x * blockDim.x) {
@@ -111,9 +121,10 @@ __global__ void preprocess_kernel(const uint8_t *veg, const float *elev,
     const float sl = slope[c];
     rec[c] = make_uint4(__float_as_uint(sl), __float_as_uint(aspect[c]),
                         __float_as_uint(wind[c]), (uint32_t)veg[c] | (up << 8));
-    psi[c] = (double)sl > 5.0
-                 ? cos(((double)aspect[c] - 315.0) * kDegToRad)
-                 : 0.0;
+    ps[2 * c] = (double)sl > 5.0 ? cos(((double)aspect[c] - 315.0) * kDegToRad) : 0.0;
+    ps[2 * c + 1] = (double)sl / 100.0;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) omega[8 * c + d] = omega_of(wind[c], d);
   }
   const int64_t nw = (int64_t)H * stride;
   for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < nw;
@@ -128,34 +139,57 @@ __global__ void preprocess_kernel(const uint8_t *veg, const float *elev,
   }
 }
 
-// One thread per source cell writes its 8 thresholds (two 16-byte stores).
+// One thread per source cell writes its 8 thresholds (two 16-byte stores)
+// for each of up to kBetaPerThread parameter vectors: the covariates of each
+// edge (omega evaluated here, not read) serve all of them.
+constexpr int kBetaPerThread = 8;
+
 __global__ void thresholds_kernel(const LandscapeDev *lsd, int W, int H,
-                                  const double *beta_dev, uint32_t forest,
+                                  const double *beta_dev, int n_beta, uint32_t forest,
                                   uint32_t *out_base, int64_t out_stride) {
-  // parameter vector blockIdx.y, its table at out_base + blockIdx.y * out_stride
+  // parameter vectors b0 .. b0 + nb - 1; vector b's table at out_base + b * out_stride
   const LandscapeDev L = *lsd;
-  double beta[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) beta[i] = beta_dev[5 * (int64_t)blockIdx.y + i];
-  uint32_t *const out = out_base + (int64_t)blockIdx.y * out_stride;
+  const int b0 = blockIdx.y * kBetaPerThread;
+  const int nb = min(kBetaPerThread, n_beta - b0);
   const int64_t n = (int64_t)W * H;
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * blockDim.x) {
     const int x = (int)(s % W), y = (int)(s / W);
-    uint32_t t8[8];
+    // directions 4h .. 4h+3 form the 16-byte store h of every table
 #pragma unroll
-    for (int d = 0; d < 8; ++d) {
-      const int tx = x + kDx[d], ty = y + kDy[d];
-      uint32_t v = 0;
-      if (tx >= 0 && tx < W && ty >= 0 && ty < H) {
+    for (int h = 0; h < 2; ++h) {
+      uint32_t t4[kBetaPerThread][4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int d = 4 * h + k;
+        const int tx = x + kDx[d], ty = y + kDy[d];
+#pragma unroll
+        for (int b = 0; b < kBetaPerThread; ++b) t4[b][k] = 0u;
+        if (tx < 0 || tx >= W || ty < 0 || ty >= H) continue;
         const int64_t t = (int64_t)ty * W + tx;
-        v = edge_threshold(beta, L.rec[t], L.psi[t], d, forest);
+        const uint4 rec = L.rec[t];
+        const uint32_t veg = rec.w & 0xFFu;
+        if (veg == 0) continue;
+        const double i_f = veg == forest ? 1.0 : 0.0;
+        const double psi = L.ps[2 * t];
+        const double sigma = ((rec.w >> (8 + d)) & 1u) ? L.ps[2 * t + 1] : 0.0;
+        const double omega = omega_of(__uint_as_float(rec.z), d);
+#pragma unroll
+        for (int b = 0; b < kBetaPerThread; ++b) {
+          if (b >= nb) break;
+          double beta[5];
+#pragma unroll
+          for (int i = 0; i < 5; ++i) beta[i] = beta_dev[5 * (int64_t)(b0 + b) + i];
+          t4[b][k] = logistic_threshold(beta, i_f, psi, omega, sigma);
+        }
       }
-      t8[d] = v;
+#pragma unroll
+      for (int b = 0; b < kBetaPerThread; ++b) {
+        if (b >= nb) break;
+        uint4 *o = reinterpret_cast<uint4 *>(out_base + (int64_t)(b0 + b) * out_stride + s * 8);
+        o[h] = make_uint4(t4[b][0], t4[b][1], t4[b][2], t4[b][3]);
+      }
     }
-    uint4 *o = reinterpret_cast<uint4 *>(out + s * 8);
-    o[0] = make_uint4(t8[0], t8[1], t8[2], t8[3]);
-    o[1] = make_uint4(t8[4], t8[5], t8[6], t8[7]);
   }
 }
 
@@ -225,6 +259,11 @@ __device__ __forceinline__ u32x4 load_x4(gmem_cu32 *q) { return *(gmem_cu32x4 *)
 __device__ __forceinline__ uint4 load_rec(const uint4 *base, int64_t t) {
   gmem_cu32 *q = (gmem_cu32 *)(base + t);
   return make_uint4(q[0], q[1], q[2], q[3]);
+}
+
+// The vegetation | up-mask word of record t.
+__device__ __forceinline__ uint32_t rec_word(const uint4 *base, int64_t t) {
+  return ((gmem_cu32 *)(base + t))[3];
 }
 
 // Offsets of direction d, packed 2 bits per direction (value + 1).
@@ -471,8 +510,8 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
           const int d = 4 * (int)g + k;
           const bool el = (elig >> k) & 1u;
           const int64_t tl = el ? (int64_t)(y + dir_dy(d)) * W + (x + dir_dx(d)) : (int64_t)s_lin;
-          const uint32_t t = edge_threshold(beta, load_rec(L.rec, tl), ((gmem_cf64 *)L.psi)[tl],
-                                            d, L.forest_class);
+          const uint32_t t = edge_threshold(beta, rec_word(L.rec, tl), (gmem_cf64 *)L.ps,
+                                            (gmem_cf64 *)L.omega, tl, d, L.forest_class);
           if (el && (t == kSaturated || r.v[k] < t)) hit |= 1u << k;
         }
       } else {
@@ -481,8 +520,8 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
           if (!((elig >> k) & 1u)) continue;
           const int d = 4 * (int)g + k;
           const int64_t tl = (int64_t)(y + dir_dy(d)) * W + (x + dir_dx(d));
-          const uint32_t t = edge_threshold(beta, load_rec(L.rec, tl), ((gmem_cf64 *)L.psi)[tl],
-                                            d, L.forest_class);
+          const uint32_t t = edge_threshold(beta, rec_word(L.rec, tl), (gmem_cf64 *)L.ps,
+                                            (gmem_cf64 *)L.omega, tl, d, L.forest_class);
           const uint32_t coin = k == 0 ? r.v[0] : k == 1 ? r.v[1] : k == 2 ? r.v[2] : r.v[3];
           if (t == kSaturated || coin < t) hit |= 1u << k;
         }
@@ -877,14 +916,14 @@ __global__ void dense_step_kernel(const uint8_t *__restrict__ cur, uint8_t *__re
       if (burning) {
         double beta[5];
         for (int k = 0; k < 5; ++k) beta[k] = beta_dev[k];
-        const uint4 rec = load_rec(L.rec, t);
-        const double psi = L.psi[t];
+        const uint32_t vu = rec_word(L.rec, t);
         double q = 1.0;
         bool sure = false;
         for (int d = 0; d < 8; ++d) {
           if (!((burning >> d) & 1u)) continue;
           // the edge from the neighbour in direction d points the other way
-          const uint32_t thr = edge_threshold(beta, rec, psi, (d + 4) & 7, L.forest_class);
+          const uint32_t thr = edge_threshold(beta, vu, L.ps, L.omega, t, (d + 4) & 7,
+                                              L.forest_class);
           sure = sure || thr == kSaturated;
           q = q * (1.0 - (double)thr * (1.0 / 4294967296.0));
         }
@@ -1107,11 +1146,11 @@ int grid_for(int64_t n, int block) {
 hipError_t launch_preprocess(const uint8_t *veg, const float *elev,
                              const float *slope, const float *aspect,
                              const float *wind, int W, int H, int stride,
-                             uint4 *rec, double *psi, uint32_t *blocked,
+                             uint4 *rec, double *ps, double *omega, uint32_t *blocked,
                              hipStream_t s) {
   const int64_t n = (int64_t)W * H;
   hipLaunchKernelGGL(preprocess_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s,
-                     veg, elev, slope, aspect, wind, W, H, stride, rec, psi,
+                     veg, elev, slope, aspect, wind, W, H, stride, rec, ps, omega,
                      blocked);
   return hipGetLastError();
 }
@@ -1126,8 +1165,9 @@ hipError_t launch_thresholds_multi(const LandscapeDev *ls_dev_entry, int W, int 
                                    const double *betas_dev, int n_params, uint32_t forest,
                                    uint32_t *out, int64_t out_stride, hipStream_t s) {
   const int64_t n = (int64_t)W * H;
-  hipLaunchKernelGGL(thresholds_kernel, dim3(grid_for(n, 256), n_params), dim3(256), 0, s,
-                     ls_dev_entry, W, H, betas_dev, forest, out, out_stride);
+  const int groups = (n_params + kBetaPerThread - 1) / kBetaPerThread;
+  hipLaunchKernelGGL(thresholds_kernel, dim3(grid_for(n, 256), groups), dim3(256), 0, s,
+                     ls_dev_entry, W, H, betas_dev, n_params, forest, out, out_stride);
   return hipGetLastError();
 }
 
