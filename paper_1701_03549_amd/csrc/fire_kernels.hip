@@ -480,7 +480,10 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         thr[0] = t4.x; thr[1] = t4.y; thr[2] = t4.z; thr[3] = t4.w;
       }
       // neighbour words from the source's: one row is ws words, and a
-      // column step crosses a word boundary only at bit 0 or 31
+      // column step crosses a word boundary only at bit 0 or 31. An edge
+      // whose target is outside (or whose source is at a window edge) reads
+      // the source's own bit, which is set: the four reads are unconditional
+      // and issue back to back.
       const int base = bw_of(x, y), xb = x & 31;
       uint32_t elig = 0;
 #pragma unroll
@@ -492,7 +495,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         const int row = dy < 0 ? -ws : (dy > 0 ? ws : 0);
         const int w = inside ? base + row + ((xb + dx) >> 5) : base;
         const int b = inside ? (xb + dx) & 31 : xb;
-        elig |= (inside && ((bits[w] >> b) & 1u) == 0) ? (1u << k) : 0u;
+        elig |= ((bits[w] >> b) & 1u) == 0 ? (1u << k) : 0u;
       }
       n_tried = __popc(elig);
       // not gated on elig: the rounds then overlap the bitset and table reads
