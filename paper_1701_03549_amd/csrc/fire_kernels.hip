@@ -518,13 +518,35 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
           if (el && (t == kSaturated || r.v[k] < t)) hit |= 1u << k;
         }
       } else {
+        // the covariates of all four targets are read first (an ineligible
+        // edge reads its source's own), then Eq. 1 is evaluated for the
+        // eligible edges only
+        uint32_t vu[4];
+        double psi[4], slope[4], om[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int d = 4 * (int)g + k;
+          const bool el = (elig >> k) & 1u;
+          const int64_t tl = el ? (int64_t)(y + dir_dy(d)) * W + (x + dir_dx(d)) : (int64_t)s_lin;
+          vu[k] = rec_word(L.rec, tl);
+          psi[k] = ((gmem_cf64 *)L.ps)[2 * tl];
+          slope[k] = ((gmem_cf64 *)L.ps)[2 * tl + 1];
+          om[k] = ((gmem_cf64 *)L.omega)[8 * tl + d];
+        }
 #pragma unroll 1
         for (int k = 0; k < 4; ++k) {
           if (!((elig >> k) & 1u)) continue;
           const int d = 4 * (int)g + k;
-          const int64_t tl = (int64_t)(y + dir_dy(d)) * W + (x + dir_dx(d));
-          const uint32_t t = edge_threshold(beta, rec_word(L.rec, tl), (gmem_cf64 *)L.ps,
-                                            (gmem_cf64 *)L.omega, tl, d, L.forest_class);
+          const uint32_t v = k == 0 ? vu[0] : k == 1 ? vu[1] : k == 2 ? vu[2] : vu[3];
+          const uint32_t veg = v & 0xFFu;
+          uint32_t t = 0u;
+          if (veg != 0) {
+            const double ps_k = k == 0 ? psi[0] : k == 1 ? psi[1] : k == 2 ? psi[2] : psi[3];
+            const double sl_k = k == 0 ? slope[0] : k == 1 ? slope[1] : k == 2 ? slope[2] : slope[3];
+            const double om_k = k == 0 ? om[0] : k == 1 ? om[1] : k == 2 ? om[2] : om[3];
+            t = logistic_threshold(beta, veg == L.forest_class ? 1.0 : 0.0, ps_k, om_k,
+                                   ((v >> (8 + d)) & 1u) ? sl_k : 0.0);
+          }
           const uint32_t coin = k == 0 ? r.v[0] : k == 1 ? r.v[1] : k == 2 ? r.v[2] : r.v[3];
           if (t == kSaturated || coin < t) hit |= 1u << k;
         }
