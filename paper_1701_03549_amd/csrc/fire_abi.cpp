@@ -787,9 +787,12 @@ fire_status fire_landscape_set_burn_steps(fire_ctx *c, int32_t id, const uint8_t
   LandscapeHost &L = c->ls[id];
   L.win_frac = 0.f;  // fire sizes change with the turn-off times
   L.win_obs = 0;
+  const int64_t n = (int64_t)L.W * L.H;
   if (!steps || all_one) {
     if (L.burn_steps) HIP_OR_FAIL(c, hipFree(L.burn_steps));
     L.burn_steps = nullptr;
+    HIP_OR_FAIL(c, launch_set_life(L.rec, n, nullptr, nullptr));
+    HIP_OR_FAIL(c, hipDeviceSynchronize());
     return sync_tables(c);
   }
   if (!L.burn_steps) HIP_OR_FAIL(c, hipMalloc(&L.burn_steps, 256));
@@ -797,6 +800,9 @@ fire_status fire_landscape_set_burn_steps(fire_ctx *c, int32_t id, const uint8_t
   std::memcpy(h, steps, 256);
   h[0] = 1;
   HIP_OR_FAIL(c, hipMemcpy(L.burn_steps, h, 256, hipMemcpyHostToDevice));
+  // each record word also carries its cell's turn-off time
+  HIP_OR_FAIL(c, launch_set_life(L.rec, n, L.burn_steps, nullptr));
+  HIP_OR_FAIL(c, hipDeviceSynchronize());
   return sync_tables(c);
 }
 

@@ -15,7 +15,7 @@ constexpr uint32_t kSaturated = 0xFFFFFFFFu;
 struct LandscapeDev {
   int32_t W, H, stride, valid;  // stride = ceil(W/32) words per bitset row
   const uint4 *rec;             // [H*W] {slope f32, aspect f32, wind f32,
-                                //        veg | up_mask << 8}
+                                //        veg | up_mask << 8 | turn-off << 16}
   const double *ps;             // [H*W][2] binary64: psi, slope / 100 of each cell
   const double *omega;          // [H*W][8] binary64: omega of each cell as the
                                 // target of an edge in direction 0..7
@@ -81,6 +81,7 @@ hipError_t launch_thresholds_multi(const LandscapeDev *ls_dev_entry, int W, int 
                                    uint32_t *out, int64_t out_stride, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_zero_words(uint32_t *p0, uint32_t *p1, uint32_t *p2, hipStream_t s);
+hipError_t launch_set_life(uint4 *rec, int64_t n, const uint8_t *steps, hipStream_t s);
 hipError_t launch_sim(const SimArgs &a, int threads, bool table, bool dur, int grid,
                       size_t lds_bytes, hipStream_t s);
 hipError_t set_sim_lds_limit(size_t bytes);

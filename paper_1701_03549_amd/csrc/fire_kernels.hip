@@ -193,6 +193,16 @@ __global__ void thresholds_kernel(const LandscapeDev *lsd, int W, int H,
   }
 }
 
+// Bits 16..23 of every record word: the turn-off time of the cell's
+// vegetation (steps[veg]), or 0 when steps is NULL.
+__global__ void set_life_kernel(uint4 *rec, int64_t n, const uint8_t *steps) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t w = rec[c].w & 0xFFFFu;
+    rec[c].w = w | ((steps ? (uint32_t)steps[w & 0xFFu] : 0u) << 16);
+  }
+}
+
 // Zero up to three counters in one launch (NULL entries are skipped).
 __global__ void zero_words_kernel(uint32_t *p0, uint32_t *p1, uint32_t *p2) {
   if (threadIdx.x == 0) {
@@ -427,11 +437,12 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       ctl[kAbort0 + 0] = 0u; ctl[kAbort0 + 1] = 0u; ctl[kAbort0 + 2] = 0u;
     }
     __syncthreads();
-    gmem_cu8 *const bsteps = DUR ? (gmem_cu8 *)L.burn_steps : nullptr;
-    // active steps of a cell that ignites
+    // active steps of a cell that ignites (bits 16..23 of its record word
+    // hold its vegetation's turn-off time when the landscape has them)
+    const bool has_life = DUR && L.burn_steps != nullptr;
     auto life_of = [&](int x, int y) -> uint32_t {
-      if (!DUR || bsteps == nullptr) return 1u;
-      return bsteps[load_rec(L.rec, (int64_t)y * W + x).w & 0xFFu];
+      if (!has_life) return 1u;
+      return (rec_word(L.rec, (int64_t)y * W + x) >> 16) & 0xFFu;
     };
     if (tid == 0) {
       bits[bw_of(ix, iy)] |= 1u << (ix & 31);
@@ -455,6 +466,14 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     // frontier length of step k lives in ctl[kLen0 + k % 3]
     int slot = 0;
     bool aborted = false;
+    // a new cell enters the queue with life 0 (not yet known); the first
+    // unit of its entry looks it up in phase 1 of the next step, where the
+    // read overlaps the unit's other reads, and it is needed only after
+    // that phase
+    auto resolve_life = [&](uint32_t e, uint32_t i) {
+      if (DUR && l_load(cq, i) == 0u)
+        l_store(cq, i, life_of((int)(e & 0xFFFu), (int)((e >> 12) & 0xFFFu)));
+    };
 
     // Phase 1 for one unit: frontier entry e and direction group g (edges
     // d = 4g .. 4g+3, whose coins are the four words of one Philox call
@@ -602,10 +621,10 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         const uint32_t v = (uint32_t)tx | ((uint32_t)ty << 12);
         if (direct) {
           lds[bw + (cq ^ 1u) * cap + idx] = v;
-          if (DUR) life_lds[(cq ^ 1u) * cap + idx] = (uint8_t)life_of(tx, ty);
+          if (DUR) life_lds[(cq ^ 1u) * cap + idx] = 0u;
         } else {
           q_store(cq ^ 1u, idx, v);
-          if (DUR) l_store(cq ^ 1u, idx, life_of(tx, ty));
+          if (DUR) l_store(cq ^ 1u, idx, 0u);
         }
         ++idx;
         ++my_new;
@@ -639,6 +658,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
           if (rr * BLOCK < (int)n_units && j < n_units) {
             const uint32_t e = rr == 0 ? e_first : lds[bw + cq * cap + (j >> 1)];
             ent[rr] = e;
+            if ((j & 1u) == 0) resolve_life(e, j >> 1);
             uint32_t nt;
             hit[rr] = unit_outcome(std::true_type{}, e, j & 1u, nt);
             my_trials += nt;
@@ -660,6 +680,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         //    memory past queue_cap ----------------------------------------
         for (uint32_t j = tid; j < n_units; j += BLOCK) {
           const uint32_t e = q_load(cq, j >> 1);
+          if ((j & 1u) == 0) resolve_life(e, j >> 1);
           uint32_t nt;
           const uint32_t m = unit_outcome(std::false_type{}, e, j & 1u, nt) & 15u;
           my_trials += nt;
@@ -1218,6 +1239,11 @@ hipError_t launch_dense_result(const uint8_t *st, const LandscapeDev &L, const u
                                uint32_t *map, hipStream_t s) {
   hipLaunchKernelGGL(dense_result_kernel, dim3(1), dim3(kDenseResThreads), 0, s, st, L, ref, n_ref,
                      has_target ? 1 : 0, steps, counts, out, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_life(uint4 *rec, int64_t n, const uint8_t *steps, hipStream_t s) {
+  hipLaunchKernelGGL(set_life_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, rec, n, steps);
   return hipGetLastError();
 }
 
