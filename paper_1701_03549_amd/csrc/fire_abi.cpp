@@ -60,8 +60,9 @@ struct fire_ctx {
   size_t ovf_words = 0;
   uint32_t *d_retry = nullptr;  // window runs: per launch, count + simulation list
   size_t retry_words = 0;
-  // retry counts of window runs, copied back without waiting: slot i holds
-  // the count of a launch on landscape stat_ls[i] of stat_n[i] simulations
+  // retry counts of window runs, written into host-mapped memory by the
+  // re-run launch (read once stat_ev[i] has passed): slot i holds the count
+  // of a launch on landscape stat_ls[i] of stat_n[i] simulations
   static constexpr int kStatSlots = 16;
   uint32_t *h_stat = nullptr;
   hipEvent_t stat_ev[kStatSlots] = {};
