@@ -90,14 +90,16 @@ def cpu_baseline(ls, centre, ref, threads, budget_s=12.0):
                       f"512x512, thresholds + simulation + Eq. 2), {dt:.1f} s"}
 
 
-def pmc_traffic(sim_ms):
+def pmc_profile():
+    """The committed counter summary of the simulation kernel, or None once
+    the kernel source differs from the one the counters were taken on."""
     if not os.path.exists(PROFILE_PMC):
         return None
     with open(PROFILE_PMC) as f:
         p = json.load(f)
     if p.get("kernel_source_sha") != kernel_sha():
         return None
-    return p.get("hbm_bytes_per_launch")
+    return p
 
 
 def run_ga(g, lid, tid, centre, plain: bool):
@@ -474,6 +476,7 @@ def main():
         f"{trials_per_s:.3e} trials/s, mean burnt {burnt / N_SIMS:.1f}, mean trials "
         f"{trials / N_SIMS:.1f}")
 
+    prof = pmc_profile()
     result = {
         "metric": METRIC, "value": sims_per_s, "unit": "sims/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -488,13 +491,19 @@ def main():
         "trials_per_s": trials_per_s,
         "mean_burnt": burnt / N_SIMS, "mean_trials": trials / N_SIMS,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(sim_ms),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": prof.get("hbm_bytes_per_launch") if prof else None,
+                     "issue": ({k: prof["sq"][k] for k in ("valu_busy_frac", "wave_busy_frac",
+                                                         "wave_wait_frac",
+                                                         "wave_issue_wait_frac")}
+                               if prof and "sq" in prof else None),
                      "kernel": "sim_kernel", "kernel_ms": sim_ms,
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "limiter": "latency of the dependent CA steps (Philox, threshold load, LDS "
+                     "limiter": "the chain of dependent CA steps (Philox, threshold load, LDS "
                                 "round trips, two barriers per step; about 180 steps per "
-                                "simulation), not HBM bandwidth: traffic is under 2% of the "
-                                "algorithmic bytes"},
+                                "simulation) and, with 5 simulations per CU, VALU issue "
+                                "('issue': SQ counters of the same kernel); not HBM "
+                                "bandwidth: traffic is under 2% of the algorithmic bytes"},
         "cpu_baseline": None,
     }
     if not args.no_cpu:

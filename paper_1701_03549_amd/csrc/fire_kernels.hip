@@ -475,6 +475,29 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         l_store(cq, i, life_of((int)(e & 0xFFFu), (int)((e >> 12) & 0xFFFu)));
     };
 
+    // The four edges of group g, k = 0..3, point to (0, -s), (s, -s),
+    // (s, 0), (s, s) with s = +1 for g = 0 (N, NE, E, SE) and s = -1 for
+    // g = 1 (S, SW, W, NW). Their LDS words and bits around a source at
+    // (x, y) with word `base` and bit xb: a column step crosses a word
+    // boundary only at bit 0 or 31.
+    struct GroupGeom {
+      int wk[4], bk[4];
+      int s;
+    };
+    auto group_geom = [&](int xb, int base, uint32_t g) -> GroupGeom {
+      GroupGeom q;
+      q.s = g ? -1 : 1;
+      const int sws = g ? -ws : ws;
+      const int xs = xb + q.s;  // -1 .. 32
+      const int wo = xs >> 5;   // -1, 0 or 1
+      const int bs = xs & 31;
+      q.wk[0] = base - sws;      q.bk[0] = xb;
+      q.wk[1] = base - sws + wo; q.bk[1] = bs;
+      q.wk[2] = base + wo;       q.bk[2] = bs;
+      q.wk[3] = base + sws + wo; q.bk[3] = bs;
+      return q;
+    };
+
     // Phase 1 for one unit: frontier entry e and direction group g (edges
     // d = 4g .. 4g+3, whose coins are the four words of one Philox call
     // (sim_index, step, source, g)). An edge is tried when its target is
@@ -504,16 +527,16 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       // the source's own bit, which is set: the four reads are unconditional
       // and issue back to back.
       const int base = bw_of(x, y), xb = x & 31;
+      const GroupGeom q = group_geom(xb, base, g);
+      const bool r1 = (unsigned)(y - q.s) < (unsigned)H && !edge;  // row -s
+      const bool r2 = (unsigned)(y + q.s) < (unsigned)H && !edge;  // row +s
+      const bool c1 = (unsigned)(x + q.s) < (unsigned)W;           // column +s
+      const bool in[4] = {r1, r1 && c1, c1 && !edge, r2 && c1};
       uint32_t elig = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int d = 4 * (int)g + k;
-        const int dx = dir_dx(d), dy = dir_dy(d);
-        const bool inside =
-            (unsigned)(x + dx) < (unsigned)W && (unsigned)(y + dy) < (unsigned)H && !edge;
-        const int row = dy < 0 ? -ws : (dy > 0 ? ws : 0);
-        const int w = inside ? base + row + ((xb + dx) >> 5) : base;
-        const int b = inside ? (xb + dx) & 31 : xb;
+        const int w = in[k] ? q.wk[k] : base;
+        const int b = in[k] ? q.bk[k] : xb;
         elig |= ((bits[w] >> b) & 1u) == 0 ? (1u << k) : 0u;
       }
       n_tried = __popc(elig);
@@ -581,15 +604,13 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       // branch-free: an edge that did not hit ORs 0 into its source's own
       // word, so the four atomics issue back to back
       const int base = bw_of(x, y), xb = x & 31;
+      const GroupGeom q = group_geom(xb, base, g);
       uint32_t old[4], bitv[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int d = 4 * (int)g + k;
-        const int dx = dir_dx(d), dy = dir_dy(d);
         const bool h = (hit >> k) & 1u;
-        const int row = dy < 0 ? -ws : (dy > 0 ? ws : 0);
-        const int w = h ? base + row + ((xb + dx) >> 5) : base;
-        bitv[k] = h ? 1u << ((xb + dx) & 31) : 0u;
+        const int w = h ? q.wk[k] : base;
+        bitv[k] = h ? 1u << q.bk[k] : 0u;
         old[k] = atomicOr(&bits[w], bitv[k]);
       }
 #pragma unroll
@@ -616,8 +637,9 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (!((fresh >> k) & 1u)) continue;
-        const int d = 4 * (int)g + k;
-        const int tx = x + dir_dx(d), ty = y + dir_dy(d);
+        // edge k of group g: (0, -s), (s, -s), (s, 0), (s, s)
+        const int sg = g ? -1 : 1;
+        const int tx = x + (k == 0 ? 0 : sg), ty = y + (k == 2 ? 0 : (k == 3 ? sg : -sg));
         const uint32_t v = (uint32_t)tx | ((uint32_t)ty << 12);
         if (direct) {
           lds[bw + (cq ^ 1u) * cap + idx] = v;
