@@ -481,7 +481,8 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     // (x, y) with word `base` and bit xb: a column step crosses a word
     // boundary only at bit 0 or 31.
     struct GroupGeom {
-      int wk[4], bk[4];
+      int wk[4], bk[4];  // LDS word and bit of each target
+      int tk[4];         // lattice offset (cells) of each target
       int s;
     };
     auto group_geom = [&](int xb, int base, uint32_t g) -> GroupGeom {
@@ -495,6 +496,11 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       q.wk[1] = base - sws + wo; q.bk[1] = bs;
       q.wk[2] = base + wo;       q.bk[2] = bs;
       q.wk[3] = base + sws + wo; q.bk[3] = bs;
+      const int sW = g ? -W : W;
+      q.tk[0] = -sW;
+      q.tk[1] = q.s - sW;
+      q.tk[2] = q.s;
+      q.tk[3] = q.s + sW;
       return q;
     };
 
@@ -554,7 +560,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         for (int k = 0; k < 4; ++k) {
           const int d = 4 * (int)g + k;
           const bool el = (elig >> k) & 1u;
-          const int64_t tl = el ? (int64_t)(y + dir_dy(d)) * W + (x + dir_dx(d)) : (int64_t)s_lin;
+          const int64_t tl = el ? (int64_t)s_lin + q.tk[k] : (int64_t)s_lin;
           const uint32_t t = edge_threshold(beta, rec_word(L.rec, tl), (gmem_cf64 *)L.ps,
                                             (gmem_cf64 *)L.omega, tl, d, L.forest_class);
           if (el && (t == kSaturated || r.v[k] < t)) hit |= 1u << k;
@@ -569,7 +575,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         for (int k = 0; k < 4; ++k) {
           const int d = 4 * (int)g + k;
           const bool el = (elig >> k) & 1u;
-          const int64_t tl = el ? (int64_t)(y + dir_dy(d)) * W + (x + dir_dx(d)) : (int64_t)s_lin;
+          const int64_t tl = el ? (int64_t)s_lin + q.tk[k] : (int64_t)s_lin;
           vu[k] = rec_word(L.rec, tl);
           psi[k] = ((gmem_cf64 *)L.ps)[2 * tl];
           slope[k] = ((gmem_cf64 *)L.ps)[2 * tl + 1];

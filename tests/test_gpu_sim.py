@@ -49,6 +49,27 @@ def test_thresholds_within_one_unit(g, W, H, seed):
     g.free_landscape(lid)
 
 
+def test_tables_for_many_parameter_vectors(g):
+    """Table mode with 13 parameter vectors: one threshold launch writes the
+    13 tables, 8 vectors per thread and a partial last group; every
+    simulation matches the oracle run on the oracle's own table."""
+    from paper_1701_03549_amd import fire
+    W, H = 100, 67
+    ls = synth.make_landscape(W, H, 6)
+    rng = np.random.default_rng(31)
+    betas = np.column_stack([rng.uniform(-1.5, 0.5, 13), rng.uniform(-1, 1, (13, 4))])
+    lid = g.load_landscape(ls)
+    T = [oracle.thresholds(ls, b) for b in betas]
+    sims = fire.make_sims(104, lid, -1, (50, 33), param_index=np.arange(104) % 13)
+    g.set_schedule(256, 256, 1, 4, window=0)
+    say("13 tables in one launch")
+    res, maps = g.run(betas, sims, SEED, want_maps=True)
+    g.sync()
+    g.set_schedule(reset=True)
+    compare_with_oracle(ls, T, _res(res), _np_maps(maps), sims, SEED)
+    g.free_landscape(lid)
+
+
 def test_config1_plain_64(g):
     """64x64, landscape seed 101, ignition at the centre, 200 replicates to
     extinction, with beta = 0 and a subcritical vector; maps and counts."""
