@@ -140,9 +140,10 @@ __global__ void preprocess_kernel(const uint8_t *veg, const float *elev,
 }
 
 // One thread per source cell writes its 8 thresholds (two 16-byte stores)
-// for each of up to kBetaPerThread parameter vectors: the covariates of each
-// edge (omega evaluated here, not read) serve all of them.
-constexpr int kBetaPerThread = 8;
+// for each of up to kBetaPerThread parameter vectors: the covariates of the
+// 8 edges (omega evaluated here, not read) are computed once and serve all
+// of them, one vector per loop iteration.
+constexpr int kBetaPerThread = 16;
 
 __global__ void thresholds_kernel(const LandscapeDev *lsd, int W, int H,
                                   const double *beta_dev, int n_beta, uint32_t forest,
@@ -155,39 +156,41 @@ __global__ void thresholds_kernel(const LandscapeDev *lsd, int W, int H,
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * blockDim.x) {
     const int x = (int)(s % W), y = (int)(s / W);
-    // directions 4h .. 4h+3 form the 16-byte store h of every table
+    // the beta-independent covariates of the 8 edges (zero for an edge
+    // whose target is outside or not burnable: its threshold is 0)
+    double cp[8], co[8], cs[8];
+    uint32_t ok = 0, fm = 0;  // edge d: bit d set when it can burn / its target is forest
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      uint32_t t4[kBetaPerThread][4];
+    for (int d = 0; d < 8; ++d) {
+      const int tx = x + kDx[d], ty = y + kDy[d];
+      cp[d] = co[d] = cs[d] = 0.0;
+      if (tx < 0 || tx >= W || ty < 0 || ty >= H) continue;
+      const int64_t t = (int64_t)ty * W + tx;
+      const uint4 rec = L.rec[t];
+      const uint32_t veg = rec.w & 0xFFu;
+      if (veg == 0) continue;
+      ok |= 1u << d;
+      fm |= veg == forest ? 1u << d : 0u;
+      cp[d] = L.ps[2 * t];
+      cs[d] = ((rec.w >> (8 + d)) & 1u) ? L.ps[2 * t + 1] : 0.0;
+      co[d] = omega_of(__uint_as_float(rec.z), d);
+    }
+    // one table at a time: 8 independent evaluations per vector
+#pragma unroll 1
+    for (int b = 0; b < nb; ++b) {
+      const double *beta = beta_dev + 5 * (int64_t)(b0 + b);
+      uint4 *o = reinterpret_cast<uint4 *>(out_base + (int64_t)(b0 + b) * out_stride + s * 8);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int d = 4 * h + k;
-        const int tx = x + kDx[d], ty = y + kDy[d];
+      for (int h = 0; h < 2; ++h) {
+        uint32_t t4[4];
 #pragma unroll
-        for (int b = 0; b < kBetaPerThread; ++b) t4[b][k] = 0u;
-        if (tx < 0 || tx >= W || ty < 0 || ty >= H) continue;
-        const int64_t t = (int64_t)ty * W + tx;
-        const uint4 rec = L.rec[t];
-        const uint32_t veg = rec.w & 0xFFu;
-        if (veg == 0) continue;
-        const double i_f = veg == forest ? 1.0 : 0.0;
-        const double psi = L.ps[2 * t];
-        const double sigma = ((rec.w >> (8 + d)) & 1u) ? L.ps[2 * t + 1] : 0.0;
-        const double omega = omega_of(__uint_as_float(rec.z), d);
-#pragma unroll
-        for (int b = 0; b < kBetaPerThread; ++b) {
-          if (b >= nb) break;
-          double beta[5];
-#pragma unroll
-          for (int i = 0; i < 5; ++i) beta[i] = beta_dev[5 * (int64_t)(b0 + b) + i];
-          t4[b][k] = logistic_threshold(beta, i_f, psi, omega, sigma);
+        for (int k = 0; k < 4; ++k) {
+          const int d = 4 * h + k;
+          t4[k] = ((ok >> d) & 1u)
+                      ? logistic_threshold(beta, ((fm >> d) & 1u) ? 1.0 : 0.0, cp[d], co[d], cs[d])
+                      : 0u;
         }
-      }
-#pragma unroll
-      for (int b = 0; b < kBetaPerThread; ++b) {
-        if (b >= nb) break;
-        uint4 *o = reinterpret_cast<uint4 *>(out_base + (int64_t)(b0 + b) * out_stride + s * 8);
-        o[h] = make_uint4(t4[b][0], t4[b][1], t4[b][2], t4[b][3]);
+        o[h] = make_uint4(t4[0], t4[1], t4[2], t4[3]);
       }
     }
   }
