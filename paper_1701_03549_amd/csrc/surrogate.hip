@@ -134,14 +134,23 @@ __global__ void relu_bwd_kernel(float *g, const float *h, uint16_t *gb, int64_t 
   }
 }
 
-// column sums of d [M][N] (bias gradients), fixed order
+// column sums of d [M][N] (bias gradients) in a fixed order: a workgroup of
+// 256 threads takes 64 columns; row group r (0..3) sums rows r, r+4, ... in
+// order, then the four partial sums are added in row-group order
+constexpr int kColsumCols = 64;
 __global__ void colsum_kernel(const float *d, int M, int N, float *out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+  __shared__ float part[4][kColsumCols];
+  const int c = threadIdx.x % kColsumCols, rg = threadIdx.x / kColsumCols;
+  const int n = blockIdx.x * kColsumCols + c;
   float s = 0.0f;
-  for (int m = 0; m < M; ++m) s += d[(int64_t)m * N + n];
-  out[n] = s;
+  if (n < N)
+    for (int m = rg; m < M; m += 4) s += d[(int64_t)m * N + n];
+  part[rg][c] = s;
+  __syncthreads();
+  if (rg == 0 && n < N) out[n] = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
 }
+
+int colsum_blocks(int N) { return (N + kColsumCols - 1) / kColsumCols; }
 
 __device__ float block_reduce(float v, float *red) {
   const int t = threadIdx.x;
@@ -563,7 +572,7 @@ hipError_t backward(fire_nn *nn, const float *y_t, const uint8_t *y_map, int B, 
                        nn->gd0, nn->d0b, (int64_t)B * kDec);
     if ((e = gemm(kH, kDec, B, nn->h3b, 1, kH, nn->d0b, kDec, 1, g + L.Wd.off, kDec, nullptr, 0,
                   0, nullptr, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks_for(kDec)), dim3(256), 0, s, nn->gd0, B, kDec,
+    hipLaunchKernelGGL(colsum_kernel, dim3(colsum_blocks(kDec)), dim3(256), 0, s, nn->gd0, B, kDec,
                        g + L.cd.off);
   } else {
     hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, s, nn->loss + 1, 0.0f, (int64_t)1);
@@ -574,7 +583,7 @@ hipError_t backward(fire_nn *nn, const float *y_t, const uint8_t *y_map, int B, 
   // fitness head
   if ((e = gemm(kH, 1, B, nn->h3b, 1, kH, nn->dtb, 1, 1, g + L.Wf.off, 1, nullptr, 0, 0, nullptr,
                 s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(64), 0, s, nn->gt, B, 1, g + L.cf.off);
+  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, nn->gt, B, 1, g + L.cf.off);
   // dh3 = dt Wf^T (+ dd0 Wd^T)
   if ((e = gemm(B, kH, 1, nn->dtb, 1, 1, wb + L.Wf.off, 1, 1, nn->gh, kH, nullptr, 0, 0, nullptr,
                 s)) != hipSuccess) return e;
@@ -592,7 +601,7 @@ hipError_t backward(fire_nn *nn, const float *y_t, const uint8_t *y_map, int B, 
                        ly.act, nn->ghb, (int64_t)B * kH);
     if ((e = gemm(ly.kin, kH, B, ly.in_b, 1, ly.kin, nn->ghb, kH, 1, g + ly.W->off, kH, nullptr, 0,
                   0, nullptr, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks_for(kH)), dim3(256), 0, s, nn->gh, B, kH,
+    hipLaunchKernelGGL(colsum_kernel, dim3(colsum_blocks(kH)), dim3(256), 0, s, nn->gh, B, kH,
                        g + ly.c->off);
     if (li < 2)
       if ((e = gemm(B, kH, kH, nn->ghb, kH, 1, wb + ly.W->off, 1, kH, nn->gh, kH, nullptr, 0, 0,
