@@ -69,25 +69,59 @@ def reference_fire(g, ls, lid, centre):
     raise RuntimeError("no contained reference fire among the first 256 replicates")
 
 
-def cpu_baseline(ls, centre, ref, threads, budget_s=12.0):
-    """The oracle (plain C, binary64) on the same batch, on host threads."""
+def _oracle_pass(ls, beta, centre, n, ref, threads):
+    """One pass of the oracle over a replicate batch: thresholds, n
+    simulations, Eq. 2 (when ref is given). Returns (sims, trials)."""
     import oracle
-    sims = [dict(param=0, ign=centre, sim_index=i) for i in range(N_SIMS)]
+    sims = [dict(param=0, ign=centre, sim_index=i) for i in range(n)]
+    T = oracle.thresholds(ls, beta)
+    out = oracle.run_batch(ls["veg"], [T], sims, SIM_SEED, ref_bits=ref, threads=threads)
+    return len(out), sum(o["trials"] for o in out)
+
+
+def _time_oracle(ls, beta, centre, n, ref, threads, budget_s):
     t0 = time.perf_counter()
-    done = 0
-    trials = 0
+    done = trials = passes = 0
     while True:
-        T = oracle.thresholds(ls, BETA_STAR)
-        out = oracle.run_batch(ls["veg"], [T], sims, SIM_SEED, ref_bits=ref, threads=threads)
-        done += len(out)
-        trials += sum(o["trials"] for o in out)
+        d, t = _oracle_pass(ls, beta, centre, n, ref, threads)
+        done += d
+        trials += t
+        passes += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "sims/s", "cores": threads, "kind": "oracle",
-            "trials_per_s": trials / dt,
-            "sample": f"{done // N_SIMS} pass(es) over the full batch ({N_SIMS} replicates at "
-                      f"512x512, thresholds + simulation + Eq. 2), {dt:.1f} s"}
+    return done / dt, trials / dt, passes, dt
+
+
+def cpu_baseline(ls, centre, ref, budget_s=8.0):
+    """The oracle (plain C, binary64), on the host's cores and on one core,
+    on the calibration batch (1280 replicates at 512x512) and on the plain
+    64x64 workload (200 replicates at beta = 0)."""
+    from paper_1701_03549_amd import synth
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    # the process's CPU share: a GPU run gets at most 16 host threads
+    threads = max(1, min(16, avail))
+    v, tr, passes, dt = _time_oracle(ls, BETA_STAR, centre, N_SIMS, ref, threads, budget_s)
+    v1, tr1, passes1, dt1 = _time_oracle(ls, BETA_STAR, centre, N_SIMS, ref, 1, budget_s / 2)
+    ls64 = synth.make_landscape(64, 64, 101)
+    c64 = synth.nearest_burnable(ls64["veg"], 32, 32)
+    beta0 = (0.0, 0.0, 0.0, 0.0, 0.0)
+    w, wtr, wp, wdt = _time_oracle(ls64, beta0, c64, 200, None, threads, budget_s / 4)
+    w1, w1tr, w1p, w1dt = _time_oracle(ls64, beta0, c64, 200, None, 1, budget_s / 4)
+    return {"value": v, "unit": "sims/s", "cores": threads, "kind": "oracle",
+            "trials_per_s": tr, "host_nproc": nproc, "host_cpus_available": avail,
+            "sample": f"{passes} pass(es) over the full calibration batch ({N_SIMS} replicates at "
+                      f"512x512, thresholds + simulation + Eq. 2) on {threads} threads, {dt:.1f} s",
+            "one_core": {"value": v1, "trials_per_s": tr1,
+                         "sample": f"{passes1} pass(es) of the same batch on 1 thread, {dt1:.1f} s"},
+            "plain_64": {"workload": "64x64, seed 101, beta = 0, 200 replicates to extinction",
+                         "value": w, "trials_per_s": wtr, "cores": threads,
+                         "one_core_value": w1, "one_core_trials_per_s": w1tr,
+                         "sample": f"{wp} and {w1p} passes, {wdt:.1f} s and {w1dt:.1f} s"}}
 
 
 def pmc_profile():
@@ -507,9 +541,11 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_cpu:
-        threads = min(16, os.cpu_count() or 1)
-        log(f"CPU oracle baseline on {threads} threads ...")
-        result["cpu_baseline"] = cpu_baseline(ls, centre, ref, threads)
+        log("CPU oracle baseline (host threads, one thread; 512x512 and 64x64) ...")
+        result["cpu_baseline"] = cpu_baseline(ls, centre, ref)
+        cb = result["cpu_baseline"]
+        log(f"oracle: {cb['value']:.0f} sims/s on {cb['cores']} threads, "
+            f"{cb['one_core']['value']:.0f} on one; 64x64: {cb['plain_64']['value']:.0f}")
     if not args.no_ga:
         log("GA calibration runs ...")
         result["ga"] = run_ga(g, lid, tid, centre, plain=not args.no_plain)

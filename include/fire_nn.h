@@ -107,6 +107,14 @@ fire_status fire_pool_maps(const uint32_t *maps, int32_t n, int32_t W,
                            int32_t H, int64_t map_words, int32_t out_w,
                            int32_t out_h, uint8_t *out, void *stream);
 
+/* Building block, exposed for tests: column sums out[n] = sum_m d[m*N + n]
+ * of a row-major fp32 matrix d [M][N] (device pointers), the bias-gradient
+ * reduction of the backward pass, in a fixed order: rows m = r, r + 4,
+ * r + 8, ... are summed in order for each r = 0..3, and the four partial
+ * sums are then added as ((p0 + p1) + p2) + p3, so repeated calls give
+ * identical bits. M >= 1, N >= 1. */
+fire_status fire_colsum_f32(const float *d, int32_t M, int32_t N, float *out, void *stream);
+
 /* Screening selection for oversampled GA offspring: out [k][G] receives
  * the first `keep` rows of cand unchanged (the elites), then the k - keep
  * rows of cand[keep..n) with the lowest score, in ascending score order

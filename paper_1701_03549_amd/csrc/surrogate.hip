@@ -792,6 +792,13 @@ fire_status fire_pool_maps(const uint32_t *maps, int32_t n, int32_t W, int32_t H
   return hipGetLastError() == hipSuccess ? FIRE_OK : FIRE_E_DEVICE;
 }
 
+fire_status fire_colsum_f32(const float *d, int32_t M, int32_t N, float *out, void *stream) {
+  if (!d || !out || M < 1 || N < 1) return FIRE_E_INVALID;
+  hipLaunchKernelGGL(colsum_kernel, dim3(colsum_blocks(N)), dim3(256), 0, (hipStream_t)stream, d,
+                     M, N, out);
+  return hipGetLastError() == hipSuccess ? FIRE_OK : FIRE_E_DEVICE;
+}
+
 fire_status fire_nn_select(const double *cand, const float *score, int32_t n, int32_t G,
                            int32_t keep, int32_t k, double *out, int32_t *out_idx, void *stream) {
   if (!cand || !score || !out || n < 1 || n > 4096 || G < 1 || k < 1 || k > n || keep < 0 ||

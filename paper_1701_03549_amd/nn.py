@@ -11,7 +11,7 @@ from . import fire
 
 EXPORTS = ["fire_nn_create", "fire_nn_destroy", "fire_nn_last_error", "fire_nn_num_params",
            "fire_nn_get_params", "fire_nn_set_params", "fire_nn_forward", "fire_nn_gradients",
-           "fire_nn_train_step", "fire_gemm_bf16", "fire_pool_maps", "fire_nn_select"]
+           "fire_nn_train_step", "fire_gemm_bf16", "fire_pool_maps", "fire_nn_select", "fire_colsum_f32"]
 MAP = 128
 
 
@@ -46,6 +46,7 @@ def _lib():
                                  i64, vp, i64, vp, ctypes.c_int, ctypes.c_int, vp, vp]),
         "fire_pool_maps": (i32, [vp, i32, i32, i32, i64, i32, i32, vp, vp]),
         "fire_nn_select": (i32, [vp, vp, i32, i32, i32, i32, vp, vp, vp]),
+        "fire_colsum_f32": (i32, [vp, i32, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -81,6 +82,18 @@ def pool_maps(maps: torch.Tensor, n: int, W: int, H: int, map_words: int, out_w=
     st = lib.fire_pool_maps(_p(maps), n, W, H, map_words, out_w, out_h, _p(out), _s(stream))
     if st != 0:
         raise fire.FireError(st, "fire_pool_maps failed")
+    return out
+
+
+def colsum(d: torch.Tensor, stream=None) -> torch.Tensor:
+    """Column sums of a [M][N] fp32 device matrix in the backward pass's order."""
+    lib = _lib()
+    d = d.contiguous()
+    M, N = d.shape
+    out = torch.empty(N, dtype=torch.float32, device=d.device)
+    st = lib.fire_colsum_f32(_p(d), M, N, _p(out), _s(stream))
+    if st != 0:
+        raise fire.FireError(st, "fire_colsum_f32 failed")
     return out
 
 

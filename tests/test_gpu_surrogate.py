@@ -5,7 +5,9 @@
 * burn-map pooling against numpy;
 * loss and every parameter gradient of the whole network against the
   binary64 reference with the same bf16 rounding points (oracle/surrogate_ref),
-  tolerance derived from fp32 accumulation and bf16 re-rounding;
+  element by element, each within a tolerance derived from its own magnitude
+  product (tests/surrogate_bounds.py);
+* the bias-gradient column sums in their fixed order, exactly;
 * Adam training on a fixed batch lowers the loss.
 """
 import numpy as np
@@ -80,42 +82,88 @@ def _random_problem(B, seed, W=256, H=256):
     return x, y_t, y_map
 
 
-def test_gradients_match_reference():
+def _surrogate_instance(seed, bias_lo, bias_hi):
+    """Flat fp32 parameters: weights as initialised by the library (seed 11),
+    biases drawn in [bias_lo, bias_hi) so that most ReLUs are active."""
     import torch
     from paper_1701_03549_amd import nn
-    B, W, H = 6, 256, 256
-    net = nn.Surrogate(max_batch=64, lattice=(W, H), w_map=0.5, seed=11)
-    # biases shifted positive so that most ReLUs are active (sharper test)
+    net = nn.Surrogate(max_batch=64, lattice=(256, 256), w_map=0.5, seed=11)
     p = net.get_params().cpu().numpy().astype(np.float64)
     d = S.unflatten(p)
-    rng = np.random.default_rng(4)
+    rng = np.random.default_rng(seed)
     for k in ("c1", "c2", "c3", "cd", "k1", "k2"):
-        d[k] = rng.uniform(0.02, 0.1, size=d[k].shape)
+        d[k] = rng.uniform(bias_lo, bias_hi, size=d[k].shape)
     p = S.flatten(d).astype(np.float32)
     net.set_params(torch.from_numpy(p))
-    x, y_t, y_map = _random_problem(B, 5, W, H)
-    say("surrogate gradients")
+    return net, p
+
+
+@pytest.mark.parametrize("B,seed,blo,bhi", [(6, 4, 0.02, 0.1), (13, 8, 0.02, 0.1), (7, 9, 0.3, 0.5)])
+def test_gradients_match_reference_per_element(B, seed, blo, bhi):
+    """Every gradient element within its own tolerance (tests/surrogate_bounds:
+    a few bf16 ulps of that element's magnitude product, plus the possible
+    jumps of ReLU masks whose pre-activation is within its error of zero)."""
+    import torch
+    import surrogate_bounds as SB
+    W = H = 256
+    net, p = _surrogate_instance(seed, blo, bhi)
+    x, y_t, y_map = _random_problem(B, seed + 1, W, H)
+    say(f"surrogate gradients B={B}")
     loss, g = net.gradients(torch.from_numpy(x), torch.from_numpy(y_t),
                             torch.from_numpy(y_map).cuda())
     torch.cuda.synchronize()
-    lf, lm, gw = S.loss_and_grads(p.astype(np.float64), x, y_t, y_map, W, H, 0.5, bf16=True)
+    g_ref, tol, M = SB.gradient_tolerances(p.astype(np.float64), x, y_t, y_map, W, H, 0.5)
+    lf, lm, _ = S.loss_and_grads(p.astype(np.float64), x, y_t, y_map, W, H, 0.5, bf16=True)
     loss = loss.cpu().numpy()
     assert abs(loss[0] - lf) <= 1e-3 * abs(lf) + 1e-6
     assert abs(loss[1] - lm) <= 1e-3 * abs(lm) + 1e-6
     g = g.cpu().numpy().astype(np.float64)
     offs = np.cumsum([0] + [int(np.prod(s)) for _, s in S.layout()])
+    bad = []
     for (name, _), o0, o1 in zip(S.layout(), offs[:-1], offs[1:]):
-        a, b = g[o0:o1], gw[o0:o1]
-        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
-        # fp32 accumulation, and bf16 re-rounding of activations that land on
-        # a rounding boundary differently in fp32 and binary64
-        assert err < 2e-2, (name, err)
+        d = np.abs(g[o0:o1] - g_ref[o0:o1])
+        over = np.nonzero(d > tol[o0:o1])[0]
+        ref = np.abs(g_ref[o0:o1])
+        nz = ref > 0
+        power = float(np.mean(0.1 * ref[nz] > tol[o0:o1][nz])) if nz.any() else 0.0
+        say(f"  {name}: max |d|/tol {np.max(d / np.maximum(tol[o0:o1], 1e-300)):.3f}, "
+            f"a 10% error detectable in {power:.0%} of elements")
+        if over.size:
+            k = int(over[0])
+            bad.append(f"{name}[{k}]: gpu {g[o0 + k]!r} ref {g_ref[o0 + k]!r} tol {tol[o0 + k]:.3e}")
+    assert not bad, f"{len(bad)} tensors with elements out of tolerance: {bad[:4]}"
     # forward agrees too
     t, mp = net.forward(torch.from_numpy(x), want_map=True)
     c = S.forward(p.astype(np.float64), x, W, H, bf16=True)
     assert np.allclose(t.cpu().numpy(), c["t"], rtol=1e-2, atol=1e-3)
     assert np.allclose(mp.cpu().numpy(), 1 / (1 + np.exp(-c["z"])), atol=2e-3)
     net.close()
+
+
+@pytest.mark.parametrize("M,N", [(1, 1), (6, 256), (13, 1), (7, 2048), (5, 100), (64, 65), (4, 64)])
+def test_colsum_order_and_values(M, N):
+    """Bias-gradient column sums: integer data (every partial sum exact in
+    fp32) equals the binary64 sum exactly; random data equals the binary64
+    sum of the fixed order (rows r, r+4, ... per group r, then
+    ((p0 + p1) + p2) + p3) evaluated in fp32, bit for bit."""
+    import torch
+    from paper_1701_03549_amd import nn
+    rng = np.random.default_rng(M * 1000 + N)
+    ints = rng.integers(-1000, 1000, size=(M, N)).astype(np.float32)
+    got = nn.colsum(torch.from_numpy(ints).cuda()).cpu().numpy()
+    assert np.array_equal(got.astype(np.float64), ints.astype(np.float64).sum(axis=0))
+    x = rng.normal(size=(M, N)).astype(np.float32)
+    got = nn.colsum(torch.from_numpy(x).cuda()).cpu().numpy()
+    parts = []
+    for r in range(4):
+        acc = np.zeros(N, dtype=np.float32)
+        for m in range(r, M, 4):
+            acc = (acc + x[m]).astype(np.float32)
+        parts.append(acc)
+    want = ((parts[0] + parts[1]).astype(np.float32) + parts[2]).astype(np.float32) + parts[3]
+    assert np.array_equal(got, want.astype(np.float32))
+    np.testing.assert_allclose(got, x.astype(np.float64).sum(axis=0),
+                               rtol=0, atol=1e-5 * np.abs(x).sum(axis=0).max())
 
 
 def test_training_lowers_loss():
