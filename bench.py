@@ -511,6 +511,31 @@ def main():
         f"{trials / N_SIMS:.1f}")
 
     prof = pmc_profile()
+    wave = bool(sched.get("wave"))
+    kname = "simw_kernel" if wave else "sim_kernel"
+    log("probing the hardware ceilings ...")
+    from paper_1701_03549_amd import probe
+    ceil = probe.measure()
+    # the ceilings this launch meets, each as the fraction of the measured
+    # kernel time it explains
+    sim_s = sim_ms * 1e-3
+    units = 2 * burnt  # Philox evaluations the simulations need (2 per burning cell)
+    # one step's dependent chain: queue entry (LDS), then the threshold load
+    # (L2) alongside the Philox evaluation, then the bit atomics and the
+    # append (LDS); plus a workgroup barrier per phase for sim_kernel
+    lds = ceil["lds_atomic_ns"]
+    step_ns = lds + max(ceil["l2_load_ns"], ceil["philox_ns"]) + 2 * lds
+    if not wave:
+        step_ns += 2 * ceil["barrier_ns"]
+    max_steps = int(r["steps"].max())
+    fractions = {
+        "hbm": alg_bytes / sim_s / 1e9 / HBM_PEAK_GBS,
+        "l2": alg_bytes / sim_s / 1e9 / ceil["l2_read_gbs"],
+        "alu": units / sim_s / ceil["philox_calls_per_s"],
+        "latency": max_steps * step_ns * 1e-9 / sim_s,
+    }
+    binding = max(fractions, key=fractions.get)
+    log(f"ceilings: {ceil}; fractions {fractions} -> {binding}")
     result = {
         "metric": METRIC, "value": sims_per_s, "unit": "sims/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -524,20 +549,33 @@ def main():
                    "ignition": list(centre), "schedule": sched, "threshold_mode": "table"},
         "trials_per_s": trials_per_s,
         "mean_burnt": burnt / N_SIMS, "mean_trials": trials / N_SIMS,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": prof.get("hbm_bytes_per_launch") if prof else None,
-                     "issue": ({k: prof["sq"][k] for k in ("valu_busy_frac", "wave_busy_frac",
-                                                         "wave_wait_frac",
-                                                         "wave_issue_wait_frac")}
-                               if prof and "sq" in prof else None),
-                     "kernel": "sim_kernel", "kernel_ms": sim_ms,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "limiter": "the chain of dependent CA steps (Philox, threshold load, LDS "
-                                "round trips, two barriers per step; about 180 steps per "
-                                "simulation) and, with 5 simulations per CU, VALU issue "
-                                "('issue': SQ counters of the same kernel); not HBM "
-                                "bandwidth: traffic is under 2% of the algorithmic bytes"},
+        "roofline": {
+            "bound": binding,
+            **({"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"} if binding == "hbm" else
+               {"achieved": alg_bytes / sim_s / 1e9, "peak": ceil["l2_read_gbs"], "unit": "GB/s"}
+               if binding == "l2" else
+               {"achieved": units / sim_s / 1e9, "peak": ceil["philox_calls_per_s"] / 1e9,
+                "unit": "G Philox calls/s"} if binding == "alu" else
+               {"achieved": max_steps * step_ns * 1e-6, "peak": sim_ms, "unit": "ms (chain of "
+                "dependent steps vs kernel time)"}),
+            "frac": fractions[binding],
+            "traffic": prof.get("hbm_bytes_per_launch") if prof else None,
+            "fractions": fractions,
+            "hbm": {"achieved_gbs": achieved, "peak_gbs": HBM_PEAK_GBS,
+                    "measured_read_gbs": ceil["hbm_read_gbs"]},
+            "l2": {"peak_gbs": ceil["l2_read_gbs"], "mall_gbs": ceil["mall_read_gbs"]},
+            "alu": {"philox_calls_per_launch": units, "trials_per_call": trials / units,
+                    "peak_calls_per_s": ceil["philox_calls_per_s"],
+                    "lane_slots_per_call": 256 * 2.4e9 * 64 / ceil["philox_calls_per_s"]},
+            "latency": {"max_steps": max_steps, "step_floor_ns": step_ns,
+                        "components_ns": {k: ceil[k] for k in ("barrier_ns", "l2_load_ns",
+                                                               "lds_atomic_ns", "philox_ns")}},
+            "issue": ({k: prof["sq"][k] for k in ("valu_busy_frac", "wave_busy_frac",
+                                                "wave_wait_frac", "wave_issue_wait_frac")}
+                      if prof and "sq" in prof else None),
+            "kernel": kname, "kernel_ms": sim_ms,
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
         "cpu_baseline": None,
     }
     if not args.no_cpu:

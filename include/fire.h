@@ -170,11 +170,13 @@ typedef struct {
  * Simulations are grouped by landscape (by size when more than 8
  * landscapes are used) and each group runs as its own persistent launch
  * with LDS sized for it; groups run concurrently on internal streams
- * forked from and joined back to `stream` (capturable). Results do not
- * depend on the schedule (threads, queue sizes, threshold mode), the
- * grouping or the order in which simulations run. Stream-ordered; calls
- * on one context must not overlap on different streams (they share
- * staging and scratch buffers). */
+ * forked from and joined back to `stream`. Results do not depend on the
+ * schedule (threads, queue sizes, threshold mode), the grouping or the
+ * order in which simulations run. Stream-ordered; calls on one context
+ * must not overlap on different streams (they share staging and scratch
+ * buffers). Not for stream capture: descriptors are staged through pinned
+ * host memory that a graph would read at replay time, so under capture
+ * this returns FIRE_E_UNSUPPORTED (use fire_run_dev). */
 fire_status fire_run(fire_ctx *ctx, const double *betas, int32_t n_params,
                      const fire_sim *sims, int32_t n_sims, uint64_t seed,
                      const uint32_t *thresholds_override, fire_result *out,
@@ -201,9 +203,18 @@ fire_status fire_run_dense(fire_ctx *ctx, const double *betas, int32_t n_params,
                            int64_t map_words, void *stream);
 
 /* As fire_run, with betas and sims already in device memory (no host
- * staging; usable under stream capture). Descriptors are checked on the
- * device: an invalid one yields {0, 0xFFFFFFFF, 0, NaN} and makes the next
- * fire_sync() return FIRE_E_INVALID. */
+ * staging). Descriptors are checked on the device: an invalid one yields
+ * {0, 0xFFFFFFFF, 0, NaN} and makes the next fire_sync() return
+ * FIRE_E_INVALID.
+ * Stream capture: allowed once an identical call (same landscapes, batch
+ * size and schedule) has run eagerly on this context, so that every
+ * context scratch buffer (frontier spill area, retry list, threshold
+ * tables) is already large enough; a call that would have to grow one
+ * during capture returns FIRE_E_UNSUPPORTED. After a capture, buffers that
+ * later calls outgrow are kept allocated (not freed) until
+ * fire_ctx_destroy, so a captured graph stays valid for the context's
+ * lifetime. Replays share the context's scratch with eager calls: keep
+ * them stream-ordered with every other call on the context. */
 fire_status fire_run_dev(fire_ctx *ctx, const double *betas_dev,
                          int32_t n_params, const fire_sim *sims_dev,
                          int32_t n_sims, uint64_t seed,
@@ -229,17 +240,33 @@ typedef struct {
                             (same coins, so the same result); smaller LDS
                             footprints keep more simulations resident.
                             Ignored (whole lattice) with 1024 threads.    */
+  int32_t wave;          /* 0: one simulation per workgroup of `threads`
+                            lanes; 1: one simulation per 64-lane wavefront
+                            (threads and wg_per_cu ignored) with its
+                            frontier queues held in LDS only (queue_cap
+                            entries each): its steps need no workgroup
+                            barrier and draw coins only for units with an
+                            eligible edge; a fire whose front outgrows
+                            queue_cap (or a window) is run again by the
+                            workgroup kernel over the whole lattice, with
+                            the same coins and so the same result. The
+                            built-in choice uses it for batches of at most
+                            8 parameter vectors without turn-off times
+                            while such re-runs stay absent.               */
 } fire_schedule;
 
 /* Fix the schedule used by later fire_run/fire_run_dev calls; NULL
  * restores the built-in choice. FIRE_E_INVALID when a field is out of
  * range or the LDS budget cannot hold it. */
 fire_status fire_set_schedule(fire_ctx *ctx, const fire_schedule *s);
-/* Schedule for one size class: runs whose landscapes have between
- * 2^(b-1)+1 and 2^b cells, b = ceil(log2(max_cells)), use `s` unless a
- * fixed schedule is set. NULL removes the class entry. Used by the
+/* Schedule for one size class and kind of batch: runs whose landscapes
+ * have between 2^(b-1)+1 and 2^b cells, b = ceil(log2(max_cells)), and
+ * (many_params = 0) at most 8 parameter vectors, as replicate batches have,
+ * or (many_params = 1) more, as GA populations and Monte Carlo draws have,
+ * use `s` unless a fixed schedule is set; its window and wave fields may be
+ * -1 (built-in choice). NULL removes the class entry. Used by the
  * autotuner. */
-fire_status fire_set_class_schedule(fire_ctx *ctx, int64_t max_cells,
+fire_status fire_set_class_schedule(fire_ctx *ctx, int64_t max_cells, int32_t many_params,
                                     const fire_schedule *s);
 /* The schedule a batch of `n_sims` simulations with `n_params` parameter
  * vectors on a square lattice of `max_cells` cells would use (window: the

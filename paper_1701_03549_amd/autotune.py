@@ -5,8 +5,9 @@ candidate schedule (threads per workgroup, workgroups per compute unit,
 LDS queue capacity, threshold table vs per-trial evaluation) with HIP
 events on the launch stream, checks that every schedule returns bit-identical
 results (they must: results do not depend on the schedule), and keeps the
-fastest. Choices are cached per GPU architecture and size class in a JSON
-file and applied through fire_set_class_schedule.
+fastest. Choices are cached per GPU architecture, size class and kind of
+batch (at most 8 parameter vectors, or more) in a JSON file committed beside
+this module, and applied through fire_set_class_schedule.
 
     python -m paper_1701_03549_amd.autotune            # tune the built-in workloads
 """
@@ -38,18 +39,24 @@ def cells_bucket(cells: int) -> int:
 
 
 def candidates(table_ok: bool, side: int = 0):
-    """Schedules to time: workgroup size x workgroups per CU x LDS queue
-    capacity x threshold mode x LDS window (none, or a quarter, half and
-    three quarters of the lattice side, when that is at least 64 cells)."""
+    """Schedules to time. One simulation per workgroup: workgroup size x
+    workgroups per CU x LDS queue capacity x threshold mode x LDS window
+    (none, or a quarter, half and three quarters of the lattice side, when
+    that is at least 64 cells). One simulation per wavefront: LDS queue
+    capacity x threshold mode x the same windows."""
     windows = [0] + sorted({w for w in (side // 4, side // 2, 3 * side // 4)
                             if w >= 64 and w % 32 == 0 and w < side})
+    tables = (0, 1) if table_ok else (0,)
     for threads, wg, qcap, win in itertools.product((128, 256, 512, 1024), (1, 2, 4, 5, 8),
                                                     (1024, 4096), windows):
         if threads > 512 and win > 0:
             continue  # the library runs 1024-thread schedules without a window
-        for table in ((0, 1) if table_ok else (0,)):
+        for table in tables:
             yield {"threads": threads, "queue_cap": qcap, "table_mode": table, "wg_per_cu": wg,
-                   "window": win}
+                   "window": win, "wave": 0}
+    for qcap, win, table in itertools.product((256, 512, 1024), windows, tables):
+        yield {"threads": 64, "queue_cap": qcap, "table_mode": table, "wg_per_cu": 1,
+               "window": win, "wave": 1}
 
 
 def time_schedule(g: fire.FireGPU, sched, d_beta, d_sims, n, seed, out, reps=3):
@@ -105,12 +112,19 @@ def load_cache(path: str = CACHE) -> dict:
     return {}
 
 
+KINDS = {"replicate": False, "many": True}
+
+
 def apply_cache(g: fire.FireGPU, path: str = CACHE) -> int:
-    """Install the cached schedules of this architecture; returns how many."""
+    """Install the cached schedules of this architecture (per size class and
+    batch kind: at most 8 parameter vectors, or more); returns how many."""
     entries = load_cache(path).get(arch_name(), {})
-    for bucket, e in entries.items():
-        g.set_class_schedule(1 << int(bucket), e["schedule"])
-    return len(entries)
+    n = 0
+    for bucket, kinds in entries.items():
+        for kind, e in kinds.items():
+            g.set_class_schedule(1 << int(bucket), e["schedule"], many_params=KINDS[kind])
+            n += 1
+    return n
 
 
 def workloads():
@@ -136,7 +150,6 @@ def main():
     cache = load_cache(args.out)
     arch = arch_name()
     mine = cache.setdefault(arch, {})
-    best_by_bucket = {}
     for W, H, seed, betas, n in workloads():
         if args.only and args.only != f"{W}x{H}":
             continue
@@ -144,20 +157,17 @@ def main():
         lid = g.load_landscape(ls)
         c = synth.ignition_site(ls)
         sims = fire.make_sims(n, lid, -1, c, param_index=np.arange(n) % len(betas))
-        log(f"{W}x{H}, {len(betas)} parameter vector(s), {n} simulations")
+        kind = "many" if len(betas) > 8 else "replicate"
+        log(f"{W}x{H}, {len(betas)} parameter vector(s), {n} simulations ({kind})")
         best, rows = tune(g, lid, sims, betas, 0x5EED0001, log=log)
         b = str(cells_bucket(W * H))
-        # keep the schedule that is best for the random-parameter batch when both
-        # kinds were tuned (it dominates GA and Monte Carlo workloads)
-        best_by_bucket.setdefault(b, {})[("table" if len(betas) == 1 else "random")] = (
-            best, rows[0][0])
+        mine.setdefault(b, {})[kind] = {"schedule": best, "ms": rows[0][0],
+                                        "lattice": [W, H], "sims": n,
+                                        "runner_up": rows[1][1] if len(rows) > 1 else None,
+                                        "runner_up_ms": rows[1][0] if len(rows) > 1 else None}
         g.free_landscape(lid)
-    for b, kinds in best_by_bucket.items():
-        best, ms = kinds.get("random", kinds.get("table"))
-        mine[b] = {"schedule": best, "ms": ms,
-                   "replicate_batch": kinds.get("table", (None, None))[0]}
-    with open(args.out, "w") as f:
-        json.dump(cache, f, indent=1, sort_keys=True)
+        with open(args.out, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
     log(f"wrote {args.out}")
     g.close()
 

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfiregpu.so")
 SOURCES = [os.path.join(CSRC, "fire_kernels.hip"), os.path.join(CSRC, "fire_abi.cpp"),
-           os.path.join(CSRC, "surrogate.hip")]
+           os.path.join(CSRC, "surrogate.hip"), os.path.join(CSRC, "probe.hip")]
 ARCH = os.environ.get("FIREGPU_ARCH", "gfx950")
 
 

@@ -86,8 +86,14 @@ struct fire_ctx {
   // fixed schedule (autotuner) or built-in choice
   bool sched_fixed = false;
   fire_schedule sched{};
-  // per size-class schedules (autotuner): log2 bucket of max_cells -> schedule
-  std::vector<std::pair<int, fire_schedule>> class_sched;
+  // per size-class schedules (autotuner): (log2 bucket of max_cells, more
+  // than kWindowMaxParams parameter vectors) -> schedule
+  struct ClassSched {
+    int bucket;
+    int many;
+    fire_schedule s;
+  };
+  std::vector<ClassSched> class_sched;
   // side streams and events for running size classes concurrently
   hipStream_t side[7] = {};
   hipEvent_t fork_ev = nullptr;
@@ -99,6 +105,12 @@ struct fire_ctx {
   uint8_t *d_dense = nullptr;
   size_t dense_bytes = 0;
   unsigned long long *h_dense = nullptr;
+  // set once a simulation launch has been recorded into a stream capture:
+  // from then on a scratch buffer that a later call outgrows is retired
+  // (kept allocated until the context is destroyed) instead of freed, so
+  // that captured graphs never address freed memory
+  bool captured = false;
+  std::vector<void *> retired;
 };
 
 namespace {
@@ -145,6 +157,37 @@ hipError_t ensure(void **p, size_t *have, size_t want) {
   return e;
 }
 
+bool stream_capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
+// Grow a context scratch buffer to `want` bytes. Never during a stream
+// capture (the graph would keep the address of a buffer a later call could
+// replace): the caller gets FIRE_E_UNSUPPORTED and should run the same call
+// once eagerly first. Once anything has been captured, the old buffer is
+// retired rather than freed.
+fire_status grow(fire_ctx *c, void **p, size_t *have, size_t want, hipStream_t st,
+                 const char *what) {
+  if (*have >= want && *p) return FIRE_OK;
+  if (stream_capturing(st))
+    return fail(c, FIRE_E_UNSUPPORTED,
+                "%s would grow from %zu to %zu bytes during stream capture; run the same call "
+                "once without capture first", what, *have, want);
+  HIP_OR_FAIL(c, hipDeviceSynchronize());
+  if (*p && c->captured) {
+    c->retired.push_back(*p);
+    *p = nullptr;
+    *have = 0;
+  }
+  HIP_OR_FAIL(c, ensure(p, have, want));
+  return FIRE_OK;
+}
+
 fire_status sync_tables(fire_ctx *c) {
   // mirror the landscape and target tables on the device
   int nl = (int)c->ls.size(), nt = (int)c->tg.size();
@@ -170,14 +213,16 @@ fire_status sync_tables(fire_ctx *c) {
   }
   if (nl > c->d_ls_cap || !c->d_ls) {
     int cap = nl < 16 ? 16 : nl * 2;
-    if (c->d_ls) HIP_OR_FAIL(c, hipFree(c->d_ls));
+    if (c->d_ls && c->captured) c->retired.push_back(c->d_ls);
+    else if (c->d_ls) HIP_OR_FAIL(c, hipFree(c->d_ls));
     c->d_ls = nullptr;
     HIP_OR_FAIL(c, hipMalloc(&c->d_ls, sizeof(LandscapeDev) * cap));
     c->d_ls_cap = cap;
   }
   if (nt > c->d_tg_cap || !c->d_tg) {
     int cap = nt < 16 ? 16 : nt * 2;
-    if (c->d_tg) HIP_OR_FAIL(c, hipFree(c->d_tg));
+    if (c->d_tg && c->captured) c->retired.push_back(c->d_tg);
+    else if (c->d_tg) HIP_OR_FAIL(c, hipFree(c->d_tg));
     c->d_tg = nullptr;
     HIP_OR_FAIL(c, hipMalloc(&c->d_tg, sizeof(TargetDev) * cap));
     c->d_tg_cap = cap;
@@ -297,11 +342,13 @@ fire_schedule default_schedule(fire_ctx *c, int64_t max_cells,
     }
   }
   best.window = 0;
+  best.wave = 0;
   return best;
 }
 
 struct RunPlan {
   fire_schedule s;
+  bool wave;  // first launch: one simulation per wavefront (simw_kernel)
   bool dur;  // some landscape of the launch has turn-off times
   int bitset_words;
   int64_t max_cells;
@@ -328,6 +375,9 @@ constexpr int kMinAutoQueue = 1024;      // LDS queue entries a built-in window 
 // Carlo draws) some fires outgrow any window and their repeats, which start
 // only after the window launch ends, cost more than the residency gains.
 constexpr int kWindowMaxParams = 8;
+// LDS queue entries of a built-in wavefront-per-simulation plan (fires whose
+// front exceeds it are run again by the workgroup kernel)
+constexpr int kWaveQueue = 512;
 
 // LDS, queue and residency of one launch shape; false if it cannot fit.
 bool shape_launch(fire_ctx *c, fire_schedule &s, int bitset_words, bool dur, bool win,
@@ -360,12 +410,14 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
                      RunPlan *out, bool dur = false, float win_frac = 0.f) {
   fire_schedule s = default_schedule(c, max_cells, bitset_words, n_params, dur, n_sims);
   s.window = -1;  // built-in: decide below
+  s.wave = -1;
   if (c->sched_fixed) {
     s = c->sched;
   } else {
     const int b = cells_bucket(max_cells);
+    const int many = n_params > kWindowMaxParams ? 1 : 0;
     for (const auto &e : c->class_sched)
-      if (e.first == b) s = e.second;
+      if (e.bucket == b && e.many == many) s = e.s;
   }
   if (!table_allowed) s.table_mode = 0;
   fire_schedule full = s;
@@ -378,7 +430,9 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
                 lds_bytes_for(bitset_words, full.queue_cap, dur), bitset_words, full.queue_cap,
                 c->max_lds);
   full.window = 0;
+  full.wave = 0;
   out->s = full;
+  out->wave = false;
   out->dur = dur;
   out->bitset_words = bitset_words;
   out->max_cells = max_cells;
@@ -402,6 +456,75 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
     ws.table_mode = full.table_mode;
     return shape_launch(c, ws, wbw, dur, true, n_sims, wl, wg);
   };
+  // wavefront-per-simulation plan: asked for by the schedule, or (built-in)
+  // for batches of a few parameter vectors without turn-off times while no
+  // run on these landscapes has had to be repeated
+  const bool want_wave = !dur && (s.wave == 1 || (s.window < 0 && s.wave < 0 &&
+                                                  win_frac <= kWindowRetryMax &&
+                                                  n_params <= kWindowMaxParams));
+  if (want_wave) {
+    const int qcap = s.wave == 1 ? s.queue_cap : kWaveQueue;
+    auto wave_shape = [&](int side, size_t *wl, int *wg) -> bool {
+      const int wbw = side > 0 ? std::min(side, max_h) * std::min(side / 32, max_stride)
+                               : bitset_words;
+      const size_t lds = simw_lds_bytes(wbw, qcap);
+      if (lds > c->max_lds || simw_scratch_bytes(full.table_mode != 0, side > 0) > 0)
+        return false;
+      const int occ = simw_occupancy(full.table_mode != 0, side > 0, lds);
+      if (occ < 1) return false;
+      *wl = lds;
+      *wg = (int)std::min<int64_t>((int64_t)occ * c->num_cu, n_sims);
+      return true;
+    };
+    int wside = -1;
+    size_t wl = 0;
+    int wg = 0;
+    if (s.wave == 1 && s.window >= 0) {
+      wside = s.window;
+      if (!wave_shape(wside, &wl, &wg))
+        return fail(c, FIRE_E_UNSUPPORTED, "wave schedule (window %d, queue_cap %d) does not fit",
+                    s.window, qcap);
+    } else {
+      // the whole lattice if every simulation of the batch is then
+      // resident, else the largest window that makes them resident (or,
+      // failing that, keeps the most resident)
+      int best_wg = -1;
+      size_t l0;
+      int g0;
+      if (wave_shape(0, &l0, &g0)) {
+        wside = 0; wl = l0; wg = g0; best_wg = g0;
+      }
+      const int top = std::max(max_h, 32 * max_stride);
+      for (int side = (top / 32) * 32; side >= 64 && best_wg < std::min(n_sims, c->num_cu * kMaxPerCu);
+           side -= 32) {
+        if (std::min(side, max_h) * std::min(side / 32, max_stride) >= bitset_words) continue;
+        if (wave_shape(side, &l0, &g0) && g0 > best_wg) {
+          wside = side; wl = l0; wg = g0; best_wg = g0;
+          if (g0 >= n_sims) break;
+        }
+      }
+    }
+    if (wside >= 0) {
+      fire_schedule ws = full;
+      ws.threads = 64;
+      ws.queue_cap = qcap;
+      ws.wg_per_cu = 1;
+      ws.window = wside;
+      ws.wave = 1;
+      out->s2 = full;
+      out->bitset_words2 = bitset_words;
+      out->lds2 = lds;
+      out->grid2 = std::min(grid, c->num_cu);
+      out->s = ws;
+      out->wave = true;
+      out->bitset_words = wside > 0 ? std::min(wside, max_h) * std::min(wside / 32, max_stride)
+                                    : bitset_words;
+      out->lds = wl;
+      out->grid = wg;
+      out->win = wside;
+      return FIRE_OK;
+    }
+  }
   int win = 0;
   if (s.window > 0) {
     win = s.window;
@@ -434,6 +557,7 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
   // spilling variants are slow enough that residency gains nothing)
   if (sim_scratch_bytes(ws.threads, ws.table_mode != 0, dur, true) > 0) return FIRE_OK;
   ws.window = win;
+  ws.wave = 0;
   out->s2 = full;
   out->bitset_words2 = bitset_words;
   out->lds2 = lds;
@@ -459,29 +583,29 @@ int64_t spill_words_one(int64_t max_cells, int queue_cap, int grid, bool dur) {
 }
 
 int64_t spill_words(const RunPlan &p) {
-  int64_t w = spill_words_one(p.max_cells, p.s.queue_cap, p.grid, p.dur);
-  if (p.win > 0) w = std::max(w, spill_words_one(p.max_cells, p.s2.queue_cap, p.grid2, p.dur));
+  // the wavefront kernel keeps its queues in LDS only
+  int64_t w = p.wave ? 0 : spill_words_one(p.max_cells, p.s.queue_cap, p.grid, p.dur);
+  if (p.win > 0 || p.wave)
+    w = std::max(w, spill_words_one(p.max_cells, p.s2.queue_cap, p.grid2, p.dur));
   return w;
 }
 
 // Retry lists of window runs: `words` words (waits for the device when it grows).
-fire_status ensure_retry(fire_ctx *c, int64_t words) {
-  if ((size_t)words <= c->retry_words && c->d_retry) return FIRE_OK;
-  HIP_OR_FAIL(c, hipDeviceSynchronize());
+fire_status ensure_retry(fire_ctx *c, int64_t words, hipStream_t st) {
   size_t have = c->retry_words * sizeof(uint32_t);
-  HIP_OR_FAIL(c, ensure((void **)&c->d_retry, &have, (size_t)words * sizeof(uint32_t)));
+  fire_status r = grow(c, (void **)&c->d_retry, &have, (size_t)words * sizeof(uint32_t), st,
+                       "the retry list");
   c->retry_words = have / sizeof(uint32_t);
-  return FIRE_OK;
+  return r;
 }
 
 // Make the spill area hold `words` entries (waits for the device when it grows).
-fire_status ensure_spill(fire_ctx *c, int64_t words) {
-  if ((size_t)words <= c->ovf_words && c->d_ovf) return FIRE_OK;
-  HIP_OR_FAIL(c, hipDeviceSynchronize());
+fire_status ensure_spill(fire_ctx *c, int64_t words, hipStream_t st) {
   size_t have = c->ovf_words * sizeof(uint32_t);
-  HIP_OR_FAIL(c, ensure((void **)&c->d_ovf, &have, (size_t)words * sizeof(uint32_t)));
+  fire_status r = grow(c, (void **)&c->d_ovf, &have, (size_t)words * sizeof(uint32_t), st,
+                       "the frontier spill area");
   c->ovf_words = have / sizeof(uint32_t);
-  return FIRE_OK;
+  return r;
 }
 
 // Fold finished retry-count copies into the landscapes' re-run shares.
@@ -551,19 +675,24 @@ fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
                        int32_t table_ls, fire_result *out, uint32_t *out_maps,
                        int64_t map_words, int counter, uint32_t *spill, uint32_t *retry,
                        hipStream_t st, int stat_lid = -1) {
+  uint32_t *const wb = c->d_work;
   SimArgs a = sim_args(c, betas_dev, n_params, sims_dev, order, n_sims, seed, tables,
                        table_stride, table_ls, out, out_maps, map_words, p.max_cells,
-                       p.s.queue_cap, p.grid, p.dur, p.bitset_words, c->d_work + counter, spill);
-  if (p.win > 0 && !retry) return fail(c, FIRE_E_INVALID, "window plan without a retry list");
-  uint32_t *const work2 = p.win > 0 ? c->d_work + counter + kMaxClasses : nullptr;
+                       p.s.queue_cap, p.grid, p.dur, p.bitset_words, wb + counter, spill);
+  const bool two = p.win > 0 || p.wave;  // a second, whole-lattice launch for repeats
+  if (two && !retry) return fail(c, FIRE_E_INVALID, "window plan without a retry list");
+  uint32_t *const work2 = two ? wb + counter + kMaxClasses : nullptr;
   // the launches' work counters and the retry count, in one launch
-  HIP_OR_FAIL(c, launch_zero_words(a.work, work2, p.win > 0 ? retry : nullptr, st));
-  if (p.win > 0) {
+  HIP_OR_FAIL(c, launch_zero_words(a.work, work2, two ? retry : nullptr, st));
+  if (two) {
     a.win = p.win;
     a.retry = retry;
   }
-  HIP_OR_FAIL(c, launch_sim(a, p.s.threads, tables != nullptr, p.dur, p.grid, p.lds, st));
-  if (p.win > 0) {
+  if (p.wave)
+    HIP_OR_FAIL(c, launch_simw(a, tables != nullptr, p.grid, p.lds, st));
+  else
+    HIP_OR_FAIL(c, launch_sim(a, p.s.threads, tables != nullptr, p.dur, p.grid, p.lds, st));
+  if (two) {
     SimArgs b = sim_args(c, betas_dev, n_params, sims_dev, retry + 1, n_sims, seed, tables,
                          table_stride, table_ls, out, out_maps, map_words, p.max_cells,
                          p.s2.queue_cap, p.grid2, p.dur, p.bitset_words2, work2, spill);
@@ -658,6 +787,7 @@ void fire_ctx_destroy(fire_ctx *c) {
   for (int i = 0; i < fire_ctx::kStatSlots; ++i)
     if (c->stat_ev[i]) (void)hipEventDestroy(c->stat_ev[i]);
   if (c->d_tables) (void)hipFree(c->d_tables);
+  for (void *p : c->retired) (void)hipFree(p);
   if (c->d_stage) (void)hipFree(c->d_stage);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->d_ga) (void)hipFree(c->d_ga);
@@ -924,17 +1054,14 @@ static fire_status check_sims_host(fire_ctx *c, const fire_sim *sims, int32_t n,
 // scratch, computed on the stream right before the simulations.
 // Room for n_params threshold tables of landscape lid (waits for the device
 // when it grows).
-static fire_status ensure_tables(fire_ctx *c, int lid, int32_t n_params) {
+static fire_status ensure_tables(fire_ctx *c, int lid, int32_t n_params, hipStream_t st) {
   const LandscapeHost &L = c->ls[lid];
   const int64_t per = (int64_t)L.W * L.H * 8;
   const size_t need = sizeof(uint32_t) * (size_t)per * n_params;
-  if (need > c->tables_words * sizeof(uint32_t)) {
-    HIP_OR_FAIL(c, hipDeviceSynchronize());
-    size_t have = c->tables_words * sizeof(uint32_t);
-    HIP_OR_FAIL(c, ensure((void **)&c->d_tables, &have, need));
-    c->tables_words = have / sizeof(uint32_t);
-  }
-  return FIRE_OK;
+  size_t have = c->tables_words * sizeof(uint32_t);
+  fire_status r = grow(c, (void **)&c->d_tables, &have, need, st, "the threshold tables");
+  c->tables_words = have / sizeof(uint32_t);
+  return r;
 }
 
 // Table-mode thresholds: one table per parameter vector into context
@@ -942,7 +1069,7 @@ static fire_status ensure_tables(fire_ctx *c, int lid, int32_t n_params) {
 static fire_status build_tables(fire_ctx *c, int lid, const double *betas_dev,
                                 int32_t n_params, hipStream_t st,
                                 const uint32_t **tables, int64_t *stride) {
-  fire_status es = ensure_tables(c, lid, n_params);
+  fire_status es = ensure_tables(c, lid, n_params, st);
   if (es != FIRE_OK) return es;
   const LandscapeHost &L = c->ls[lid];
   const int64_t per = (int64_t)L.W * L.H * 8;
@@ -974,6 +1101,10 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
     return fail(c, FIRE_E_INVALID, "thresholds_override must be 16-byte aligned");
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
+  if (stream_capturing(st))
+    return fail(c, FIRE_E_UNSUPPORTED,
+                "fire_run stages host descriptors through pinned memory, which a captured "
+                "graph would read at replay time; use fire_run_dev under stream capture");
 
   // Size classes: simulations grouped by landscape (by size when there are
   // more landscapes than concurrent launches), each class run by its own
@@ -1032,7 +1163,7 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
     if (ps != FIRE_OK) return ps;
     spill_total += spill_words(plans[k]);
   }
-  fire_status ss = ensure_spill(c, spill_total);
+  fire_status ss = ensure_spill(c, spill_total, st);
   if (ss != FIRE_OK) return ss;
   // retry lists: class k at retry_start[k], 1 + |class| words
   std::vector<int64_t> retry_start(n_cls, 0);
@@ -1041,7 +1172,7 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
     retry_start[k] = retry_total;
     retry_total += 1 + (int64_t)members[k].size();
   }
-  fire_status rs = ensure_retry(c, retry_total);
+  fire_status rs = ensure_retry(c, retry_total, st);
   if (rs != FIRE_OK) return rs;
 
   // stage descriptors, parameters and class member lists
@@ -1136,7 +1267,11 @@ fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
   int64_t mc = 1;
   bool any_dur = false;
   float frac = 0.f;
-  harvest_stats(c);
+  // under capture: no event queries, no buffer growth; every buffer the
+  // graph records stays allocated for the context's lifetime
+  const bool capturing = stream_capturing((hipStream_t)stream);
+  if (capturing) c->captured = true;
+  else harvest_stats(c);
   for (size_t i = 0; i < c->ls.size(); ++i) {
     const LandscapeHost &L = c->ls[i];
     if (!L.live) continue;
@@ -1160,9 +1295,9 @@ fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
   fire_status ps =
       plan_run(c, bw, mc, mh, ms, n_params, n_sims, nlive == 1, &plan, any_dur, frac);
   if (ps != FIRE_OK) return ps;
-  fire_status ss = ensure_spill(c, spill_words(plan));
+  fire_status ss = ensure_spill(c, spill_words(plan), st);
   if (ss != FIRE_OK) return ss;
-  fire_status rs = ensure_retry(c, 1 + (int64_t)n_sims);
+  fire_status rs = ensure_retry(c, 1 + (int64_t)n_sims, st);
   if (rs != FIRE_OK) return rs;
   const uint32_t *tables = override_T;
   int64_t tstride = 0;
@@ -1254,24 +1389,28 @@ fire_status fire_run_dense(fire_ctx *c, const double *betas, int32_t n_params,
   return FIRE_OK;
 }
 
-fire_status fire_set_class_schedule(fire_ctx *c, int64_t max_cells, const fire_schedule *s) {
+fire_status fire_set_class_schedule(fire_ctx *c, int64_t max_cells, int32_t many_params,
+                                    const fire_schedule *s) {
   if (!c) return FIRE_E_INVALID;
   if (max_cells < 1) return fail(c, FIRE_E_INVALID, "max_cells < 1");
+  if (many_params != 0 && many_params != 1)
+    return fail(c, FIRE_E_INVALID, "many_params must be 0 or 1");
   const int b = cells_bucket(max_cells);
+  if (s) {
+    if (!valid_threads(s->threads))
+      return fail(c, FIRE_E_INVALID, "threads must be 64, 128, 256, 512 or 1024");
+    if (s->queue_cap < 64 || s->wg_per_cu < 1 || s->wg_per_cu > 32 ||
+        (s->table_mode != 0 && s->table_mode != 1) || !valid_window(s->window) ||
+        s->wave < -1 || s->wave > 1)
+      return fail(c, FIRE_E_INVALID, "schedule field out of range");
+  }
   for (size_t i = 0; i < c->class_sched.size(); ++i)
-    if (c->class_sched[i].first == b) {
-      if (s) c->class_sched[i].second = *s;
+    if (c->class_sched[i].bucket == b && c->class_sched[i].many == many_params) {
+      if (s) c->class_sched[i].s = *s;
       else c->class_sched.erase(c->class_sched.begin() + i);
       return FIRE_OK;
     }
-  if (!s) return FIRE_OK;
-  if (s->threads != 64 && s->threads != 128 && s->threads != 256 && s->threads != 512 &&
-      s->threads != 1024)
-    return fail(c, FIRE_E_INVALID, "threads must be 64, 128, 256, 512 or 1024");
-  if (s->queue_cap < 64 || s->wg_per_cu < 1 || s->wg_per_cu > 32 ||
-      (s->table_mode != 0 && s->table_mode != 1) || !valid_window(s->window))
-    return fail(c, FIRE_E_INVALID, "schedule field out of range");
-  c->class_sched.push_back({b, *s});
+  if (s) c->class_sched.push_back({b, many_params, *s});
   return FIRE_OK;
 }
 
@@ -1283,8 +1422,10 @@ fire_status fire_set_schedule(fire_ctx *c, const fire_schedule *s) {
   }
   if (!valid_threads(s->threads) || s->queue_cap < 64 || s->wg_per_cu < 1 ||
       s->wg_per_cu > 32 || (s->table_mode != 0 && s->table_mode != 1) ||
-      !valid_window(s->window))
+      !valid_window(s->window) || s->wave < -1 || s->wave > 1)
     return fail(c, FIRE_E_INVALID, "schedule field out of range");
+  if (s->wave == 1 && simw_lds_bytes(0, s->queue_cap) > c->max_lds)
+    return fail(c, FIRE_E_INVALID, "queue_cap %d does not fit LDS", s->queue_cap);
   if (lds_bytes_for(0, s->queue_cap) > c->max_lds)
     return fail(c, FIRE_E_INVALID, "queue_cap %d does not fit LDS", s->queue_cap);
   c->sched = *s;
@@ -1314,6 +1455,7 @@ fire_status fire_get_schedule(fire_ctx *c, int64_t max_cells, int32_t n_params,
   if (ps != FIRE_OK) return ps;
   *out = plan.s;
   out->window = plan.win;
+  out->wave = plan.wave ? 1 : 0;
   return FIRE_OK;
 }
 
@@ -1447,12 +1589,12 @@ static fire_status ga_run_graph(fire_ctx *c, int32_t lid, int32_t tid, int32_t i
   const bool tables = plan.s.table_mode != 0;
   const int64_t per = (int64_t)L.W * L.H * 8;
   if (tables) {
-    fire_status ts = ensure_tables(c, lid, P);
+    fire_status ts = ensure_tables(c, lid, P, user);
     if (ts != FIRE_OK) return ts;
   }
-  fire_status ss = ensure_spill(c, spill_words(plan));
+  fire_status ss = ensure_spill(c, spill_words(plan), user);
   if (ss != FIRE_OK) return ss;
-  fire_status rs = ensure_retry(c, 1 + (int64_t)n);
+  fire_status rs = ensure_retry(c, 1 + (int64_t)n, user);
   if (rs != FIRE_OK) return rs;
 
   // capture one generation

@@ -85,6 +85,12 @@ hipError_t launch_set_life(uint4 *rec, int64_t n, const uint8_t *steps, hipStrea
 hipError_t launch_sim(const SimArgs &a, int threads, bool table, bool dur, int grid,
                       size_t lds_bytes, hipStream_t s);
 hipError_t set_sim_lds_limit(size_t bytes);
+// wavefront-per-simulation kernel (one 64-lane workgroup per simulation,
+// LDS-only queues; a.retry receives the simulations it could not finish)
+hipError_t launch_simw(const SimArgs &a, bool table, int grid, size_t lds, hipStream_t s);
+size_t simw_lds_bytes(int bitset_words, int queue_cap);
+int simw_occupancy(bool table, bool win, size_t lds_bytes);
+size_t simw_scratch_bytes(bool table, bool win);
 // workgroups of the simulation kernel resident per compute unit for this
 // launch shape (registers and LDS), 0 if unknown
 int sim_occupancy(int threads, bool table, bool dur, bool win, size_t lds_bytes);

@@ -812,6 +812,432 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Wavefront-per-simulation kernel, for fronts of up to queue_cap cells.
+//
+// Each workgroup is one 64-lane wavefront that takes simulations from the
+// same atomic work counter as sim_kernel and runs each alone, with no
+// workgroup barrier: the parts of a step are ordered by program order
+// within the wavefront (LDS operations of one wavefront are performed in
+// issue order), and every count that decides control flow is wave-uniform.
+// LDS per wavefront: burn bitset (whole lattice or window, as in
+// sim_kernel) and two frontier queues of queue_cap entries.
+// A step with up to 4 * 64 units (frontier entry, direction group) keeps
+// up to four units per lane in registers and interleaves them: the entries,
+// the targets' bits, the thresholds and the four Philox evaluations of all
+// of a lane's units are issued before any result is needed, then the bits
+// of the hit targets are set (every bit read of the step precedes every
+// atomic, so eligibility is the burn state at the start of the step) and
+// the cells whose bit a lane flipped are appended to the next frontier. A
+// larger front first stores the hit nibbles of each entry in its queue
+// word's top byte, then sets bits and appends in a second pass.
+// A simulation whose next frontier would exceed queue_cap, or (with a
+// window) whose fire comes within one cell of a window edge inside the
+// lattice, stops and is listed in `retry` for the whole-lattice re-run
+// launch of sim_kernel, which draws the same coins and so gives the same
+// result.
+// ---------------------------------------------------------------------------
+constexpr int kWave = 64;
+constexpr int kWaveRegUnits = 4;  // units per lane held in registers
+
+// LDS words of one wavefront of simw_kernel.
+__host__ __device__ constexpr int64_t simw_lds_words(int bitset_words, int queue_cap) {
+  return (int64_t)bitset_words + 2 * (int64_t)queue_cap;
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+template <bool TABLE, bool WIN>
+__global__ __launch_bounds__(kWave) void simw_kernel(SimArgs a) {
+  extern __shared__ uint32_t lds[];
+  const int bw = a.bitset_words;
+  const uint32_t cap = (uint32_t)a.queue_cap;
+  uint32_t *const bits = lds;
+  uint32_t *const ql = lds + bw;  // queue q entry i: ql[q * cap + i]
+  const int lane = threadIdx.x;
+
+  for (;;) {
+    uint32_t sim = 0;
+    if (lane == 0) {
+      const uint32_t k = atomicAdd(a.work, 1u);
+      const uint32_t n = a.n_dev ? *a.n_dev : (uint32_t)a.n_sims;
+      sim = k < n ? (a.order ? a.order[k] : k) : 0xFFFFFFFFu;
+    }
+    sim = __builtin_amdgcn_readfirstlane(sim);
+    if (sim == 0xFFFFFFFFu) break;
+    const fire_sim sd = a.sims[sim];
+
+    // -- descriptor checks, as in sim_kernel -------------------------------
+    bool ok = sd.landscape_id >= 0 && sd.landscape_id < a.n_ls &&
+              sd.param_index < (uint32_t)a.n_params;
+    LandscapeDev L{};
+    if (ok) {
+      L = a.ls[sd.landscape_id];
+      ok = L.valid && sd.ign_x >= 0 && sd.ign_x < L.W && sd.ign_y >= 0 &&
+           sd.ign_y < L.H &&
+           (WIN ? min(a.win, L.H) * min(a.win >> 5, L.stride) : L.H * L.stride) <=
+               a.bitset_words &&
+           (a.maps == nullptr || (int64_t)L.H * L.stride <= a.map_words) &&
+           (a.tables == nullptr || a.table_ls == sd.landscape_id);
+    }
+    TargetDev tg{};
+    const bool has_target = sd.target_id >= 0;
+    if (ok && has_target) {
+      ok = sd.target_id < a.n_tg;
+      if (ok) {
+        tg = a.tg[sd.target_id];
+        ok = tg.valid && tg.landscape_id == sd.landscape_id;
+      }
+    } else if (ok) {
+      ok = sd.target_id == -1;
+    }
+    if (!ok) {
+      if (lane == 0) {
+        fire_result r;
+        r.burnt = 0; r.steps = 0xFFFFFFFFu; r.trials = 0;
+        r.fitness = __builtin_nan("");
+        a.out[sim] = r;
+        atomicOr(a.error_flag, 1u);
+      }
+      continue;
+    }
+    const int W = L.W, H = L.H, stride = L.stride;
+    const int words = H * stride;
+    const int ix = sd.ign_x, iy = sd.ign_y;
+    gmem_cu32 *const blocked = (gmem_cu32 *)L.blocked;
+    if (((blocked[iy * stride + (ix >> 5)] >> (ix & 31)) & 1u) != 0) {
+      // a non-burnable ignition burns nothing
+      if (lane == 0) {
+        fire_result r;
+        r.burnt = 0; r.steps = 0; r.trials = 0;
+        r.fitness = has_target ? 1.0 : __builtin_nan("");
+        a.out[sim] = r;
+      }
+      if (a.maps != nullptr) {
+        uint32_t *m = a.maps + (int64_t)sim * a.map_words;
+        for (int w = lane; w < words; w += kWave) m[w] = 0u;
+      }
+      continue;
+    }
+
+    // -- window (whole lattice without one), as in sim_kernel --------------
+    const int ws = WIN ? min(a.win >> 5, stride) : stride;
+    const int wh = WIN ? min(a.win, H) : H;
+    const int wx0w = WIN ? min(max((ix >> 5) - ws / 2, 0), stride - ws) : 0;
+    const int wy0 = WIN ? min(max(iy - wh / 2, 0), H - wh) : 0;
+    const int x_lo = wx0w > 0 ? 32 * wx0w + 1 : 0;
+    const uint32_t x_span = (uint32_t)((wx0w + ws < stride ? 32 * (wx0w + ws) - 2 : 8191) - x_lo);
+    const int y_lo = wy0 > 0 ? wy0 + 1 : 0;
+    const uint32_t y_span = (uint32_t)((wy0 + wh < H ? wy0 + wh - 2 : 8191) - y_lo);
+    const int w_off = wy0 * ws + wx0w;
+    const int wwords = wh * ws;
+
+    for (int w = lane; w < wwords; w += kWave)
+      bits[w] = blocked[(wy0 + w / ws) * stride + wx0w + w % ws];
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (lane == 0) {
+      bits[iy * ws + (ix >> 5) - w_off] |= 1u << (ix & 31);
+      ql[0] = (uint32_t)ix | ((uint32_t)iy << 12);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    double beta[5];
+    if (!TABLE) {
+      const double *bp = a.betas + (int64_t)sd.param_index * 5;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) beta[i] = bp[i];
+    }
+    gmem_cu32 *const table =
+        TABLE ? (gmem_cu32 *)(a.tables + (int64_t)sd.param_index * a.table_stride) : nullptr;
+    const uint32_t max_steps = sd.max_steps;
+    const uint32_t sim_index = sd.sim_index;
+
+    uint32_t n_cur = 1, cq = 0, step = 0, n_new = 0, my_trials = 0;
+    bool stopped = false;
+
+    // Targets of group g around a source at (x, y): (0, -s), (s, -s),
+    // (s, 0), (s, s), s = +1 for g = 0 and -1 for g = 1. LDS words and bits
+    // of the four; an edge that cannot be tried (target outside, or source
+    // at a window edge) reads its source's own bit, which is set.
+    struct Unit {
+      uint32_t e, g, elig, hit;
+      int base, xb;
+      int wk[4], bk[4];
+      bool edge;
+    };
+    auto unit_geom = [&](Unit &u, uint32_t e, uint32_t g, bool valid) {
+      u.e = e;
+      u.g = g;
+      const int x = (int)(e & 0xFFFu), y = (int)((e >> 12) & 0xFFFu);
+      u.edge = WIN && valid && ((uint32_t)(x - x_lo) > x_span || (uint32_t)(y - y_lo) > y_span);
+      const int sg = g ? -1 : 1;
+      const int sws = g ? -ws : ws;
+      u.base = y * ws + (x >> 5) - w_off;
+      u.xb = x & 31;
+      const int xs = u.xb + sg;
+      const int wo = xs >> 5, bs = xs & 31;
+      u.wk[0] = u.base - sws;       u.bk[0] = u.xb;
+      u.wk[1] = u.base - sws + wo;  u.bk[1] = bs;
+      u.wk[2] = u.base + wo;        u.bk[2] = bs;
+      u.wk[3] = u.base + sws + wo;  u.bk[3] = bs;
+      const bool r1 = (unsigned)(y - sg) < (unsigned)H && !u.edge;
+      const bool r2 = (unsigned)(y + sg) < (unsigned)H && !u.edge;
+      const bool c1 = (unsigned)(x + sg) < (unsigned)W;
+      const bool in[4] = {r1 && valid, r1 && c1 && valid, c1 && !u.edge && valid,
+                          r2 && c1 && valid};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (!in[q]) {
+          u.wk[q] = u.base;
+          u.bk[q] = u.xb;
+        }
+    };
+    // the threshold of edge q (0..3) of the unit (TABLE: from the table)
+    auto thresholds = [&](const Unit &u, uint32_t s_lin, uint32_t thr[4]) {
+      if (TABLE) {
+        const u32x4 t4 = load_x4(table + (int64_t)s_lin * 8 + 4 * u.g);
+        thr[0] = t4.x; thr[1] = t4.y; thr[2] = t4.z; thr[3] = t4.w;
+      } else {
+        // Eq. 1 for the eligible edges; the covariates of the four targets
+        // are read first (an ineligible edge reads its source's)
+        const int sg = u.g ? -1 : 1;
+        const int sW = u.g ? -W : W;
+        const int tk[4] = {-sW, sg - sW, sg, sg + sW};
+        uint32_t vu[4];
+        double psi[4], slope[4], om[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int d = 4 * (int)u.g + q;
+          const int64_t tl = ((u.elig >> q) & 1u) ? (int64_t)s_lin + tk[q] : (int64_t)s_lin;
+          vu[q] = rec_word(L.rec, tl);
+          psi[q] = ((gmem_cf64 *)L.ps)[2 * tl];
+          slope[q] = ((gmem_cf64 *)L.ps)[2 * tl + 1];
+          om[q] = ((gmem_cf64 *)L.omega)[8 * tl + d];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int d = 4 * (int)u.g + q;
+          const uint32_t veg = vu[q] & 0xFFu;
+          thr[q] = ((u.elig >> q) & 1u) && veg != 0
+                       ? logistic_threshold(beta, veg == L.forest_class ? 1.0 : 0.0, psi[q],
+                                            om[q], ((vu[q] >> (8 + d)) & 1u) ? slope[q] : 0.0)
+                       : 0u;
+        }
+      }
+    };
+    // set the bits of the hit targets; the mask of targets whose bit this
+    // lane flipped
+    auto ignite = [&](const Unit &u, uint32_t hit) -> uint32_t {
+      uint32_t old[4], bitv[4], fresh = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool h = (hit >> q) & 1u;
+        bitv[q] = h ? 1u << u.bk[q] : 0u;
+        old[q] = atomicOr(&bits[h ? u.wk[q] : u.base], bitv[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (bitv[q] && (old[q] & bitv[q]) == 0) fresh |= 1u << q;
+      return fresh;
+    };
+    // append the fresh cells of every lane (wave prefix of per-lane counts
+    // 0..4); `n_next` and `over` are wave-uniform
+    auto append = [&](const Unit &u, uint32_t fresh, uint32_t &n_next, bool &over) {
+      const uint32_t cnt = __popc(fresh);
+      const uint64_t b0 = __ballot(cnt & 1u), b1 = __ballot(cnt & 2u), b2 = __ballot(cnt & 4u);
+      const uint32_t total = (uint32_t)(__popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2));
+      if (over || n_next + total > cap) {
+        over = true;
+      } else if (fresh) {
+        uint32_t idx = n_next + lane_prefix(b0) + 2 * lane_prefix(b1) + 4 * lane_prefix(b2);
+        const int x = (int)(u.e & 0xFFFu), y = (int)((u.e >> 12) & 0xFFFu);
+        const int sg = u.g ? -1 : 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (!((fresh >> q) & 1u)) continue;
+          const int tx = x + (q == 0 ? 0 : sg), ty = y + (q == 2 ? 0 : (q == 3 ? sg : -sg));
+          ql[(cq ^ 1u) * cap + idx++] = (uint32_t)tx | ((uint32_t)ty << 12);
+        }
+      }
+      n_next += total;
+    };
+
+    // a step whose units fit R per lane: everything in registers
+    auto step_regs = [&](auto RC, uint32_t n_units, uint32_t &n_next, bool &over) -> bool {
+      constexpr int R = decltype(RC)::value;
+      Unit u[R];
+      uint32_t rv[R][4], thr[R][4], s_lin[R], wv[R][4];
+      bool valid[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t j = (uint32_t)(lane + kWave * r);
+        valid[r] = j < n_units;
+        // a lane without a unit takes entry 0 (a burning cell inside the
+        // bitset) and reads only its own bit
+        const uint32_t e = ql[cq * cap + (valid[r] ? j >> 1 : 0u)] & 0xFFFFFFu;
+        unit_geom(u[r], e, j & 1u, valid[r]);
+        s_lin[r] = (uint32_t)((int)((e >> 12) & 0xFFFu) * W + (int)(e & 0xFFFu));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wv[r][q] = bits[u[r].wk[q]];
+      }
+      if (TABLE) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) thresholds(u[r], s_lin[r], thr[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const Words4 w4 = philox10(sim_index, step, s_lin[r], u[r].g, a.key0, a.key1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rv[r][q] = w4.v[q];
+      }
+      bool edge = false;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        uint32_t el = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) el |= ((wv[r][q] >> u[r].bk[q]) & 1u) == 0 ? 1u << q : 0u;
+        u[r].elig = el;
+        my_trials += __popc(el);
+        edge = edge || u[r].edge;
+      }
+      if (WIN && __ballot(edge) != 0) return true;
+      if (!TABLE) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) thresholds(u[r], s_lin[r], thr[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        uint32_t hit = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (((u[r].elig >> q) & 1u) && (thr[r][q] == kSaturated || rv[r][q] < thr[r][q]))
+            hit |= 1u << q;
+        u[r].hit = hit;
+      }
+      uint32_t fresh[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) fresh[r] = u[r].hit ? ignite(u[r], u[r].hit) : 0u;
+#pragma unroll
+      for (int r = 0; r < R; ++r) append(u[r], fresh[r], n_next, over);
+      return false;
+    };
+
+    for (;;) {
+      if (n_cur == 0 || step >= max_steps) break;
+      const uint32_t n_units = 2 * n_cur;
+      uint32_t n_next = 0;
+      bool over = false, edge = false;
+      if (n_units <= (uint32_t)(kWave * kWaveRegUnits)) {
+        const uint32_t rounds = (n_units + kWave - 1) / kWave;
+        if (rounds == 1) edge = step_regs(std::integral_constant<int, 1>{}, n_units, n_next, over);
+        else if (rounds == 2) edge = step_regs(std::integral_constant<int, 2>{}, n_units, n_next, over);
+        else if (rounds == 3) edge = step_regs(std::integral_constant<int, 3>{}, n_units, n_next, over);
+        else edge = step_regs(std::integral_constant<int, 4>{}, n_units, n_next, over);
+      } else {
+        // large front: hit nibbles of both groups of an entry go to its
+        // queue word's top byte, then a second pass sets bits and appends
+        for (uint32_t base = 0; base < n_units; base += kWave) {
+          const uint32_t j = base + (uint32_t)lane;
+          const bool valid = j < n_units;
+          Unit u;
+          const uint32_t e = ql[cq * cap + (valid ? j >> 1 : 0u)] & 0xFFFFFFu;
+          unit_geom(u, e, j & 1u, valid);
+          const uint32_t s_lin = (uint32_t)((int)((e >> 12) & 0xFFFu) * W + (int)(e & 0xFFFu));
+          uint32_t wv[4], thr[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) wv[q] = bits[u.wk[q]];
+          if (TABLE) thresholds(u, s_lin, thr);
+          const Words4 w4 = philox10(sim_index, step, s_lin, u.g, a.key0, a.key1);
+          uint32_t el = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) el |= ((wv[q] >> u.bk[q]) & 1u) == 0 ? 1u << q : 0u;
+          u.elig = el;
+          my_trials += __popc(el);
+          edge = edge || __ballot(u.edge) != 0;
+          if (!TABLE) thresholds(u, s_lin, thr);
+          uint32_t hit = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (((el >> q) & 1u) && (thr[q] == kSaturated || w4.v[q] < thr[q])) hit |= 1u << q;
+          const uint32_t other = (uint32_t)__shfl_xor((int)hit, 1);
+          if (valid && (j & 1u) == 0 && (hit | other) != 0)
+            ql[cq * cap + (j >> 1)] = e | ((hit | (other << 4)) << 24);
+        }
+        if (WIN && edge) {
+          stopped = true;
+          break;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        for (uint32_t base = 0; base < n_units; base += kWave) {
+          const uint32_t j = base + (uint32_t)lane;
+          const bool valid = j < n_units;
+          const uint32_t q8 = ql[cq * cap + (valid ? j >> 1 : 0u)];
+          Unit u;
+          unit_geom(u, q8 & 0xFFFFFFu, j & 1u, valid);
+          const uint32_t hit = valid ? (q8 >> (24 + 4 * (j & 1u))) & 15u : 0u;
+          const uint32_t fresh = hit ? ignite(u, hit) : 0u;
+          append(u, fresh, n_next, over);
+        }
+      }
+      if (edge || over) {
+        stopped = true;
+        break;
+      }
+      n_new += n_next;
+      n_cur = n_next;
+      cq ^= 1u;
+      ++step;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+
+    if (stopped) {
+      // outgrew the queues or reached the window edge: run again over the
+      // whole lattice in the workgroup kernel
+      if (lane == 0) a.retry[1 + atomicAdd(a.retry, 1u)] = sim;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      continue;
+    }
+
+    // -- result: counts, Eq. 2 over the window, map ------------------------
+    const uint64_t trials = wave_sum(my_trials);
+    uint64_t inter = 0;
+    if (has_target) {
+      gmem_cu32 *const ref = (gmem_cu32 *)tg.bits;
+      uint32_t mine = 0;
+      for (int w = lane; w < wwords; w += kWave) {
+        const int gw = (wy0 + w / ws) * stride + wx0w + w % ws;
+        mine += __popc(bits[w] & ~blocked[gw] & ref[gw]);
+      }
+      inter = wave_sum(mine);
+    }
+    if (lane == 0) {
+      fire_result r;
+      r.burnt = 1u + n_new;
+      r.steps = step;
+      r.trials = trials;
+      if (has_target) {
+        const int64_t num = (int64_t)tg.n_ref + r.burnt - 2 * (int64_t)inter;
+        r.fitness = (double)num / (double)tg.n_ref;
+      } else {
+        r.fitness = __builtin_nan("");
+      }
+      a.out[sim] = r;
+    }
+    if (a.maps != nullptr) {
+      uint32_t *m = a.maps + (int64_t)sim * a.map_words;
+      for (int w = lane; w < words; w += kWave) {
+        const int y = w / stride, xw = w % stride;
+        const bool in = y >= wy0 && y < wy0 + wh && xw >= wx0w && xw < wx0w + ws;
+        m[w] = in ? bits[(y - wy0) * ws + (xw - wx0w)] & ~blocked[w] : 0u;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Genetic-algorithm generation (Appendix B): elitism, tournament of two,
 // one-point crossover of consecutive non-elite pairs, dynamic mutation.
 // One workgroup, thread i owns slot i. Only exact IEEE operations.
@@ -1289,6 +1715,52 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_simw(const SimArgs &a, bool table, int grid, size_t lds, hipStream_t s) {
+  const bool win = a.win > 0;
+  if (a.retry == nullptr) return hipErrorInvalidValue;
+  if (table) {
+    if (win) hipLaunchKernelGGL((simw_kernel<true, true>), dim3(grid), dim3(kWave), lds, s, a);
+    else hipLaunchKernelGGL((simw_kernel<true, false>), dim3(grid), dim3(kWave), lds, s, a);
+  } else {
+    if (win) hipLaunchKernelGGL((simw_kernel<false, true>), dim3(grid), dim3(kWave), lds, s, a);
+    else hipLaunchKernelGGL((simw_kernel<false, false>), dim3(grid), dim3(kWave), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+size_t simw_lds_bytes(int bitset_words, int queue_cap) {
+  return sizeof(uint32_t) * (size_t)simw_lds_words(bitset_words, queue_cap);
+}
+
+int simw_occupancy(bool table, bool win, size_t lds_bytes) {
+  int n = 0;
+  hipError_t e;
+  if (table)
+    e = win ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, simw_kernel<true, true>, kWave, lds_bytes)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, simw_kernel<true, false>, kWave, lds_bytes);
+  else
+    e = win ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, simw_kernel<false, true>, kWave, lds_bytes)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, simw_kernel<false, false>, kWave, lds_bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+size_t simw_scratch_bytes(bool table, bool win) {
+  hipFuncAttributes at{};
+  const void *f = table ? (win ? reinterpret_cast<const void *>(&simw_kernel<true, true>)
+                               : reinterpret_cast<const void *>(&simw_kernel<true, false>))
+                        : (win ? reinterpret_cast<const void *>(&simw_kernel<false, true>)
+                               : reinterpret_cast<const void *>(&simw_kernel<false, false>));
+  if (hipFuncGetAttributes(&at, f) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return at.localSizeBytes;
+}
+
 template <int BLOCK, bool TABLE, bool DUR>
 static void launch_one(const SimArgs &a, bool win, int grid, size_t lds, hipStream_t s) {
   if (win)
@@ -1410,6 +1882,14 @@ static hipError_t set_limit_block(size_t bytes) {
 
 hipError_t set_sim_lds_limit(size_t bytes) {
   hipError_t e;
+  const void *wk[4] = {reinterpret_cast<const void *>(&simw_kernel<true, true>),
+                       reinterpret_cast<const void *>(&simw_kernel<true, false>),
+                       reinterpret_cast<const void *>(&simw_kernel<false, true>),
+                       reinterpret_cast<const void *>(&simw_kernel<false, false>)};
+  for (const void *f : wk)
+    if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) !=
+        hipSuccess)
+      return e;
   if ((e = set_limit_block<64>(bytes)) != hipSuccess) return e;
   if ((e = set_limit_block<128>(bytes)) != hipSuccess) return e;
   if ((e = set_limit_block<256>(bytes)) != hipSuccess) return e;

@@ -29,7 +29,8 @@ STATUS = {0: "FIRE_OK", -1: "FIRE_E_INVALID", -2: "FIRE_E_OOM", -3: "FIRE_E_DEVI
 EXPORTS = ["fire_ctx_create", "fire_ctx_destroy", "fire_last_error", "fire_sync", "fire_version",
            "fire_landscape_load", "fire_landscape_free", "fire_landscape_set_burn_steps",
            "fire_target_load", "fire_target_free",
-           "fire_thresholds", "fire_run", "fire_run_dev", "fire_run_dense", "fire_set_schedule",
+           "fire_thresholds", "fire_run", "fire_run_dev", "fire_run_dense",
+           "fire_set_schedule",
            "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_step_genes",
            "fire_ga_sims_from_pop", "fire_ga_run", "fire_ga_run_ignition", "fire_ensemble", "fire_scan_reduce"]
 
@@ -51,7 +52,7 @@ class LandscapeDesc(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
                 ("table_mode", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("window", ctypes.c_int32)]
+                ("window", ctypes.c_int32), ("wave", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -93,7 +94,7 @@ def load_library(path: str = LIB_PATH):
         "fire_run_dense": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, i64, vp]),
         "fire_set_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
         "fire_get_schedule": (i32, [vp, i64, i32, i32, ctypes.POINTER(Schedule)]),
-        "fire_set_class_schedule": (i32, [vp, i64, ctypes.POINTER(Schedule)]),
+        "fire_set_class_schedule": (i32, [vp, i64, i32, ctypes.POINTER(Schedule)]),
         "fire_ga_step": (i32, [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(GACfg), u32, u64, vp]),
         "fire_ga_step_genes": (i32, [vp, vp, vp, vp, i32, i32, i32, i32, dbl, vp, vp, vp, u32, u32,
                                      u64, vp]),
@@ -274,23 +275,31 @@ class FireGPU:
 
     # -- schedule ------------------------------------------------------------
     def set_schedule(self, threads=None, queue_cap=None, table_mode=None, wg_per_cu=None,
-                     window=0, reset=False):
+                     window=0, wave=0, reset=False):
         """Fix the schedule (window: 0 = whole-lattice bitsets, -1 = built-in
-        choice, else the LDS window side in cells)."""
+        choice, else the LDS window side in cells; wave: 1 = one simulation
+        per wavefront, 0 = one per workgroup of `threads`)."""
         if reset:
             self._check(self.lib.fire_set_schedule(self.ctx, None))
             return
-        s = Schedule(int(threads), int(queue_cap), int(table_mode), int(wg_per_cu), int(window))
+        s = Schedule(int(threads), int(queue_cap), int(table_mode), int(wg_per_cu), int(window),
+                     int(wave))
         self._check(self.lib.fire_set_schedule(self.ctx, ctypes.byref(s)))
 
-    def set_class_schedule(self, max_cells: int, sched: dict | None):
-        """Schedule for runs on landscapes of the size class of ``max_cells``."""
-        if sched is None:
-            self._check(self.lib.fire_set_class_schedule(self.ctx, int(max_cells), None))
-            return
-        s = Schedule(int(sched["threads"]), int(sched["queue_cap"]), int(sched["table_mode"]),
-                     int(sched["wg_per_cu"]), int(sched.get("window", -1)))
-        self._check(self.lib.fire_set_class_schedule(self.ctx, int(max_cells), ctypes.byref(s)))
+    def set_class_schedule(self, max_cells: int, sched: dict | None, many_params=None):
+        """Schedule for runs on landscapes of the size class of ``max_cells``:
+        for batches of more than 8 parameter vectors (many_params=True), of
+        at most 8 (False), or both (None)."""
+        kinds = (0, 1) if many_params is None else (1 if many_params else 0,)
+        for k in kinds:
+            if sched is None:
+                self._check(self.lib.fire_set_class_schedule(self.ctx, int(max_cells), k, None))
+                continue
+            s = Schedule(int(sched["threads"]), int(sched["queue_cap"]),
+                         int(sched["table_mode"]), int(sched["wg_per_cu"]),
+                         int(sched.get("window", -1)), int(sched.get("wave", -1)))
+            self._check(self.lib.fire_set_class_schedule(self.ctx, int(max_cells), k,
+                                                         ctypes.byref(s)))
 
     def get_schedule(self, max_cells: int, n_params: int = 1, n_sims: int = 1 << 20) -> dict:
         """The schedule a batch of n_sims simulations would use."""

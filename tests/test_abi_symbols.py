@@ -60,6 +60,16 @@ def test_nn_library_exports():
     assert all(hasattr(lib, n) for n in declared)
 
 
+def test_probe_library_exports():
+    from paper_1701_03549_amd import probe
+    text = open(os.path.join(ROOT, "include", "fire_probe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    declared = sorted(set(re.findall(r"\b(fire_[a-z_0-9]+)\s*\(", text)))
+    assert sorted(probe.EXPORTS) == declared
+    lib = ctypes.CDLL(LIB)
+    assert all(hasattr(lib, n) for n in declared)
+
+
 def test_library_has_no_undefined_internal_symbols():
     """Every symbol of the library's own namespaces is defined in it."""
     import shutil

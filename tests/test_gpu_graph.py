@@ -95,3 +95,55 @@ def test_grouped_classes_match_single_launch_and_oracle(g):
     g.set_class_schedule(128 * 128, None)
     for lid in lids:
         g.free_landscape(lid)
+
+
+def test_capture_rules(g):
+    """fire_run refuses stream capture (its host staging would be read at
+    replay time); a captured fire_run_dev stays valid after a later, larger
+    eager call grows the context's scratch buffers (they are retired, not
+    freed), and its replays still equal the eager results."""
+    import torch
+    from paper_1701_03549_amd import fire
+    W, H = 96, 80
+    ls = synth.make_landscape(W, H, 21)
+    lid = g.load_landscape(ls)
+    c = synth.nearest_burnable(ls["veg"], W // 2, H // 2)
+    n = 64
+    betas = np.array([(-0.4, -0.3, 0.2, 0.8, 1.0)])
+    sims = fire.make_sims(n, lid, -1, c)
+    d_sims = torch.from_numpy(sims.view(np.uint8).copy()).cuda()
+    d_beta = torch.from_numpy(betas.copy()).cuda()
+    out = torch.empty((n, 24), dtype=torch.uint8, device="cuda")
+    say("capture rules: eager")
+    g.run_dev(d_beta, d_sims, n, SEED, out)
+    g.sync()
+    eager = out.clone()
+    graph = torch.cuda.CUDAGraph()
+    err = None
+    say("capture rules: capture (fire_run refused, fire_run_dev recorded)")
+    with torch.cuda.graph(graph):
+        try:
+            g.run(betas, sims, SEED, stream=torch.cuda.current_stream())
+        except fire.FireError as e:
+            err = e
+        g.run_dev(d_beta, d_sims, n, SEED, out, stream=torch.cuda.current_stream())
+    assert err is not None and err.status == -4, err
+    # a larger eager call: 512x512 landscape, 1280 simulations (spill area,
+    # retry list and threshold tables all grow)
+    big = synth.make_landscape(512, 512, 102)
+    lid2 = g.load_landscape(big)
+    bs = fire.make_sims(1280, lid2, -1, synth.ignition_site(big))
+    say("capture rules: larger eager call")
+    res_big, _ = g.run(np.array([(-3.0, -0.5, 6.0, 1.0, 2.0)]), bs, SEED)
+    g.sync()
+    assert fire.results_to_numpy(res_big)["burnt"].min() >= 1
+    g.free_landscape(lid2)
+    for k in range(3):
+        say(f"capture rules: replay {k}")
+        out.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), k
+    g.sync()
+    del graph
+    g.free_landscape(lid)

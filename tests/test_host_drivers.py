@@ -48,5 +48,9 @@ def test_autotune_candidates():
     wins = {c["window"] for c in cs}
     assert wins == {0, 128, 256, 384}
     assert {c["table_mode"] for c in cs} == {0, 1}
-    assert all(c["threads"] in (128, 256, 512, 1024) for c in cs)
+    assert all(c["threads"] in (128, 256, 512, 1024) for c in cs if c["wave"] == 0)
+    waves = [c for c in cs if c["wave"] == 1]
+    assert waves and all(c["threads"] == 64 and c["wg_per_cu"] == 1 for c in waves)
+    assert {c["window"] for c in waves} == {0, 128, 256, 384}
+    assert not any(c["threads"] == 1024 and c["window"] > 0 for c in cs)
     assert {c["window"] for c in autotune.candidates(False, side=64)} == {0}
