@@ -456,12 +456,11 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
     ws.table_mode = full.table_mode;
     return shape_launch(c, ws, wbw, dur, true, n_sims, wl, wg);
   };
-  // wavefront-per-simulation plan: asked for by the schedule, or (built-in)
-  // for batches of a few parameter vectors without turn-off times while no
-  // run on these landscapes has had to be repeated
-  const bool want_wave = !dur && (s.wave == 1 || (s.window < 0 && s.wave < 0 &&
-                                                  win_frac <= kWindowRetryMax &&
-                                                  n_params <= kWindowMaxParams));
+  // wavefront-per-simulation plan: only when the schedule asks for it. On
+  // the 512x512 calibration batch it took 0.565 ms against 0.42 ms for the
+  // workgroup kernel (fronts of a few hundred cells need several 64-lane
+  // passes per step), so built-in plans use the workgroup kernel
+  const bool want_wave = !dur && s.wave == 1;
   if (want_wave) {
     const int qcap = s.wave == 1 ? s.queue_cap : kWaveQueue;
     auto wave_shape = [&](int side, size_t *wl, int *wg) -> bool {

@@ -3,7 +3,7 @@ runs a simulation with its frontier queues in LDS; fires whose front
 outgrows them, or that reach a window edge, are run again by the workgroup
 kernel) against the oracle: maps, burnt, steps, trials and Eq. 2 bit-exact,
 with small queues and windows that force many re-runs, both threshold
-modes, step caps, non-burnable ignitions and the built-in plan."""
+modes, step caps, non-burnable ignitions; built-in plans do not choose it."""
 import numpy as np
 import pytest
 
@@ -60,9 +60,10 @@ def test_wave_kernel_matches_oracle(g, table, qcap, window):
 
 
 def test_wave_kernel_equals_workgroup_kernel_512(g):
-    """The calibration batch: built-in plan (wavefront kernel in a window),
-    the wavefront kernel over the whole lattice and the workgroup kernel give
-    identical results and maps; all 1280 against the oracle."""
+    """The calibration batch: the built-in plan (workgroup kernel), the
+    wavefront kernel in a 416-cell window and over the whole lattice, and the
+    workgroup kernel with a fixed schedule give identical results and maps;
+    all 1280 against the oracle."""
     import torch
     from paper_1701_03549_amd import fire
     W = H = 512
@@ -79,9 +80,10 @@ def test_wave_kernel_equals_workgroup_kernel_512(g):
     g.set_schedule(reset=True)
     sched = g.get_schedule(W * H, 1, n)
     say(f"built-in plan at 512^2: {sched}")
-    assert sched["wave"] == 1
+    assert sched["wave"] == 0
     outs = []
-    for s in (None, dict(threads=64, queue_cap=512, table_mode=1, wg_per_cu=1, window=0, wave=1),
+    for s in (None, dict(threads=64, queue_cap=512, table_mode=1, wg_per_cu=1, window=416, wave=1),
+              dict(threads=64, queue_cap=512, table_mode=1, wg_per_cu=1, window=0, wave=1),
               dict(threads=256, queue_cap=1016, table_mode=1, wg_per_cu=4, window=0, wave=0)):
         say(f"512^2 schedule {s}")
         if s is None:
