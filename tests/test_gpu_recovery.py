@@ -1,18 +1,34 @@
 """Recovery of the generating parameters by the batched GA (Appendix B) at
 512x512: 64 individuals x 20 replicates x 50 generations from the Gaussian
-prior of Table 1, against a reference fire made at the calibration vector.
-Bounds (set from a pilot before timing): the best individual's mean fitness
-is below the stochastic floor of replicates at the generating vector (0.054),
-and the wind coefficient, the best identified one, is recovered within 1 by
-the accepted ensemble (fitness < 0.3)."""
+prior of Table 1, against a contained reference fire made by the oracle at
+the calibration vector, for five initial populations.
+
+Bounds were set from a five-seed pilot before they were written here (pilot
+values in brackets: the worst of the five seeds):
+
+* the best individual's mean fitness is below the stochastic floor of
+  replicates at the generating vector (0.054) [0.037];
+* the accepted ensemble (fitness < 0.3) recovers the forest, wind and slope
+  coefficients: |mean - true| < 1.5, 1.0 and 3.0 [0.93, 0.80, 2.25];
+* the intercept and the aspect coefficient are not identified one by one:
+  the fit moves along a ridge towards larger aspect effects and lower
+  intercepts (fires that are less random reproduce the one reference fire
+  better), but the linear predictor at aspect value 0.26,
+  b0 + 0.26 * b2, is: |mean - (-3 + 0.26 * 6)| < 0.5 [0.22];
+* the fitness profile shows why: one unit of intercept across the ridge
+  raises the mean fitness by more than 0.05 on both sides, while moving
+  along it (b0 - 0.26 t, b2 + t) for t = 2 and 4 changes it by less than
+  0.02 (128 replicates per point).
+"""
 import numpy as np
 import pytest
 
-from gpu_util import say
+from gpu_util import BETA_STAR, oracle_target, say
 from paper_1701_03549_amd import synth
 
 pytestmark = pytest.mark.gpu
-BETA_STAR = (-3.0, -0.5, 6.0, 1.0, 2.0)
+RIDGE = 0.26  # aspect value at which the linear predictor is identified
+SEEDS = (2024, 7, 11, 13, 17)
 
 
 def test_ga_recovers_calibration_vector():
@@ -21,21 +37,41 @@ def test_ga_recovers_calibration_vector():
     W = H = 512
     ls = synth.make_landscape(W, H, 102)
     c = synth.ignition_site(ls)
+    ref, k = oracle_target(ls, BETA_STAR, c, lo=0.01, hi=0.15)
     lid = g.load_landscape(ls)
-    res, maps = g.run(np.array([BETA_STAR]), fire.make_sims(32, lid, -1, c), 0x7A26E7,
-                      want_maps=True)
-    g.sync()
-    r = fire.results_to_numpy(res)
-    k = int(np.argmax(r["burnt"] >= 0.01 * W * H))
-    tid = g.load_target(lid, maps.cpu().numpy().view(np.uint32)[k].reshape(H, -1))
-    pop0 = np.clip(np.random.default_rng(2024).normal(0.0, 5.0, size=(64, 5)), -30, 30)
-    say("GA recovery at 512x512")
-    hist = ga.run_batched(g, lid, tid, c, pop0, R=20, generations=50, sim_seed=0x5EED0001,
-                          ga_seed=0x6A00001)
-    rec = ga.recovered(g, hist, cutoff=0.3)
-    say(f"best mean fitness {rec['best_mean_fitness']:.4f}, accepted {rec['n_accepted']}, "
-        f"mean {np.round(rec['accepted_mean'], 2)}")
-    assert rec["best_mean_fitness"] < 0.054
-    assert rec["n_accepted"] > 1000
-    assert abs(rec["accepted_mean"][3] - BETA_STAR[3]) < 1.0
+    tid = g.load_target(lid, ref)
+    truth = np.array(BETA_STAR)
+    ridge_true = truth[0] + RIDGE * truth[2]
+    for seed in SEEDS:
+        pop0 = np.clip(np.random.default_rng(seed).normal(0.0, 5.0, size=(64, 5)), -30, 30)
+        say(f"GA recovery at 512x512, initial population seed {seed}")
+        hist = ga.run_batched(g, lid, tid, c, pop0, R=20, generations=50, sim_seed=0x5EED0001,
+                              ga_seed=0x6A00001)
+        rec = ga.recovered(g, hist, cutoff=0.3)
+        m = np.array(rec["accepted_mean"])
+        sd = np.array(rec["accepted_sd"])
+        say(f"  best mean fitness {rec['best_mean_fitness']:.4f}, accepted {rec['n_accepted']}, "
+            f"mean {np.round(m, 2)} sd {np.round(sd, 2)}, b0 + {RIDGE} b2 = "
+            f"{m[0] + RIDGE * m[2]:.3f} (true {ridge_true:.3f})")
+        assert rec["best_mean_fitness"] < 0.054
+        assert rec["n_accepted"] > 1000
+        assert abs(m[1] - truth[1]) < 1.5
+        assert abs(m[3] - truth[3]) < 1.0
+        assert abs(m[4] - truth[4]) < 3.0
+        assert abs(m[0] + RIDGE * m[2] - ridge_true) < 0.5
+
+    def mean_fitness(beta, reps=128):
+        sims = fire.make_sims(reps, lid, tid, c,
+                              sim_index=np.arange(reps, dtype=np.uint32) + 900000)
+        res, _ = g.run(np.array([beta]), sims, 0x5EED0001)
+        g.sync()
+        return float(fire.results_to_numpy(res)["fitness"].mean())
+
+    d0 = mean_fitness(truth)
+    along = [mean_fitness(truth + t * np.array([-RIDGE, 0, 1, 0, 0])) for t in (2, 4)]
+    across = [mean_fitness(truth + s * np.array([1.0, 0, 0, 0, 0])) for s in (-1, 1)]
+    say(f"fitness profile: at the generating vector {d0:.4f}, along the ridge "
+        f"{np.round(along, 4)}, intercept -1/+1 {np.round(across, 4)}")
+    assert all(abs(a - d0) < 0.02 for a in along)
+    assert all(a - d0 > 0.05 for a in across)
     g.close()
