@@ -222,6 +222,28 @@ fire_status fire_run_dev(fire_ctx *ctx, const double *betas_dev,
                          fire_result *out, uint32_t *out_maps,
                          int64_t map_words, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * fire_run_dev, but every scratch buffer of the call (work counters, the
+ * list of simulations run again, the frontier spill area) lives in one
+ * 64 MiB device array that the library holds per GPU for the life of the
+ * process, and the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine). Thresholds come from thresholds_override or
+ * are evaluated per trial (no context tables). The launch grids shrink so
+ * that the spill area fits; a batch that cannot fit even one workgroup's
+ * spill area (about 2 * W * H words for the largest loaded landscape, plus
+ * n_sims + 65 words) is rejected with FIRE_E_INVALID before any device
+ * work. Every call on one GPU shares that GPU's array and leaves its
+ * contents behind (counters are cleared by each call): calls that overlap
+ * on one GPU, on any stream or context, race and must not be issued.
+ * Results are identical to fire_run_dev's. */
+fire_status fire_run_dev_noalloc(fire_ctx *ctx, const double *betas_dev,
+                                 int32_t n_params, const fire_sim *sims_dev,
+                                 int32_t n_sims, uint64_t seed,
+                                 const uint32_t *thresholds_override,
+                                 fire_result *out, uint32_t *out_maps,
+                                 int64_t map_words, void *stream);
+
 /* ---- schedule (autotuner hooks) --------------------------------------- */
 
 typedef struct {

@@ -111,6 +111,8 @@ struct fire_ctx {
   // that captured graphs never address freed memory
   bool captured = false;
   std::vector<void *> retired;
+  // this device's copy of the no-allocation scratch array (set at creation)
+  uint32_t *noalloc = nullptr;
 };
 
 namespace {
@@ -673,8 +675,10 @@ fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
                        const uint32_t *tables, int64_t table_stride,
                        int32_t table_ls, fire_result *out, uint32_t *out_maps,
                        int64_t map_words, int counter, uint32_t *spill, uint32_t *retry,
-                       hipStream_t st, int stat_lid = -1) {
-  uint32_t *const wb = c->d_work;
+                       hipStream_t st, int stat_lid = -1, uint32_t *work_base = nullptr) {
+  // work counters: the context's (or, for the no-allocation entry point,
+  // words of its scratch)
+  uint32_t *const wb = work_base ? work_base : c->d_work;
   SimArgs a = sim_args(c, betas_dev, n_params, sims_dev, order, n_sims, seed, tables,
                        table_stride, table_ls, out, out_maps, map_words, p.max_cells,
                        p.s.queue_cap, p.grid, p.dur, p.bitset_words, wb + counter, spill);
@@ -748,6 +752,11 @@ fire_status fire_ctx_create(int device, fire_ctx **out) {
     c->max_lds = prop.sharedMemPerBlock;
   // raising the dynamic-LDS ceiling is advisory on this platform
   if (set_sim_lds_limit(c->max_lds) != hipSuccess) (void)hipGetLastError();
+  // the no-allocation entry point's scratch on this device (device current)
+  if (noalloc_scratch(&c->noalloc) != hipSuccess) {
+    delete c;
+    return FIRE_E_DEVICE;
+  }
   bool ev_ok = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess;
   for (int i = 0; i < kMaxClasses && ev_ok; ++i)
     ev_ok = hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming) == hipSuccess;
@@ -1253,10 +1262,11 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
   return FIRE_OK;
 }
 
-fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
-                         const fire_sim *sims_dev, int32_t n_sims, uint64_t seed,
-                         const uint32_t *override_T, fire_result *out,
-                         uint32_t *out_maps, int64_t map_words, void *stream) {
+static fire_status run_dev_impl(fire_ctx *c, const double *betas_dev, int32_t n_params,
+                                const fire_sim *sims_dev, int32_t n_sims, uint64_t seed,
+                                const uint32_t *override_T, fire_result *out,
+                                uint32_t *out_maps, int64_t map_words, void *stream,
+                                bool noalloc) {
   if (!c) return FIRE_E_INVALID;
   if (n_sims < 0 || n_params < 1 || !betas_dev || (n_sims > 0 && (!sims_dev || !out)))
     return fail(c, FIRE_E_INVALID, "bad sizes or null pointers");
@@ -1291,24 +1301,73 @@ fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   RunPlan plan;
-  fire_status ps =
-      plan_run(c, bw, mc, mh, ms, n_params, n_sims, nlive == 1, &plan, any_dur, frac);
+  // without allocation, thresholds come from the caller's tables or are
+  // evaluated per trial (no context tables)
+  fire_status ps = plan_run(c, bw, mc, mh, ms, n_params, n_sims,
+                            nlive == 1 && (!noalloc || override_T != nullptr), &plan, any_dur,
+                            frac);
   if (ps != FIRE_OK) return ps;
-  fire_status ss = ensure_spill(c, spill_words(plan), st);
-  if (ss != FIRE_OK) return ss;
-  fire_status rs = ensure_retry(c, 1 + (int64_t)n_sims, st);
-  if (rs != FIRE_OK) return rs;
+  uint32_t *spill = c->d_ovf, *retry = c->d_retry, *work = nullptr;
+  if (noalloc) {
+    // scratch words: [0, 32) work counters, [64, 65 + n_sims) re-run list,
+    // then the spill area of the launches, whose grids shrink to fit it
+    const int64_t cap = (int64_t)kNoAllocScratchWords;
+    const int64_t spill_off = (65 + (int64_t)n_sims + 63) / 64 * 64;
+    const int64_t avail = cap - spill_off;
+    auto per_wg = [&](int qcap) {
+      const int64_t ovf = std::max<int64_t>(1, plan.max_cells - qcap);
+      return 2 * ovf + (plan.dur ? (2 * ovf + 3) / 4 : 0);
+    };
+    const int64_t need1 = plan.wave ? 0 : per_wg(plan.s.queue_cap);
+    const int64_t need2 = (plan.win > 0 || plan.wave) ? per_wg(plan.s2.queue_cap) : 0;
+    if (avail < std::max(need1, need2))
+      return fail(c, FIRE_E_INVALID,
+                  "the no-allocation scratch holds %lld words; %d simulations on landscapes of "
+                  "up to %lld cells need at least %lld",
+                  (long long)cap, n_sims, (long long)plan.max_cells,
+                  (long long)(spill_off + std::max(need1, need2)));
+    if (need1 > 0) plan.grid = (int)std::min<int64_t>(plan.grid, avail / need1);
+    if (need2 > 0) plan.grid2 = (int)std::min<int64_t>(plan.grid2, avail / need2);
+    work = c->noalloc;
+    retry = c->noalloc + 64;
+    spill = c->noalloc + spill_off;
+  } else {
+    fire_status ss = ensure_spill(c, spill_words(plan), st);
+    if (ss != FIRE_OK) return ss;
+    fire_status rs = ensure_retry(c, 1 + (int64_t)n_sims, st);
+    if (rs != FIRE_OK) return rs;
+    spill = c->d_ovf;  // (re)allocated above
+    retry = c->d_retry;
+  }
   const uint32_t *tables = override_T;
   int64_t tstride = 0;
   if (override_T) {
     tstride = mc * 8;
   } else if (plan.s.table_mode) {
+    if (noalloc) return fail(c, FIRE_E_INVALID, "internal: a table plan without tables");
     fire_status tsx = build_tables(c, lid, betas_dev, n_params, st, &tables, &tstride);
     if (tsx != FIRE_OK) return tsx;
   }
   return launch_run(c, plan, betas_dev, n_params, sims_dev, nullptr, n_sims, seed, tables,
-                    tstride, tables ? lid : -1, out, out_maps, map_words, 0, c->d_ovf,
-                    c->d_retry, st, nlive == 1 ? lid : -1);
+                    tstride, tables ? lid : -1, out, out_maps, map_words, 0, spill, retry, st,
+                    nlive == 1 ? lid : -1, work);
+}
+
+fire_status fire_run_dev(fire_ctx *c, const double *betas_dev, int32_t n_params,
+                         const fire_sim *sims_dev, int32_t n_sims, uint64_t seed,
+                         const uint32_t *override_T, fire_result *out,
+                         uint32_t *out_maps, int64_t map_words, void *stream) {
+  return run_dev_impl(c, betas_dev, n_params, sims_dev, n_sims, seed, override_T, out, out_maps,
+                      map_words, stream, false);
+}
+
+fire_status fire_run_dev_noalloc(fire_ctx *c, const double *betas_dev, int32_t n_params,
+                                 const fire_sim *sims_dev, int32_t n_sims, uint64_t seed,
+                                 const uint32_t *override_T, fire_result *out,
+                                 uint32_t *out_maps, int64_t map_words, void *stream) {
+  if (c && !c->noalloc) return fail(c, FIRE_E_DEVICE, "no scratch on this device");
+  return run_dev_impl(c, betas_dev, n_params, sims_dev, n_sims, seed, override_T, out, out_maps,
+                      map_words, stream, true);
 }
 
 fire_status fire_run_dense(fire_ctx *c, const double *betas, int32_t n_params,

@@ -85,6 +85,11 @@ hipError_t launch_set_life(uint4 *rec, int64_t n, const uint8_t *steps, hipStrea
 hipError_t launch_sim(const SimArgs &a, int threads, bool table, bool dur, int grid,
                       size_t lds_bytes, hipStream_t s);
 hipError_t set_sim_lds_limit(size_t bytes);
+// Device scratch of the no-allocation entry point: kNoAllocScratchWords
+// words per GPU (64 MiB), a file-scope array in fire_kernels.hip. `ptr`
+// receives the current device's copy (looked up once per device).
+constexpr size_t kNoAllocScratchWords = (size_t)16 << 20;
+hipError_t noalloc_scratch(uint32_t **ptr);
 // wavefront-per-simulation kernel (one 64-lane workgroup per simulation,
 // LDS-only queues; a.retry receives the simulations it could not finish)
 hipError_t launch_simw(const SimArgs &a, bool table, int grid, size_t lds, hipStream_t s);

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <math.h>
 #include <stdint.h>
@@ -1713,6 +1715,31 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s,
                      p, v, n);
   return hipGetLastError();
+}
+
+// Scratch of the no-allocation entry point (fire_run_dev_noalloc): its work
+// counters, re-run list and frontier spill area, in a file-scope device
+// array; every GPU the library runs on holds its own copy until the process
+// ends. Host code uses the address hipGetSymbolAddress returns for the
+// current device (noalloc_scratch), never the array's name.
+static __device__ __align__(256) uint32_t scratch[kNoAllocScratchWords];
+
+hipError_t noalloc_scratch(uint32_t **ptr) {
+  static std::mutex mu;
+  static std::map<int, uint32_t *> addr;  // device -> address of its copy
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = addr.emplace(dev, static_cast<uint32_t *>(p)).first;
+  }
+  *ptr = it->second;
+  return hipSuccess;
 }
 
 hipError_t launch_simw(const SimArgs &a, bool table, int grid, size_t lds, hipStream_t s) {

@@ -29,7 +29,7 @@ STATUS = {0: "FIRE_OK", -1: "FIRE_E_INVALID", -2: "FIRE_E_OOM", -3: "FIRE_E_DEVI
 EXPORTS = ["fire_ctx_create", "fire_ctx_destroy", "fire_last_error", "fire_sync", "fire_version",
            "fire_landscape_load", "fire_landscape_free", "fire_landscape_set_burn_steps",
            "fire_target_load", "fire_target_free",
-           "fire_thresholds", "fire_run", "fire_run_dev", "fire_run_dense",
+           "fire_thresholds", "fire_run", "fire_run_dev", "fire_run_dev_noalloc", "fire_run_dense",
            "fire_set_schedule",
            "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_step_genes",
            "fire_ga_sims_from_pop", "fire_ga_run", "fire_ga_run_ignition", "fire_ensemble", "fire_scan_reduce"]
@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH):
         "fire_thresholds": (i32, [vp, i32, vp, vp, vp]),
         "fire_run": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_run_dev": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
+        "fire_run_dev_noalloc": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_run_dense": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, i64, vp]),
         "fire_set_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
         "fire_get_schedule": (i32, [vp, i64, i32, i32, ctypes.POINTER(Schedule)]),
@@ -272,6 +273,17 @@ class FireGPU:
         self._check(self.lib.fire_run_dev(self.ctx, _ptr(betas_dev), n_params, _ptr(sims_dev),
                                           n_sims, int(seed) & (2 ** 64 - 1), _ptr(override),
                                           _ptr(out), _ptr(maps), map_words, _stream(stream)))
+
+    def run_dev_noalloc(self, betas_dev: torch.Tensor, sims_dev: torch.Tensor, n_sims: int,
+                        seed: int, out: torch.Tensor, maps: torch.Tensor | None = None,
+                        map_words: int = 0, override: torch.Tensor | None = None, stream=None):
+        """fire_run_dev_noalloc: as run_dev, with the library's per-GPU scratch
+        array instead of allocated buffers (calls on one GPU must not overlap)."""
+        n_params = betas_dev.numel() // 5
+        self._check(self.lib.fire_run_dev_noalloc(
+            self.ctx, _ptr(betas_dev), n_params, _ptr(sims_dev), n_sims,
+            int(seed) & (2 ** 64 - 1), _ptr(override), _ptr(out), _ptr(maps), map_words,
+            _stream(stream)))
 
     # -- schedule ------------------------------------------------------------
     def set_schedule(self, threads=None, queue_cap=None, table_mode=None, wg_per_cu=None,
