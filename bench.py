@@ -49,6 +49,13 @@ def kernel_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def apply_tuned(g) -> int:
+    """Install the autotuner's cached schedules for this GPU architecture
+    (per size class and batch kind); returns how many."""
+    from paper_1701_03549_amd import autotune
+    return autotune.apply_cache(g)
+
+
 def reference_fire(g, ls, lid, centre):
     """Reference map: the first replicate under the reference seed whose burnt
     fraction lies in [1%, 15%] and that does not touch the lattice border,
@@ -274,30 +281,37 @@ def run_turn_off(g, lid, tid, centre, d_sims, reps=10):
 
 
 def run_scan(log_fn):
-    """Ignition-point scan on the 1024x1024 landscape (seed 103, smooth wind):
-    256 candidate cells on a 4-cell grid around the true ignition x 32
-    replicates, Eq. 2 against the reference fire, device reduction."""
+    """Ignition-point scan on the 1024x1024 scan landscape (seed 103, smooth
+    wind) at the scan parameter vector: 256 candidate cells on a 4-cell grid
+    around the true ignition x 32 replicates, Eq. 2 against a contained
+    reference fire (2-20% of the lattice, off the border), device reduction."""
     import torch
     from paper_1701_03549_amd import fire, scan, synth
     g = fire.FireGPU(0)
-    W = H = 1024
-    ls = synth.make_landscape(W, H, 103, wind="smooth")
-    c = synth.ignition_site(ls)
+    apply_tuned(g)
+    ls = synth.scan_landscape()
+    W, H = synth.SCAN_SIZE
+    beta = synth.SCAN_BETA
+    c = synth.scan_ignition(ls)
     lid = g.load_landscape(ls)
-    res, maps = g.run(np.array([BETA_STAR]), fire.make_sims(16, lid, -1, c), TARGET_SEED,
+    res, maps = g.run(np.array([beta]), fire.make_sims(64, lid, -1, c), TARGET_SEED,
                       want_maps=True)
     g.sync()
     r = fire.results_to_numpy(res)
-    k = int(np.argmax(r["burnt"]))
-    tid = g.load_target(lid, maps.cpu().numpy().view(np.uint32)[k].reshape(H, -1))
+    m = maps.cpu().numpy().view(np.uint32).reshape(64, H, -1)
+    k = next(i for i in range(64)
+             if 0.02 <= r["burnt"][i] / (W * H) <= 0.20 and not (
+                 m[i, 0].any() or m[i, -1].any() or (m[i, :, 0] & 1).any()
+                 or ((m[i, :, -1] >> ((W - 1) % 32)) & 1).any()))
+    tid = g.load_target(lid, m[k])
     cands = scan.candidate_grid(c, W, H, spacing=4, half=8)
-    scan.run_scan(g, lid, tid, BETA_STAR, cands, R=32, seed=SIM_SEED, cutoff=0.3)  # warm-up
+    scan.run_scan(g, lid, tid, beta, cands, R=32, seed=SIM_SEED, cutoff=0.3)  # warm-up
     g.sync()
     times = []
     for _ in range(5):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = scan.run_scan(g, lid, tid, BETA_STAR, cands, R=32, seed=SIM_SEED, cutoff=0.3)
+        out = scan.run_scan(g, lid, tid, beta, cands, R=32, seed=SIM_SEED, cutoff=0.3)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     mean = out["mean"].cpu().numpy()
@@ -306,9 +320,10 @@ def run_scan(log_fn):
     dt = float(np.median(times))
     g.close()
     log_fn(f"scan: {len(cands)} x 32 simulations in {dt * 1e3:.2f} ms; true ignition ranks {rank}")
-    return {"lattice": [W, H], "candidates": len(cands), "replicates": 32,
+    return {"lattice": [W, H], "beta": list(beta), "candidates": len(cands), "replicates": 32,
             "wall_ms": dt * 1e3, "sims_per_s": len(cands) * 32 / dt,
-            "true_candidate_rank": rank, "reference_cells": int(r["burnt"][k])}
+            "true_candidate_rank": rank, "reference_cells": int(r["burnt"][k]),
+            "reference_replicate": k}
 
 
 def run_uneven(log_fn):
@@ -319,6 +334,7 @@ def run_uneven(log_fn):
     import torch
     from paper_1701_03549_amd import fire, synth
     g = fire.FireGPU(0)
+    apply_tuned(g)
     sizes = [(128, 128, 101), (256, 256, 102), (512, 512, 103), (1024, 768, 104)]
     lids, sims = [], []
     rng = np.random.default_rng(404)
@@ -350,15 +366,45 @@ def run_uneven(log_fn):
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
     same = bool(torch.equal(res, out))
+    # the single launch captured as a graph, as a GA generation launches it
+    out_g = torch.empty_like(out)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.run_dev(d_beta, d_sims, 2000, SIM_SEED, out_g, stream=torch.cuda.current_stream())
+    tr = []
+    for _ in range(3):
+        out_g.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        tr.append(time.perf_counter() - t0)
+    same_graph = bool(torch.equal(out_g, out))
+    del graph
+    # load balance of each form, from the per-simulation device clocks
+    from paper_1701_03549_amd.timing import load_balance
+    clocks = torch.zeros((2000, 2), dtype=torch.int64, device="cuda")
+    g.set_sim_timing(clocks)
+    g.run_dev(d_beta, d_sims, 2000, SIM_SEED, out)
+    g.sync()
+    lb_single = load_balance(clocks.cpu().numpy())
+    clocks.zero_()
+    g.run(betas, sims, SIM_SEED)
+    g.sync()
+    lb_grouped = load_balance(clocks.cpu().numpy())
+    g.set_sim_timing(None)
     r = fire.results_to_numpy(res)
     trials = int(r["trials"].sum())
     g.close()
-    dt_g, dt_s = float(np.median(tg)), float(np.median(ts))
-    log_fn(f"uneven: grouped {dt_g * 1e3:.1f} ms, single launch {dt_s * 1e3:.1f} ms")
+    dt_g, dt_s, dt_r = float(np.median(tg)), float(np.median(ts)), float(np.median(tr))
+    log_fn(f"uneven: grouped {dt_g * 1e3:.1f} ms, single launch {dt_s * 1e3:.1f} ms, graph replay "
+           f"{dt_r * 1e3:.1f} ms; load balance single {lb_single}, grouped {lb_grouped}")
     return {"sims": 2000, "lattices": [[w, h] for w, h, _ in sizes],
-            "grouped_ms": dt_g * 1e3, "single_launch_ms": dt_s * 1e3,
+            "grouped_ms": dt_g * 1e3, "single_launch_ms": dt_s * 1e3, "graph_replay_ms": dt_r * 1e3,
             "grouped_sims_per_s": 2000 / dt_g, "grouped_trials_per_s": trials / dt_g,
-            "identical_results": same, "mean_burnt": float(r["burnt"].mean())}
+            "identical_results": same, "graph_identical": same_graph,
+            "load_balance_single": lb_single, "load_balance_grouped": lb_grouped,
+            "mean_burnt": float(r["burnt"].mean())}
 
 
 def run_surrogate(log_fn):
@@ -453,6 +499,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     g = fire.FireGPU(0)
+    n_tuned = apply_tuned(g)
     ls = synth.make_landscape(W, H, LANDSCAPE_SEED)
     centre = synth.ignition_site(ls)
     lid = g.load_landscape(ls)
@@ -546,7 +593,8 @@ def main():
                                "NW-facing slope nearest the centre, run to extinction, Eq. 2 "
                                "vs a contained reference fire",
                    "lattice": [W, H], "sims_per_step": N_SIMS, "beta": list(BETA_STAR),
-                   "ignition": list(centre), "schedule": sched, "threshold_mode": "table"},
+                   "ignition": list(centre), "schedule": sched, "threshold_mode": "table",
+                   "tuned_schedules": n_tuned},
         "trials_per_s": trials_per_s,
         "mean_burnt": burnt / N_SIMS, "mean_trials": trials / N_SIMS,
         "roofline": {

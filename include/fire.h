@@ -244,6 +244,19 @@ fire_status fire_run_dev_noalloc(fire_ctx *ctx, const double *betas_dev,
                                  fire_result *out, uint32_t *out_maps,
                                  int64_t map_words, void *stream);
 
+/* Per-simulation clocks, for load-balance analysis of the persistent
+ * launches (not a passage of the paper: a diagnostic of the batch
+ * scheduler). While set, every simulation launch of the context writes, for
+ * batch index i < capacity, times_dev[2i] = the device's constant 100 MHz
+ * wall clock when a workgroup took simulation i and times_dev[2i + 1] = the
+ * clock when its result was written; a simulation that is run again over
+ * the whole lattice (LDS windows) keeps the second run's pair. times_dev is
+ * the caller's device buffer of 2 * capacity uint64 words, 8-byte aligned,
+ * and must stay allocated while launches that use it run; launches already
+ * captured into a graph keep the buffer they were captured with. NULL stops
+ * the writes. FIRE_E_INVALID for capacity < 1 with a buffer. */
+fire_status fire_set_sim_timing(fire_ctx *ctx, uint64_t *times_dev, int64_t capacity);
+
 /* ---- schedule (autotuner hooks) --------------------------------------- */
 
 typedef struct {

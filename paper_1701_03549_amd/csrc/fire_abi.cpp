@@ -113,6 +113,9 @@ struct fire_ctx {
   std::vector<void *> retired;
   // this device's copy of the no-allocation scratch array (set at creation)
   uint32_t *noalloc = nullptr;
+  // caller's buffer for per-simulation start/end clocks (fire_set_sim_timing)
+  uint64_t *times = nullptr;
+  int64_t times_cap = 0;
 };
 
 namespace {
@@ -666,6 +669,7 @@ SimArgs sim_args(fire_ctx *c, const double *betas_dev, int32_t n_params,
   a.ovf_life = dur ? reinterpret_cast<uint8_t *>(spill + (int64_t)grid * 2 * ovf_cap) : nullptr;
   a.queue_cap = queue_cap; a.bitset_words = bitset_words;
   a.win = 0; a.retry = nullptr; a.n_dev = nullptr; a.stat_out = nullptr;
+  a.times = c->times; a.times_cap = c->times ? c->times_cap : 0;
   return a;
 }
 
@@ -812,6 +816,17 @@ void fire_ctx_destroy(fire_ctx *c) {
 
 const char *fire_last_error(const fire_ctx *c) {
   return c ? c->err.c_str() : "null context";
+}
+
+fire_status fire_set_sim_timing(fire_ctx *c, uint64_t *times_dev, int64_t capacity) {
+  if (!c) return FIRE_E_INVALID;
+  if (times_dev && capacity < 1)
+    return fail(c, FIRE_E_INVALID, "timing buffer capacity %lld", (long long)capacity);
+  if (times_dev && ((uintptr_t)times_dev) % 8 != 0)
+    return fail(c, FIRE_E_INVALID, "timing buffer must be 8-byte aligned");
+  c->times = times_dev;
+  c->times_cap = times_dev ? capacity : 0;
+  return FIRE_OK;
 }
 
 fire_status fire_sync(fire_ctx *c, void *stream) {

@@ -63,6 +63,9 @@ struct SimArgs {
                            // fire reached the window edge
   const uint32_t *n_dev;   // NULL, or the device count of simulations (else n_sims)
   uint32_t *stat_out;      // NULL, or a host-mapped word that receives *n_dev
+  uint64_t *times;         // NULL, or per simulation i < times_cap: [2i] wall clock
+  int64_t times_cap;       // when a workgroup took it, [2i + 1] when its result was
+                           // written (100 MHz ticks)
 };
 
 // Launchers (fire_kernels.hip). Each returns the hipError_t of its launch.

@@ -342,7 +342,10 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     if (tid == 0) {
       const uint32_t k = atomicAdd(a.work, 1u);
       const uint32_t n = a.n_dev ? *a.n_dev : (uint32_t)a.n_sims;
-      ctl[kSim] = k < n ? (a.order ? a.order[k] : k) : 0xFFFFFFFFu;
+      const uint32_t took = k < n ? (a.order ? a.order[k] : k) : 0xFFFFFFFFu;
+      ctl[kSim] = took;
+      if (a.times != nullptr && (int64_t)took < a.times_cap)
+        a.times[2 * (int64_t)took] = wall_clock64();
     }
     __syncthreads();
     const uint32_t sim = ctl[kSim];
@@ -379,6 +382,8 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         r.burnt = 0; r.steps = 0xFFFFFFFFu; r.trials = 0;
         r.fitness = __builtin_nan("");
         a.out[sim] = r;
+        if (a.times != nullptr && (int64_t)sim < a.times_cap)
+          a.times[2 * (int64_t)sim + 1] = wall_clock64();
         atomicOr(a.error_flag, 1u);
       }
       __syncthreads();
@@ -397,6 +402,8 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         r.burnt = 0; r.steps = 0; r.trials = 0;
         r.fitness = has_target ? 1.0 : __builtin_nan("");
         a.out[sim] = r;
+        if (a.times != nullptr && (int64_t)sim < a.times_cap)
+          a.times[2 * (int64_t)sim + 1] = wall_clock64();
       }
       if (a.maps != nullptr) {
         uint32_t *m = a.maps + (int64_t)sim * a.map_words;
@@ -800,6 +807,8 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         r.fitness = __builtin_nan("");
       }
       a.out[sim] = r;
+      if (a.times != nullptr && (int64_t)sim < a.times_cap)
+        a.times[2 * (int64_t)sim + 1] = wall_clock64();
     }
     if (a.maps != nullptr) {
       uint32_t *m = a.maps + (int64_t)sim * a.map_words;
@@ -867,6 +876,8 @@ __global__ __launch_bounds__(kWave) void simw_kernel(SimArgs a) {
       const uint32_t k = atomicAdd(a.work, 1u);
       const uint32_t n = a.n_dev ? *a.n_dev : (uint32_t)a.n_sims;
       sim = k < n ? (a.order ? a.order[k] : k) : 0xFFFFFFFFu;
+      if (a.times != nullptr && (int64_t)sim < a.times_cap)
+        a.times[2 * (int64_t)sim] = wall_clock64();
     }
     sim = __builtin_amdgcn_readfirstlane(sim);
     if (sim == 0xFFFFFFFFu) break;
@@ -902,6 +913,8 @@ __global__ __launch_bounds__(kWave) void simw_kernel(SimArgs a) {
         r.burnt = 0; r.steps = 0xFFFFFFFFu; r.trials = 0;
         r.fitness = __builtin_nan("");
         a.out[sim] = r;
+        if (a.times != nullptr && (int64_t)sim < a.times_cap)
+          a.times[2 * (int64_t)sim + 1] = wall_clock64();
         atomicOr(a.error_flag, 1u);
       }
       continue;
@@ -917,6 +930,8 @@ __global__ __launch_bounds__(kWave) void simw_kernel(SimArgs a) {
         r.burnt = 0; r.steps = 0; r.trials = 0;
         r.fitness = has_target ? 1.0 : __builtin_nan("");
         a.out[sim] = r;
+        if (a.times != nullptr && (int64_t)sim < a.times_cap)
+          a.times[2 * (int64_t)sim + 1] = wall_clock64();
       }
       if (a.maps != nullptr) {
         uint32_t *m = a.maps + (int64_t)sim * a.map_words;
@@ -1226,6 +1241,8 @@ __global__ __launch_bounds__(kWave) void simw_kernel(SimArgs a) {
         r.fitness = __builtin_nan("");
       }
       a.out[sim] = r;
+      if (a.times != nullptr && (int64_t)sim < a.times_cap)
+        a.times[2 * (int64_t)sim + 1] = wall_clock64();
     }
     if (a.maps != nullptr) {
       uint32_t *m = a.maps + (int64_t)sim * a.map_words;

@@ -30,6 +30,7 @@ EXPORTS = ["fire_ctx_create", "fire_ctx_destroy", "fire_last_error", "fire_sync"
            "fire_landscape_load", "fire_landscape_free", "fire_landscape_set_burn_steps",
            "fire_target_load", "fire_target_free",
            "fire_thresholds", "fire_run", "fire_run_dev", "fire_run_dev_noalloc", "fire_run_dense",
+           "fire_set_sim_timing",
            "fire_set_schedule",
            "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_step_genes",
            "fire_ga_sims_from_pop", "fire_ga_run", "fire_ga_run_ignition", "fire_ensemble", "fire_scan_reduce"]
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "fire_run_dev": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_run_dev_noalloc": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_run_dense": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, i64, vp]),
+        "fire_set_sim_timing": (i32, [vp, vp, i64]),
         "fire_set_schedule": (i32, [vp, ctypes.POINTER(Schedule)]),
         "fire_get_schedule": (i32, [vp, i64, i32, i32, ctypes.POINTER(Schedule)]),
         "fire_set_class_schedule": (i32, [vp, i64, i32, ctypes.POINTER(Schedule)]),
@@ -284,6 +286,18 @@ class FireGPU:
             self.ctx, _ptr(betas_dev), n_params, _ptr(sims_dev), n_sims,
             int(seed) & (2 ** 64 - 1), _ptr(override), _ptr(out), _ptr(maps), map_words,
             _stream(stream)))
+
+    def set_sim_timing(self, times: torch.Tensor | None):
+        """fire_set_sim_timing: per-simulation (take, finish) device clocks
+        into `times` (int64, shape (capacity, 2), on this device) until
+        called with None."""
+        if times is None:
+            self._check(self.lib.fire_set_sim_timing(self.ctx, None, 0))
+            return
+        if times.dtype != torch.int64 or times.dim() != 2 or times.shape[1] != 2 \
+                or not times.is_contiguous():
+            raise ValueError("times must be a contiguous int64 tensor of shape (n, 2)")
+        self._check(self.lib.fire_set_sim_timing(self.ctx, _ptr(times), times.shape[0]))
 
     # -- schedule ------------------------------------------------------------
     def set_schedule(self, threads=None, queue_cap=None, table_mode=None, wg_per_cu=None,

@@ -147,3 +147,50 @@ def test_capture_rules(g):
     g.sync()
     del graph
     g.free_landscape(lid)
+
+
+def test_sim_timing_clocks(g):
+    """Per-simulation clocks: results with the clocks on equal results with
+    them off; every simulation gets a take and a later finish stamp, and the
+    load-balance summary is consistent (slots at most the simulations, span
+    at least the longest simulation)."""
+    import torch
+    from paper_1701_03549_amd import fire
+    from paper_1701_03549_amd.timing import load_balance
+    lss, lids, betas, which, sims = _mixed(g, n=200)
+    n = len(sims)
+    d_sims = torch.from_numpy(sims.view(np.uint8).copy()).cuda()
+    d_beta = torch.from_numpy(betas.copy()).cuda()
+    out0 = torch.empty((n, 24), dtype=torch.uint8, device="cuda")
+    out1 = torch.empty_like(out0)
+    say("timing: off")
+    g.run_dev(d_beta, d_sims, n, SEED, out0)
+    g.sync()
+    clocks = torch.zeros((n, 2), dtype=torch.int64, device="cuda")
+    g.set_sim_timing(clocks)
+    say("timing: on (device descriptors, then grouped host path)")
+    g.run_dev(d_beta, d_sims, n, SEED, out1)
+    g.sync()
+    t = clocks.cpu().numpy()
+    assert torch.equal(out0, out1)
+    assert np.all(t[:, 0] > 0) and np.all(t[:, 1] >= t[:, 0])
+    lb = load_balance(t)
+    assert lb["sims"] == n and 1 <= lb["slots"] <= n
+    assert lb["span_ms"] >= lb["longest_sim_ms"] > 0 and 0 < lb["efficiency"] <= 1
+    clocks.zero_()
+    res, _ = g.run(betas, sims, SEED)
+    g.sync()
+    assert torch.equal(res, out0)
+    t = clocks.cpu().numpy()
+    assert np.all(t[:, 0] > 0) and np.all(t[:, 1] >= t[:, 0])
+    # a buffer shorter than the batch: stamps only below its capacity
+    short = torch.zeros((n // 2, 2), dtype=torch.int64, device="cuda")
+    g.set_sim_timing(short)
+    g.run_dev(d_beta, d_sims, n, SEED, out1)
+    g.sync()
+    assert torch.equal(out0, out1) and np.all(short.cpu().numpy()[:, 0] > 0)
+    g.set_sim_timing(None)
+    with pytest.raises(ValueError):
+        g.set_sim_timing(torch.zeros(8, dtype=torch.int64, device="cuda"))
+    for lid in lids:
+        g.free_landscape(lid)

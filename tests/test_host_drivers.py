@@ -49,8 +49,26 @@ def test_autotune_candidates():
     assert wins == {0, 128, 256, 384}
     assert {c["table_mode"] for c in cs} == {0, 1}
     assert all(c["threads"] in (128, 256, 512, 1024) for c in cs if c["wave"] == 0)
-    waves = [c for c in cs if c["wave"] == 1]
-    assert waves and all(c["threads"] == 64 and c["wg_per_cu"] == 1 for c in waves)
-    assert {c["window"] for c in waves} == {0, 128, 256, 384}
+    assert all(c["wave"] == 0 for c in cs)
     assert not any(c["threads"] == 1024 and c["window"] > 0 for c in cs)
     assert {c["window"] for c in autotune.candidates(False, side=64)} == {0}
+
+
+def test_load_balance_of_sim_clocks():
+    from paper_1701_03549_amd.timing import load_balance
+    # 4 slots, 8 simulations of 10 ticks packed back to back: no idle slot
+    t = np.array([[100 + 10 * (i // 4), 110 + 10 * (i // 4)] for i in range(8)])
+    lb = load_balance(t, hz=1.0)
+    assert lb["slots"] == 4 and lb["span_ms"] == 20e3 and lb["efficiency"] == 1.0
+    assert lb["tail_ms"] == 10e3 and lb["drain_ms"] == 0.0 and lb["sims"] == 8
+    # 2 slots: one holds a 30-tick and then a 50-tick simulation, the other
+    # four of 10 ticks; the straggler runs alone for its last 40 ticks
+    t = np.array([[1000, 1030], [1000, 1010], [1010, 1020], [1020, 1030], [1030, 1080],
+                  [1030, 1040]])
+    lb = load_balance(t, hz=1.0)
+    assert lb["slots"] == 2 and lb["span_ms"] == 80e3
+    assert abs(lb["efficiency"] - 120 / (2 * 80)) < 1e-12
+    assert lb["tail_ms"] == 50e3 and lb["drain_ms"] == 40e3 and lb["longest_sim_ms"] == 50e3
+    # incomplete pairs (never taken, or not finished) are left out
+    t = np.array([[0, 0], [5, 3], [1, 4]])  # never taken, no result, complete
+    assert load_balance(t, hz=1.0)["sims"] == 1
