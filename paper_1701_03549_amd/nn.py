@@ -128,6 +128,16 @@ class Surrogate:
         self.max_batch = int(max_batch)
         self.num_params = int(self.lib.fire_nn_num_params(h))
         self.steps = 0
+        self._args = dict(device=device, max_batch=max_batch, lattice=tuple(lattice),
+                          w_map=w_map, seed=seed, adam=tuple(adam))
+
+    def clone(self) -> "Surrogate":
+        """A new handle with this one's configuration and parameters and a
+        fresh optimiser (zero Adam moments, step count 0)."""
+        c = Surrogate(**self._args)
+        c.set_params(self.get_params())
+        torch.cuda.synchronize()
+        return c
 
     def close(self):
         if getattr(self, "h", None):

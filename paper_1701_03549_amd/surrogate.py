@@ -13,7 +13,8 @@
    (fire_nn_select); every kept individual is then evaluated by exact
    simulation, which is what the GA uses, and those exact evaluations
    fine-tune the network online. Without a network it is the plain GA and
-   reproduces fire_ga_run bit for bit.
+   reproduces fire_ga_run bit for bit. A whole run can be captured as one
+   HIP graph and replayed.
 
 Training data drawn from the GA's own prior (Table 1's Gaussian) at the
 reference ignition ranks the GA's candidates far better than data from the
@@ -90,23 +91,38 @@ def spearman(a: np.ndarray, b: np.ndarray) -> float:
     return float((ra * rb).sum() / np.sqrt((ra ** 2).sum() * (rb ** 2).sum()))
 
 
+def online_indices(generations: int, P: int, R: int, steps: int, batch: int, seed: int):
+    """Minibatch rows of the online Adam steps of every generation, drawn
+    before the first generation runs: generation g draws `steps` batches of
+    min(batch, (g + 1) P R) rows uniformly from the (g + 1) P R exact
+    evaluations made so far."""
+    rng = np.random.default_rng(seed)
+    return [rng.integers(0, (gen + 1) * P * R, size=(steps, min(batch, (gen + 1) * P * R)))
+            for gen in range(generations)]
+
+
 def run_ga(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=0, ga_seed=0,
            net: nn.Surrogate | None = None, oversample=8, cfg=None, online_steps=8,
-           online_lr=5e-4, unscreened=None, seed=0):
+           online_lr=5e-4, unscreened=None, seed=0, graph=False):
     """GA with optional surrogate screening. Returns (hist_pop, hist_fit,
     timings). With screening: `unscreened` offspring of the first set are
     kept as the plain GA would keep them, the rest of the population is the
     best-predicted of all `oversample` sets; with `online_steps` > 0 the
     network takes that many Adam steps per generation on every exact
-    evaluation made so far (which are free training data)."""
+    evaluation made so far (which are free training data).
+
+    With `graph`, the whole run (every generation's simulations, network
+    steps, GA steps and selections) is captured as one HIP graph and replayed
+    once; the results are those of the eager run with the same arguments and
+    a network in the same state. Eager runs time simulation and screening
+    separately (a device synchronisation after each part of a generation)."""
     from .ga import default_cfg
     cfg = cfg or default_cfg(generations)
-    W, H = g.dims[lid]
     P = pop0.shape[0]
     E = int(cfg.elite)
     dev = g.device
-    stream = torch.cuda.current_stream()
-    pop = torch.from_numpy(np.ascontiguousarray(pop0, dtype=np.float64)).to(dev)
+    screen = net is not None and oversample > 1
+    pop_in = torch.from_numpy(np.ascontiguousarray(pop0, dtype=np.float64)).to(dev)
     hist_pop = torch.empty((generations, P, 5), dtype=torch.float64, device=dev)
     hist_fit = torch.empty((generations, P, R), dtype=torch.float64, device=dev)
     res = torch.empty((P * R, 24), dtype=torch.uint8, device=dev)
@@ -114,54 +130,77 @@ def run_ga(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=
     sims = fire.make_sims(generations * P * R, lid, tid, ign,
                           param_index=np.tile(np.repeat(np.arange(P), R), generations))
     d_sims_all = torch.from_numpy(sims.view(np.uint8).copy()).to(dev).reshape(-1, 28)
-    t_sim = t_nn = 0.0
     bank_x = torch.empty((generations * P * R, 7), dtype=torch.float32, device=dev)
     bank_y = torch.empty(generations * P * R, dtype=torch.float32, device=dev)
-    # minibatch indices are drawn on the device, so queuing a generation's
-    # work never waits for the GPU
-    gen_rng = torch.Generator(device=dev)
-    gen_rng.manual_seed(seed)
-    for gen in range(generations):
-        d_sims = d_sims_all[gen * P * R:(gen + 1) * P * R]
-        hist_pop[gen].copy_(pop)
-        t0 = time.perf_counter()
-        g.run_dev(pop, d_sims, P * R, sim_seed, res, stream=stream)
-        fit = res.view(torch.float64).reshape(P * R, 3)[:, 2].reshape(P, R).contiguous()
-        hist_fit[gen].copy_(fit)
-        torch.cuda.synchronize()
-        t_sim += time.perf_counter() - t0
-        if net is None or oversample <= 1:
-            g.ga_step(pop, fit, cfg, gen, ga_seed, stream=stream)
-            continue
-        t0 = time.perf_counter()
-        if online_steps > 0:
-            k0 = gen * P * R
-            bank_x[k0:k0 + P * R, :5] = pop.repeat_interleave(R, dim=0).float()
-            bank_x[k0:k0 + P * R, 5] = float(ign[0])
-            bank_x[k0:k0 + P * R, 6] = float(ign[1])
-            bank_y[k0:k0 + P * R] = torch.log1p(fit.reshape(-1)).float()
-            n_bank = k0 + P * R
-            for _ in range(online_steps):
-                idx = torch.randint(0, n_bank, (min(net.max_batch, n_bank),), generator=gen_rng,
-                                    device=dev)
-                net.train_step(bank_x[idx], bank_y[idx], None, lr=online_lr)
-        keep = E + ((P - E) // 2 if unscreened is None else unscreened)
-        sets = []
-        for o in range(oversample):
-            p = pop.clone()
-            g.ga_step(p, fit, cfg, gen, ga_seed + o * 0x9E3779B97F4A7C15, stream=stream)
-            sets.append(p if o == 0 else p[E:])
-        cand = torch.cat(sets).contiguous()
-        x = torch.empty((cand.shape[0], 7), dtype=torch.float32, device=dev)
-        x[:, :5] = cand.float()
-        x[:, 5] = float(ign[0])
-        x[:, 6] = float(ign[1])
-        score = net.predict(x)
-        pop, _ = nn.select(cand, score, keep=keep, k=P)
-        torch.cuda.synchronize()
-        t_nn += time.perf_counter() - t0
+    idx = []
+    if screen and online_steps > 0:
+        idx = [torch.from_numpy(a).to(dev)
+               for a in online_indices(generations, P, R, online_steps, net.max_batch, seed)]
+    keep = E + ((P - E) // 2 if unscreened is None else unscreened)
+    timing = {"simulation_s": 0.0, "screening_s": 0.0}
+
+    def body(stream, eager):
+        pop = pop_in.clone()
+        for gen in range(generations):
+            d_sims = d_sims_all[gen * P * R:(gen + 1) * P * R]
+            hist_pop[gen].copy_(pop)
+            t0 = time.perf_counter()
+            g.run_dev(pop, d_sims, P * R, sim_seed, res, stream=stream)
+            fit = res.view(torch.float64).reshape(P * R, 3)[:, 2].reshape(P, R).contiguous()
+            hist_fit[gen].copy_(fit)
+            if eager:
+                torch.cuda.synchronize()
+                timing["simulation_s"] += time.perf_counter() - t0
+            if not screen:
+                g.ga_step(pop, fit, cfg, gen, ga_seed, stream=stream)
+                continue
+            t0 = time.perf_counter()
+            if online_steps > 0:
+                k0 = gen * P * R
+                bank_x[k0:k0 + P * R, :5] = pop.repeat_interleave(R, dim=0).float()
+                bank_x[k0:k0 + P * R, 5] = float(ign[0])
+                bank_x[k0:k0 + P * R, 6] = float(ign[1])
+                bank_y[k0:k0 + P * R] = torch.log1p(fit.reshape(-1)).float()
+                for s in range(online_steps):
+                    rows = idx[gen][s]
+                    net.train_step(bank_x[rows], bank_y[rows], None, lr=online_lr, stream=stream)
+            sets = []
+            for o in range(oversample):
+                p = pop.clone()
+                g.ga_step(p, fit, cfg, gen, ga_seed + o * 0x9E3779B97F4A7C15, stream=stream)
+                sets.append(p if o == 0 else p[E:])
+            cand = torch.cat(sets).contiguous()
+            x = torch.empty((cand.shape[0], 7), dtype=torch.float32, device=dev)
+            x[:, :5] = cand.float()
+            x[:, 5] = float(ign[0])
+            x[:, 6] = float(ign[1])
+            score = net.predict(x, stream=stream)
+            pop, _ = nn.select(cand, score, keep=keep, k=P, stream=stream)
+            if eager:
+                torch.cuda.synchronize()
+                timing["screening_s"] += time.perf_counter() - t0
+
+    if not graph:
+        body(torch.cuda.current_stream(), True)
+        g.sync()
+        return hist_pop, hist_fit, timing
+    # the context's simulation buffers must not grow under capture: one
+    # eager launch of a generation's batch sizes them
+    g.run_dev(pop_in, d_sims_all[:P * R], P * R, sim_seed, res)
     g.sync()
-    return hist_pop, hist_fit, {"simulation_s": t_sim, "screening_s": t_nn}
+    t0 = time.perf_counter()
+    G = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(G):
+        body(torch.cuda.current_stream(), False)
+    timing["capture_s"] = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G.replay()
+    torch.cuda.synchronize()
+    timing["replay_s"] = time.perf_counter() - t0
+    del G
+    g.sync()
+    return hist_pop, hist_fit, timing
 
 
 def best_mean_fitness(hist_fit: torch.Tensor) -> float:

@@ -35,7 +35,6 @@ def test_screened_ga_beats_plain_ga():
     surrogate.train(net, X[10000:], y_t[10000:], y_map[10000:], epochs=4)
     pv = net.predict(X[:10000]).cpu().numpy()
     assert surrogate.spearman(pv, y_t[:10000].cpu().numpy()) > 0.85
-    trained = net.get_params()
     # the plain driver is the library's graph-captured GA, bit for bit
     pop0 = np.clip(np.random.default_rng(0).normal(0, 5, size=(64, 5)), -30, 30)
     hb = ga.run_batched(g, lid, tid, c, pop0, R=20, generations=3, sim_seed=1, ga_seed=2)
@@ -48,14 +47,49 @@ def test_screened_ga_beats_plain_ga():
         pop0 = np.clip(np.random.default_rng(100 + s).normal(0, 5, size=(64, 5)), -30, 30)
         _, fp, _ = surrogate.run_ga(g, lid, tid, c, pop0, R=20, generations=30,
                                     sim_seed=0x5EED0001 + s, ga_seed=0x6A00001 + s)
-        net.set_params(trained)
+        ns = net.clone()  # trained parameters, fresh optimiser
         _, fs, _ = surrogate.run_ga(g, lid, tid, c, pop0, R=20, generations=30,
-                                    sim_seed=0x5EED0001 + s, ga_seed=0x6A00001 + s, net=net,
+                                    sim_seed=0x5EED0001 + s, ga_seed=0x6A00001 + s, net=ns,
                                     seed=s)
+        ns.close()
         plain.append(surrogate.best_mean_fitness(fp))
         screened.append(surrogate.best_mean_fitness(fs))
     say(f"plain {np.round(plain, 4)} screened {np.round(screened, 4)}")
     assert np.mean(screened) < np.mean(plain)
     assert sum(b < a for a, b in zip(plain, screened)) >= 4
     net.close()
+    g.close()
+
+
+def test_screened_ga_graph_equals_eager():
+    """The screened GA captured as one graph (4 generations: simulations,
+    online Adam steps, 8 offspring sets, prediction, selection) and replayed
+    gives the eager run's populations, fitness values and final network
+    parameters exactly."""
+    import torch
+    from paper_1701_03549_amd import fire, nn, surrogate
+    g = fire.FireGPU(0)
+    W = H = 128
+    ls = synth.make_landscape(W, H, 101)
+    c = synth.ignition_site(ls)
+    lid = g.load_landscape(ls)
+    res, maps = g.run(np.array([BETA_STAR]), fire.make_sims(16, lid, -1, c), 0x7A26E7,
+                      want_maps=True)
+    g.sync()
+    k = int(np.argmax(fire.results_to_numpy(res)["burnt"]))
+    tid = g.load_target(lid, maps.cpu().numpy().view(np.uint32)[k].reshape(H, -1))
+    net = nn.Surrogate(max_batch=512, lattice=(W, H), w_map=1.0, seed=1)
+    pop0 = np.clip(np.random.default_rng(3).normal(0, 5, size=(64, 5)), -30, 30)
+    kw = dict(R=20, generations=4, sim_seed=11, ga_seed=12, seed=5)
+    a, b = net.clone(), net.clone()
+    say("screened GA: eager")
+    pe, fe, _ = surrogate.run_ga(g, lid, tid, c, pop0, net=a, **kw)
+    say("screened GA: captured graph")
+    pg, fg, tm = surrogate.run_ga(g, lid, tid, c, pop0, net=b, graph=True, **kw)
+    say(f"capture {tm['capture_s']:.3f} s, replay {tm['replay_s']:.4f} s")
+    assert torch.equal(pe, pg) and torch.equal(fe, fg)
+    assert torch.equal(a.get_params(), b.get_params())
+    assert a.steps == b.steps == 4 * 8
+    for h in (net, a, b):
+        h.close()
     g.close()
