@@ -445,29 +445,55 @@ def run_surrogate(log_fn):
     rho = surrogate.spearman(pv, y_t[:n_data // 10].cpu().numpy())
     trained = net.get_params()
     log_fn(f"surrogate: data {t_data:.2f} s, training {t_train:.2f} s, held-out Spearman {rho:.3f}")
-    plain, screened, tp, ts = [], [], 0.0, 0.0
+    from paper_1701_03549_amd import ga
+    rows = []
     for s_ in range(5):
         pop0 = np.clip(np.random.default_rng(100 + s_).normal(0, 5, size=(64, 5)), -30, 30)
+        kw = dict(R=20, sim_seed=SIM_SEED + s_, ga_seed=GA_SEED + s_)
+        # plain: the library's graph-captured GA, 30 generations
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, fp, _ = surrogate.run_ga(g, lid, tid, c, pop0, R=20, generations=30,
-                                    sim_seed=SIM_SEED + s_, ga_seed=GA_SEED + s_)
-        tp += time.perf_counter() - t0
-        net.set_params(trained)
-        t0 = time.perf_counter()
-        _, fs, _ = surrogate.run_ga(g, lid, tid, c, pop0, R=20, generations=30,
-                                    sim_seed=SIM_SEED + s_, ga_seed=GA_SEED + s_, net=net, seed=s_)
-        ts += time.perf_counter() - t0
-        plain.append(surrogate.best_mean_fitness(fp))
-        screened.append(surrogate.best_mean_fitness(fs))
+        _, fp = ga.run_batched(g, lid, tid, c, pop0, generations=30, **kw)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        plain = surrogate.best_mean_fitness(fp)
+        # screened: the whole 30-generation run captured as one graph, a
+        # fresh optimiser on the trained parameters
+        ns = net.clone()
+        _, fs, tm = surrogate.run_ga(g, lid, tid, c, pop0, generations=30, net=ns, seed=s_,
+                                     graph=True, **kw)
+        ns.close()
+        screened = surrogate.best_mean_fitness(fs)
+        # the plain GA at equal accuracy: the shortest run (30 ... 480
+        # generations) whose best mean fitness reaches the screened run's
+        match = None
+        for G in (30, 60, 120, 240, 480):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, fg = ga.run_batched(g, lid, tid, c, pop0, generations=G, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if surrogate.best_mean_fitness(fg) <= screened:
+                match = {"generations": G, "wall_s": dt, "sims": 64 * 20 * G}
+                break
+        rows.append({"plain_best_mean_fitness": plain, "plain_wall_s": t_plain,
+                     "screened_best_mean_fitness": screened,
+                     "screened_wall_s": tm["capture_s"] + tm["replay_s"],
+                     "screened_replay_s": tm["replay_s"], "plain_to_equal_accuracy": match})
+        log_fn(f"surrogate GA seed {s_}: {rows[-1]}")
     net.close()
     g.close()
     return {"lattice": [W, H], "training_runs": n_data, "data_s": t_data,
             "train_s": t_train, "train_samples_per_s": steps * batch / t_train,
             "gemm_tflops": steps * batch * gemm_flop / t_train / 1e12,
             "gemm_peak_tflops": 2500.0, "heldout_spearman": rho,
-            "ga_seeds": 5, "ga_sims_per_run": 64 * 20 * 30,
-            "plain_best_mean_fitness": plain, "screened_best_mean_fitness": screened,
-            "plain_wall_s": tp / 5, "screened_wall_s": ts / 5}
+            "ga_seeds": 5, "ga_sims_per_run": 64 * 20 * 30, "runs": rows,
+            "plain_best_mean_fitness": [r["plain_best_mean_fitness"] for r in rows],
+            "screened_best_mean_fitness": [r["screened_best_mean_fitness"] for r in rows],
+            "plain_wall_s": float(np.mean([r["plain_wall_s"] for r in rows])),
+            "screened_wall_s": float(np.mean([r["screened_wall_s"] for r in rows])),
+            "note": "screened wall time excludes the one-off training data ("
+                    f"{t_data:.2f} s) and training ({t_train:.2f} s) on this landscape"}
 
 
 def main():
@@ -515,7 +541,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(ev=None):
-        g.thresholds(lid, BETA_STAR, out=table, stream=stream)
+        g.thresholds_dev(lid, d_beta, out=table, stream=stream)
         if ev is not None:
             ev[0].record(stream)
         g.run_dev(d_beta, d_sims, N_SIMS, SIM_SEED, out, override=table, stream=stream)

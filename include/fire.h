@@ -130,6 +130,17 @@ fire_status fire_thresholds(fire_ctx *ctx, int32_t landscape_id,
                             const double beta[5], uint32_t *out_T,
                             void *stream);
 
+/* As fire_thresholds, for n_params parameter vectors already on the device
+ * (betas_dev: n_params x 5 binary64, row-major): table k goes to
+ * out_T + k * W*H*8 (device, 16-byte aligned, n_params tables). One launch,
+ * no host synchronisation and no allocation, so it can be captured into a
+ * graph. The parameters are not checked on the host: a non-finite value
+ * makes p NaN, which quantises to the saturated threshold (certain
+ * ignition). FIRE_E_INVALID for a null pointer, n_params < 1, an unknown
+ * landscape or a misaligned out_T. */
+fire_status fire_thresholds_dev(fire_ctx *ctx, int32_t landscape_id, const double *betas_dev,
+                                int32_t n_params, uint32_t *out_T, void *stream);
+
 /* ---- simulations (Methods: propagation rules; Eq. 2 fitness) ---------- */
 
 typedef struct {

@@ -1032,6 +1032,22 @@ fire_status fire_thresholds(fire_ctx *c, int32_t lid, const double beta[5],
   return FIRE_OK;
 }
 
+fire_status fire_thresholds_dev(fire_ctx *c, int32_t lid, const double *betas_dev,
+                                int32_t n_params, uint32_t *out_T, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (!betas_dev || !out_T || n_params < 1)
+    return fail(c, FIRE_E_INVALID, "null argument or n_params < 1");
+  if (lid < 0 || lid >= (int)c->ls.size() || !c->ls[lid].live)
+    return fail(c, FIRE_E_INVALID, "unknown landscape id %d", lid);
+  if (((uintptr_t)out_T) % 16 != 0)
+    return fail(c, FIRE_E_INVALID, "out_T must be 16-byte aligned");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  const LandscapeHost &L = c->ls[lid];
+  HIP_OR_FAIL(c, launch_thresholds_multi(c->d_ls + lid, L.W, L.H, betas_dev, n_params, L.forest,
+                                         out_T, (int64_t)L.W * L.H * 8, (hipStream_t)stream));
+  return FIRE_OK;
+}
+
 static fire_status check_sims_host(fire_ctx *c, const fire_sim *sims, int32_t n,
                                    int32_t n_params, int *bitset_words,
                                    int64_t *max_cells, int *one_ls,

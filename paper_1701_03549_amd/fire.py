@@ -29,7 +29,7 @@ STATUS = {0: "FIRE_OK", -1: "FIRE_E_INVALID", -2: "FIRE_E_OOM", -3: "FIRE_E_DEVI
 EXPORTS = ["fire_ctx_create", "fire_ctx_destroy", "fire_last_error", "fire_sync", "fire_version",
            "fire_landscape_load", "fire_landscape_free", "fire_landscape_set_burn_steps",
            "fire_target_load", "fire_target_free",
-           "fire_thresholds", "fire_run", "fire_run_dev", "fire_run_dev_noalloc", "fire_run_dense",
+           "fire_thresholds", "fire_thresholds_dev", "fire_run", "fire_run_dev", "fire_run_dev_noalloc", "fire_run_dense",
            "fire_set_sim_timing",
            "fire_set_schedule",
            "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_step_genes",
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "fire_target_free": (i32, [vp, i32]),
         "fire_landscape_set_burn_steps": (i32, [vp, i32, vp]),
         "fire_thresholds": (i32, [vp, i32, vp, vp, vp]),
+        "fire_thresholds_dev": (i32, [vp, i32, vp, i32, vp, vp]),
         "fire_run": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_run_dev": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_run_dev_noalloc": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
@@ -228,6 +229,23 @@ class FireGPU:
             out = torch.empty((H, W, 8), dtype=torch.int32, device=self.device)
         assert out.numel() == H * W * 8 and out.is_contiguous()
         self._check(self.lib.fire_thresholds(self.ctx, lid, b, _ptr(out), _stream(stream)))
+        return out
+
+    def thresholds_dev(self, lid: int, betas_dev: torch.Tensor, out: torch.Tensor | None = None,
+                       stream=None) -> torch.Tensor:
+        """fire_thresholds_dev: Eq. 1 tables [n_params][H][W][8] for the
+        float64 parameter rows of `betas_dev` (on the device); no host
+        synchronisation, capturable."""
+        W, H = self.dims[lid]
+        if betas_dev.dtype != torch.float64 or not betas_dev.is_contiguous() \
+                or betas_dev.numel() % 5 != 0 or betas_dev.numel() == 0:
+            raise ValueError("betas_dev must be a contiguous float64 tensor of n x 5 values")
+        n = betas_dev.numel() // 5
+        if out is None:
+            out = torch.empty((n, H, W, 8), dtype=torch.int32, device=self.device)
+        assert out.numel() == n * H * W * 8 and out.is_contiguous()
+        self._check(self.lib.fire_thresholds_dev(self.ctx, lid, _ptr(betas_dev), n, _ptr(out),
+                                                 _stream(stream)))
         return out
 
     # -- simulations ---------------------------------------------------------

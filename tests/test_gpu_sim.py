@@ -49,6 +49,27 @@ def test_thresholds_within_one_unit(g, W, H, seed):
     g.free_landscape(lid)
 
 
+def test_thresholds_dev_equals_host_entry(g):
+    """fire_thresholds_dev (device parameters, several tables in one launch)
+    writes the tables fire_thresholds writes; a NaN parameter saturates every
+    burnable edge."""
+    import torch
+    W, H = 100, 67
+    ls = synth.make_landscape(W, H, 6)
+    lid = g.load_landscape(ls)
+    betas = np.array([BETA_STAR, (0, 0, 0, 0, 0), (-5, -10, 5, 18.1, -5), (0.3, 0, 0, 0, 0),
+                      (np.nan, 0, 0, 0, 0)], dtype=np.float64)
+    say("thresholds from device parameters")
+    T = g.thresholds_dev(lid, torch.from_numpy(betas).cuda()).cpu().numpy().view(np.uint32)
+    for k in range(4):
+        assert np.array_equal(T[k], g.thresholds(lid, betas[k]).cpu().numpy().view(np.uint32))
+    # every edge into a burnable cell has a positive threshold at the
+    # calibration vector (its logit is at least -12.5)
+    live = T[0] > 0
+    assert np.all(T[4][live] == U32) and np.all(T[4][~live] == 0)
+    g.free_landscape(lid)
+
+
 def test_tables_for_many_parameter_vectors(g):
     """Table mode with 13 parameter vectors: one threshold launch writes the
     13 tables, 8 vectors per thread and a partial last group; every
