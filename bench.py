@@ -318,12 +318,41 @@ def run_scan(log_fn):
     true_k = int(np.argmin(np.abs(cands - np.array(c)).sum(axis=1)))
     rank = int((mean < mean[true_k]).sum())
     dt = float(np.median(times))
+    # surrogate screening of the candidates: a network trained on runs with
+    # ignitions uniform over the candidate box keeps 64 of the 256, which
+    # are then scanned exactly (with the coins of the full scan)
+    from paper_1701_03549_amd import nn, surrogate
+    x0, y0 = int(cands[:, 0].min()), int(cands[:, 1].min())
+    box = (x0, y0, int(cands[:, 0].max()) - x0 + 1, int(cands[:, 1].max()) - y0 + 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, y = surrogate.make_ignition_dataset(g, lid, tid, beta, box, 4096, seed=3, sim_seed=0xDA7A)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = nn.Surrogate(max_batch=512, lattice=box[2:], w_map=0.0, seed=1)
+    t0 = time.perf_counter()
+    surrogate.train(net, X, y, None, epochs=8, batch=512, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    kept, so = surrogate.screened_scan(g, net, lid, tid, beta, cands, box, 64, R=32,
+                                       seed=SIM_SEED, cutoff=0.3)
+    torch.cuda.synchronize()
+    t_screen = time.perf_counter() - t0
+    top = set(np.argsort(mean, kind="stable")[:64].tolist())
+    screening = {"training_runs": 4096, "data_s": t_data, "train_s": t_train,
+                 "kept": 64, "screened_scan_ms": t_screen * 1e3,
+                 "best_kept": bool(int(np.argmin(mean)) in set(kept.tolist())),
+                 "top64_overlap": len(top & set(kept.tolist())),
+                 "rows_equal_full_scan": bool(torch.equal(so["deltas"], out["deltas"][kept]))}
+    net.close()
     g.close()
-    log_fn(f"scan: {len(cands)} x 32 simulations in {dt * 1e3:.2f} ms; true ignition ranks {rank}")
+    log_fn(f"scan: {len(cands)} x 32 simulations in {dt * 1e3:.2f} ms; true ignition ranks {rank}; "
+           f"screening {screening}")
     return {"lattice": [W, H], "beta": list(beta), "candidates": len(cands), "replicates": 32,
             "wall_ms": dt * 1e3, "sims_per_s": len(cands) * 32 / dt,
             "true_candidate_rank": rank, "reference_cells": int(r["burnt"][k]),
-            "reference_replicate": k}
+            "reference_replicate": k, "screening": screening}
 
 
 def run_uneven(log_fn):

@@ -109,10 +109,11 @@ fire_status fire_pool_maps(const uint32_t *maps, int32_t n, int32_t W,
 
 /* Building block, exposed for tests: column sums out[n] = sum_m d[m*N + n]
  * of a row-major fp32 matrix d [M][N] (device pointers), the bias-gradient
- * reduction of the backward pass, in a fixed order: rows m = r, r + 4,
- * r + 8, ... are summed in order for each r = 0..3, and the four partial
- * sums are then added as ((p0 + p1) + p2) + p3, so repeated calls give
- * identical bits. M >= 1, N >= 1. */
+ * reduction of the backward pass, in a fixed order: rows m = r, r + 16,
+ * r + 32, ... are summed in order for each r = 0..15, and the sixteen
+ * partial sums are then added pairwise, (p0 + p1), (p2 + p3), ..., then
+ * those results pairwise in the same way down to one, so repeated calls
+ * give identical bits. M >= 1, N >= 1. */
 fire_status fire_colsum_f32(const float *d, int32_t M, int32_t N, float *out, void *stream);
 
 /* Screening selection for oversampled GA offspring: out [k][G] receives

@@ -36,47 +36,129 @@ int blocks_for(int64_t n, int t = 256) {
 
 // ---------------------------------------------------------------------------
 // GEMM: 64x64 output tile per workgroup of 4 waves, each wave one 32x32 MFMA
-// tile; K staged through LDS 32 at a time (A row-major, B transposed so that
-// each lane's 8 consecutive k of a fragment are contiguous).
+// tile; K staged through two LDS buffers 32 at a time (the next tile's
+// global loads are in flight while the current one is multiplied). Both
+// operands are stored in LDS as [row][k] (A rows are m, B rows are n), so
+// that each lane's 8 consecutive k of a fragment are contiguous. A thread
+// moves 8 bf16 of each operand per tile; how depends on the operand's
+// strides (LoadMode).
 constexpr int kTM = 64, kTN = 64, kTK = 32, kLdt = kTK + 8;
 
+// kAlongK: k is contiguous (stride 1) and rows start on 16-byte boundaries:
+//   one 16-byte load per thread, one 16-byte LDS store.
+// kAlongRows: rows are contiguous and k-slices start on 16-byte boundaries:
+//   one 16-byte load of 8 rows at one k, 8 two-byte LDS stores.
+// kElementwise: any strides, 8 two-byte loads.
+enum LoadMode { kElementwise = 0, kAlongK = 1, kAlongRows = 2 };
+
+template <int MODE>
+__device__ __forceinline__ void tile_load(const uint16_t *base, int64_t sr, int64_t sk, int row0,
+                                          int rows, int k0, int kdim, int t, uint16_t v[8]) {
+  if (MODE == kAlongK) {
+    const int row = row0 + (t >> 2), k = k0 + (t & 3) * 8;
+    if (row < rows && k + 8 <= kdim) {
+      const uint4 q = *reinterpret_cast<const uint4 *>(base + (int64_t)row * sr + k);
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[2 * j] = (uint16_t)(w[j] & 0xFFFFu);
+        v[2 * j + 1] = (uint16_t)(w[j] >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        v[i] = (row < rows && k + i < kdim) ? base[(int64_t)row * sr + k + i] : (uint16_t)0;
+    }
+  } else if (MODE == kAlongRows) {
+    const int k = k0 + (t >> 3), row = row0 + (t & 7) * 8;
+    if (k < kdim && row + 8 <= rows) {
+      const uint4 q = *reinterpret_cast<const uint4 *>(base + (int64_t)k * sk + row);
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[2 * j] = (uint16_t)(w[j] & 0xFFFFu);
+        v[2 * j + 1] = (uint16_t)(w[j] >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        v[i] = (k < kdim && row + i < rows) ? base[(int64_t)k * sk + row + i] : (uint16_t)0;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = t + 256 * i;
+      const int row = row0 + (e >> 5), k = k0 + (e & 31);
+      v[i] = (row < rows && k < kdim) ? base[(int64_t)row * sr + (int64_t)k * sk] : (uint16_t)0;
+    }
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void tile_store(uint16_t *S, int t, const uint16_t v[8]) {
+  if (MODE == kAlongK) {
+    uint4 q;
+    q.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+    q.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+    q.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+    q.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+    *reinterpret_cast<uint4 *>(&S[(t >> 2) * kLdt + (t & 3) * 8]) = q;
+  } else if (MODE == kAlongRows) {
+    const int kk = t >> 3, r = (t & 7) * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) S[(r + i) * kLdt + kk] = v[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = t + 256 * i;
+      S[(e >> 5) * kLdt + (e & 31)] = v[i];
+    }
+  }
+}
+
+template <int AM, int BM>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const uint16_t *A,
                                                    int64_t sam, int64_t sak, const uint16_t *B,
                                                    int64_t sbk, int64_t sbn, float *C,
                                                    int64_t ldc, const float *bias, int relu,
                                                    int accumulate, uint16_t *Cb) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[kTM * kLdt];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[kTN * kLdt];
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][kTM * kLdt];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kTN * kLdt];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   f32x16_t acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  uint16_t va[8], vb[8];
+  tile_load<AM>(A, sam, sak, m0, M, 0, K, tid, va);
+  tile_load<BM>(B, sbn, sbk, n0, N, 0, K, tid, vb);
+  tile_store<AM>(As[0], tid, va);
+  tile_store<BM>(Bs[0], tid, vb);
+  __syncthreads();
+  const int half = lane >> 5, r = lane & 31;
+  int buf = 0;
   for (int k0 = 0; k0 < K; k0 += kTK) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = tid + 256 * i;
-      const int r = e >> 5, kk = e & 31;
-      const int m = m0 + r, k = k0 + kk;
-      As[r * kLdt + kk] = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : (uint16_t)0;
+    const bool more = k0 + kTK < K;
+    if (more) {
+      tile_load<AM>(A, sam, sak, m0, M, k0 + kTK, K, tid, va);
+      tile_load<BM>(B, sbn, sbk, n0, N, k0 + kTK, K, tid, vb);
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = tid + 256 * i;
-      const int nn = e & 63, kk = e >> 6;
-      const int n = n0 + nn, k = k0 + kk;
-      Bs[nn * kLdt + kk] = (n < N && k < K) ? B[(int64_t)k * sbk + (int64_t)n * sbn] : (uint16_t)0;
-    }
-    __syncthreads();
-    const int half = lane >> 5, r = lane & 31;
 #pragma unroll
     for (int kk = 0; kk < kTK; kk += 16) {
-      const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(&As[(wr + r) * kLdt + kk + half * 8]);
-      const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(&Bs[(wc + r) * kLdt + kk + half * 8]);
+      const bf16x8_t a =
+          *reinterpret_cast<const bf16x8_t *>(&As[buf][(wr + r) * kLdt + kk + half * 8]);
+      const bf16x8_t b =
+          *reinterpret_cast<const bf16x8_t *>(&Bs[buf][(wc + r) * kLdt + kk + half * 8]);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
+    if (more) {
+      // the other buffer was last read before the previous barrier
+      tile_store<AM>(As[buf ^ 1], tid, va);
+      tile_store<BM>(Bs[buf ^ 1], tid, vb);
+    }
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
@@ -94,13 +176,43 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const ui
   }
 }
 
+// how an operand of `rows` x `kdim` with strides (sr, sk) is loaded
+int load_mode(const uint16_t *p, int64_t sr, int64_t sk) {
+  if ((reinterpret_cast<uintptr_t>(p) & 15u) != 0) return kElementwise;
+  if (sk == 1 && sr % 8 == 0) return kAlongK;
+  if (sr == 1 && sk % 8 == 0) return kAlongRows;
+  return kElementwise;
+}
+
+template <int AM>
+hipError_t gemm_b(int bm, dim3 grid, hipStream_t s, int M, int N, int K, const uint16_t *A,
+                  int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk, int64_t sbn, float *C,
+                  int64_t ldc, const float *bias, int relu, int accumulate, uint16_t *Cb) {
+  if (bm == kAlongK)
+    hipLaunchKernelGGL((gemm_kernel<AM, kAlongK>), grid, dim3(256), 0, s, M, N, K, A, sam, sak,
+                       B, sbk, sbn, C, ldc, bias, relu, accumulate, Cb);
+  else if (bm == kAlongRows)
+    hipLaunchKernelGGL((gemm_kernel<AM, kAlongRows>), grid, dim3(256), 0, s, M, N, K, A, sam,
+                       sak, B, sbk, sbn, C, ldc, bias, relu, accumulate, Cb);
+  else
+    hipLaunchKernelGGL((gemm_kernel<AM, kElementwise>), grid, dim3(256), 0, s, M, N, K, A, sam,
+                       sak, B, sbk, sbn, C, ldc, bias, relu, accumulate, Cb);
+  return hipGetLastError();
+}
+
 hipError_t gemm(int M, int N, int K, const uint16_t *A, int64_t sam, int64_t sak,
                 const uint16_t *B, int64_t sbk, int64_t sbn, float *C, int64_t ldc,
                 const float *bias, int relu, int accumulate, uint16_t *Cb, hipStream_t s) {
   dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM);
-  hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, C,
-                     ldc, bias, relu, accumulate, Cb);
-  return hipGetLastError();
+  const int am = load_mode(A, sam, sak), bm = load_mode(B, sbn, sbk);
+  if (am == kAlongK)
+    return gemm_b<kAlongK>(bm, grid, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, relu,
+                           accumulate, Cb);
+  if (am == kAlongRows)
+    return gemm_b<kAlongRows>(bm, grid, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, relu,
+                              accumulate, Cb);
+  return gemm_b<kElementwise>(bm, grid, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, relu,
+                              accumulate, Cb);
 }
 
 // ---------------------------------------------------------------------------
@@ -135,19 +247,29 @@ __global__ void relu_bwd_kernel(float *g, const float *h, uint16_t *gb, int64_t 
 }
 
 // column sums of d [M][N] (bias gradients) in a fixed order: a workgroup of
-// 256 threads takes 64 columns; row group r (0..3) sums rows r, r+4, ... in
-// order, then the four partial sums are added in row-group order
-constexpr int kColsumCols = 64;
-__global__ void colsum_kernel(const float *d, int M, int N, float *out) {
-  __shared__ float part[4][kColsumCols];
+// 256 threads takes 16 columns; row group r (0..15) sums rows r, r+16, ...
+// in order, then the 16 partial sums are added pairwise:
+// p0+p1, p2+p3, ..., then those pairwise, down to one
+constexpr int kColsumCols = 16, kColsumGroups = 16;
+__global__ __launch_bounds__(256) void colsum_kernel(const float *d, int M, int N, float *out) {
+  __shared__ float part[kColsumGroups][kColsumCols];
   const int c = threadIdx.x % kColsumCols, rg = threadIdx.x / kColsumCols;
   const int n = blockIdx.x * kColsumCols + c;
   float s = 0.0f;
   if (n < N)
-    for (int m = rg; m < M; m += 4) s += d[(int64_t)m * N + n];
+    for (int m = rg; m < M; m += kColsumGroups) s += d[(int64_t)m * N + n];
   part[rg][c] = s;
   __syncthreads();
-  if (rg == 0 && n < N) out[n] = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
+  if (rg == 0 && n < N) {
+    float p[kColsumGroups];
+#pragma unroll
+    for (int i = 0; i < kColsumGroups; ++i) p[i] = part[i][c];
+#pragma unroll
+    for (int w = kColsumGroups; w > 1; w >>= 1)
+#pragma unroll
+      for (int i = 0; i < w / 2; ++i) p[i] = p[2 * i] + p[2 * i + 1];
+    out[n] = p[0];
+  }
 }
 
 int colsum_blocks(int N) { return (N + kColsumCols - 1) / kColsumCols; }

@@ -203,6 +203,54 @@ def run_ga(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=
     return hist_pop, hist_fit, timing
 
 
+def make_ignition_dataset(g: fire.FireGPU, lid: int, tid: int, beta, box, n: int, seed: int,
+                          sim_seed: int, chunk=8192):
+    """Training runs for ignition screening: parameters fixed at `beta`,
+    ignition cells uniform over box = (x0, y0, w, h). Inputs are
+    (beta, x - x0, y - y0), for a network whose lattice is the box (w, h);
+    targets log(1 + delta) against the reference map."""
+    x0, y0, bw, bh = box
+    rng = np.random.default_rng(seed)
+    ign = np.stack([rng.integers(x0, x0 + bw, n), rng.integers(y0, y0 + bh, n)], 1)
+    X = torch.empty((n, 7), dtype=torch.float32, device=g.device)
+    y_t = torch.empty(n, dtype=torch.float32, device=g.device)
+    beta = np.asarray(beta, dtype=np.float64)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        sims = fire.make_sims(e - s, lid, tid, ign[s:e], param_index=0,
+                              sim_index=np.arange(s, e, dtype=np.uint32))
+        res, _ = g.run(beta[None, :], sims, sim_seed)
+        y_t[s:e] = torch.log1p(res.view(torch.float64).reshape(-1, 3)[:, 2]).float()
+        X[s:e, :5] = torch.from_numpy(np.tile(beta, (e - s, 1))).float().to(g.device)
+        X[s:e, 5:] = torch.from_numpy(ign[s:e] - np.array([x0, y0])).float().to(g.device)
+    g.sync()
+    return X, y_t
+
+
+def screen_ignitions(net: nn.Surrogate, beta, cands, box, keep: int) -> np.ndarray:
+    """Grid positions of the `keep` candidate cells with the lowest predicted
+    fitness (a network trained by make_ignition_dataset on the same box)."""
+    x0, y0 = box[0], box[1]
+    c = np.asarray(cands, dtype=np.float64)
+    x = torch.empty((len(c), 7), dtype=torch.float32, device=net.device)
+    x[:, :5] = torch.tensor(np.asarray(beta, dtype=np.float32), device=net.device)
+    x[:, 5:] = torch.from_numpy((c - np.array([x0, y0])).astype(np.float32)).to(net.device)
+    score = net.predict(x).cpu().numpy()
+    return np.sort(np.argsort(score, kind="stable")[:keep])
+
+
+def screened_scan(g: fire.FireGPU, net: nn.Surrogate, lid, tid, beta, cands, box, keep, R=32,
+                  seed=0, cutoff=0.3):
+    """Ignition scan of the `keep` best-predicted candidates only, each by R
+    exact simulations with the coins the full scan would draw for it (its
+    rows equal the full scan's rows). Returns (kept grid positions, scan)."""
+    from . import scan
+    kept = screen_ignitions(net, beta, cands, box, keep)
+    out = scan.run_scan(g, lid, tid, beta, np.asarray(cands)[kept], R=R, seed=seed,
+                        cutoff=cutoff, index=kept)
+    return kept, out
+
+
 def best_mean_fitness(hist_fit: torch.Tensor) -> float:
     """Lowest mean-over-replicates fitness of any evaluated individual."""
     return float(hist_fit.mean(dim=2).min().item())

@@ -1,7 +1,9 @@
 """GPU checks of the learned surrogate (through the C ABI in fire_nn.h).
 
 * the MFMA bf16 GEMM against binary64 products of the same bf16 inputs, for
-  every transpose pattern the network uses, ragged sizes and the epilogues;
+  every transpose pattern the network uses and each way an operand's tile is
+  loaded (16-byte loads along k or along rows, element by element), ragged
+  sizes and the epilogues;
 * burn-map pooling against numpy;
 * loss and every parameter gradient of the whole network against the
   binary64 reference with the same bf16 rounding points (oracle/surrogate_ref),
@@ -32,7 +34,9 @@ def _bits(t):
 @pytest.mark.parametrize("M,N,K,ta,tb", [(64, 64, 32, 0, 0), (100, 37, 70, 0, 0),
                                           (256, 16, 513, 1, 0), (33, 300, 17, 0, 1),
                                           (7, 1, 256, 0, 0), (256, 2048, 9, 1, 0),
-                                          (130, 257, 129, 1, 1)])
+                                          (130, 257, 129, 1, 1), (96, 80, 64, 0, 1),
+                                          (72, 136, 40, 1, 1), (512, 256, 256, 0, 0),
+                                          (256, 256, 512, 1, 0)])
 def test_gemm_bf16_against_binary64(M, N, K, ta, tb):
     import torch
     from paper_1701_03549_amd import nn
@@ -140,12 +144,13 @@ def test_gradients_match_reference_per_element(B, seed, blo, bhi):
     net.close()
 
 
-@pytest.mark.parametrize("M,N", [(1, 1), (6, 256), (13, 1), (7, 2048), (5, 100), (64, 65), (4, 64)])
+@pytest.mark.parametrize("M,N", [(1, 1), (6, 256), (13, 1), (7, 2048), (5, 100), (64, 65), (4, 64),
+                                 (512, 256), (37, 17)])
 def test_colsum_order_and_values(M, N):
     """Bias-gradient column sums: integer data (every partial sum exact in
-    fp32) equals the binary64 sum exactly; random data equals the binary64
-    sum of the fixed order (rows r, r+4, ... per group r, then
-    ((p0 + p1) + p2) + p3) evaluated in fp32, bit for bit."""
+    fp32) equals the binary64 sum exactly; random data equals the sum in
+    the fixed order (rows r, r+16, ... per group r = 0..15, then a pairwise
+    tree over the 16 partial sums) evaluated in fp32, bit for bit."""
     import torch
     from paper_1701_03549_amd import nn
     rng = np.random.default_rng(M * 1000 + N)
@@ -155,12 +160,15 @@ def test_colsum_order_and_values(M, N):
     x = rng.normal(size=(M, N)).astype(np.float32)
     got = nn.colsum(torch.from_numpy(x).cuda()).cpu().numpy()
     parts = []
-    for r in range(4):
+    for r in range(16):
         acc = np.zeros(N, dtype=np.float32)
-        for m in range(r, M, 4):
+        for m in range(r, M, 16):
             acc = (acc + x[m]).astype(np.float32)
         parts.append(acc)
-    want = ((parts[0] + parts[1]).astype(np.float32) + parts[2]).astype(np.float32) + parts[3]
+    while len(parts) > 1:
+        parts = [(parts[2 * i] + parts[2 * i + 1]).astype(np.float32)
+                 for i in range(len(parts) // 2)]
+    want = parts[0]
     assert np.array_equal(got, want.astype(np.float32))
     np.testing.assert_allclose(got, x.astype(np.float64).sum(axis=0),
                                rtol=0, atol=1e-5 * np.abs(x).sum(axis=0).max())
