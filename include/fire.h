@@ -307,12 +307,14 @@ typedef struct {
 fire_status fire_set_schedule(fire_ctx *ctx, const fire_schedule *s);
 /* Schedule for one size class and kind of batch: runs whose landscapes
  * have between 2^(b-1)+1 and 2^b cells, b = ceil(log2(max_cells)), and
- * (many_params = 0) at most 8 parameter vectors, as replicate batches have,
- * or (many_params = 1) more, as GA populations and Monte Carlo draws have,
- * use `s` unless a fixed schedule is set; its window and wave fields may be
- * -1 (built-in choice). NULL removes the class entry. Used by the
- * autotuner. */
-fire_status fire_set_class_schedule(fire_ctx *ctx, int64_t max_cells, int32_t many_params,
+ * whose batch is of `kind` -- 0: at most 8 parameter vectors (replicate
+ * batches); 1: more vectors with at least 8 simulations each (GA
+ * populations); 2: other batches (Monte Carlo draws, random-parameter
+ * batches) -- use `s` unless a fixed schedule is set; runs with turn-off
+ * times keep the built-in choice. Its window and wave fields may be -1
+ * (built-in choice). NULL removes the class entry. FIRE_E_INVALID for a
+ * kind outside 0..2 or a field out of range. Used by the autotuner. */
+fire_status fire_set_class_schedule(fire_ctx *ctx, int64_t max_cells, int32_t kind,
                                     const fire_schedule *s);
 /* The schedule a batch of `n_sims` simulations with `n_params` parameter
  * vectors on a square lattice of `max_cells` cells would use (window: the

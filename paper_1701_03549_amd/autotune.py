@@ -6,7 +6,7 @@ LDS queue capacity, threshold table vs per-trial evaluation) with HIP
 events on the launch stream, checks that every schedule returns bit-identical
 results (they must: results do not depend on the schedule), and keeps the
 fastest. Choices are cached per GPU architecture, size class and kind of
-batch (at most 8 parameter vectors, or more) in a JSON file committed beside
+batch (replicate, GA population, scattered) in a JSON file committed beside
 this module, and applied through fire_set_class_schedule.
 
     python -m paper_1701_03549_amd.autotune            # tune the built-in workloads
@@ -93,10 +93,11 @@ def tune(g: fire.FireGPU, lid: int, sims: np.ndarray, betas: np.ndarray, seed: i
     builtin = g.get_schedule(W * H, len(betas), n)
     ms = time_schedule(g, None, d_beta, d_sims, n, seed, out)
     ref = out.clone()
-    rows.append((ms, dict(builtin)))
+    rows.append((ms, dict(builtin, builtin=True)))
     if log:
         log(f"{ms:8.3f} ms  built-in {builtin}")
-    for sched in candidates(table_ok=len(betas) <= 8, side=side):
+    table_ok = len(betas) <= 8 or n >= 8 * len(betas)
+    for sched in candidates(table_ok=table_ok, side=side):
         if log:
             log(f"timing {sched}")
         try:
@@ -124,57 +125,85 @@ def load_cache(path: str = CACHE) -> dict:
     return {}
 
 
-KINDS = {"replicate": False, "many": True}
-
-
 def apply_cache(g: fire.FireGPU, path: str = CACHE) -> int:
     """Install the cached schedules of this architecture (per size class and
-    batch kind: at most 8 parameter vectors, or more); returns how many."""
+    batch kind: replicate, population, scattered); returns how many."""
     entries = load_cache(path).get(arch_name(), {})
     n = 0
     for bucket, kinds in entries.items():
         for kind, e in kinds.items():
-            g.set_class_schedule(1 << int(bucket), e["schedule"], many_params=KINDS[kind])
+            if kind not in fire.FireGPU.BATCH_KINDS:
+                continue
+            g.set_class_schedule(1 << int(bucket), e["schedule"], kind=kind)
             n += 1
     return n
 
 
 def workloads():
-    """Representative batches per size class: replicate batches at a
-    contained parameter vector and random parameter vectors from the
-    search box, on the synthetic landscapes of the benchmark configs."""
+    """The batches the library runs, per size class and kind: replicate
+    batches at the calibration vector (the scan workload's 256 candidate
+    ignitions x 32 replicates at 1024x1024), GA populations (64 vectors from
+    Table 1's Gaussian prior x 20 replicates) and scattered batches (one
+    simulation per vector drawn uniformly from the search box, as Monte
+    Carlo fits and the uneven batch have). Yields (kind, landscape, label,
+    parameter rows, descriptors-builder)."""
+    from . import scan
     rng = np.random.default_rng(7)
     beta_star = np.array([[-3.0, -0.5, 6.0, 1.0, 2.0]])
-    for W, H, seed in ((128, 128, 101), (256, 256, 102), (512, 512, 102), (1024, 768, 104),
-                       (1024, 1024, 103)):
-        yield (W, H, seed, beta_star, 1280)
-        yield (W, H, seed, rng.uniform(-30, 30, size=(500, 5)), 500)
+    for W, H, seed in ((128, 128, 101), (256, 256, 102), (512, 512, 102)):
+        ls = synth.make_landscape(W, H, seed)
+        c = synth.ignition_site(ls)
+        yield ("replicate", ls, f"{W}x{H}", beta_star,
+               lambda lid, c=c: fire.make_sims(1280, lid, -1, c))
+        pop = np.clip(rng.normal(0.0, 5.0, size=(64, 5)), -30, 30)
+        yield ("population", ls, f"{W}x{H}", pop,
+               lambda lid, c=c: fire.make_sims(1280, lid, -1, c,
+                                               param_index=np.repeat(np.arange(64), 20)))
+        box = rng.uniform(-30.0, 30.0, size=(2000, 5))
+        yield ("scattered", ls, f"{W}x{H}", box,
+               lambda lid, c=c: fire.make_sims(2000, lid, -1, c, param_index=np.arange(2000)))
+    ls = synth.make_landscape(1024, 768, 104)
+    c = synth.ignition_site(ls)
+    box = rng.uniform(-30.0, 30.0, size=(500, 5))
+    yield ("scattered", ls, "1024x768", box,
+           lambda lid, c=c: fire.make_sims(500, lid, -1, c, param_index=np.arange(500)))
+    ls = synth.scan_landscape()
+    c = synth.scan_ignition(ls)
+    cands = scan.candidate_grid(c, *synth.SCAN_SIZE, spacing=4, half=8)
+    yield ("replicate", ls, "1024x1024 scan", np.array([synth.SCAN_BETA]),
+           lambda lid, cands=cands: scan.scan_sims(lid, -1, cands, 32))
 
 
 def main():
     import argparse
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=CACHE, help="cache file to update")
-    ap.add_argument("--only", default=None, help="tune only this lattice, e.g. 512x512")
+    ap.add_argument("--only", default=None, help="tune only workloads whose label starts so")
     args = ap.parse_args()
     log = lambda m: print(f"[autotune] {m}", flush=True)  # noqa: E731
     g = fire.FireGPU(0)
     cache = load_cache(args.out)
     arch = arch_name()
     mine = cache.setdefault(arch, {})
-    for W, H, seed, betas, n in workloads():
-        if args.only and args.only != f"{W}x{H}":
+    for kind, ls, label, betas, make in workloads():
+        if args.only and not label.startswith(args.only):
             continue
-        ls = synth.make_landscape(W, H, seed)
+        H, W = np.asarray(ls["veg"]).shape
         lid = g.load_landscape(ls)
-        c = synth.ignition_site(ls)
-        sims = fire.make_sims(n, lid, -1, c, param_index=np.arange(n) % len(betas))
-        kind = "many" if len(betas) > 8 else "replicate"
-        log(f"{W}x{H}, {len(betas)} parameter vector(s), {n} simulations ({kind})")
+        sims = make(lid)
+        log(f"{label}, {kind}: {len(betas)} parameter vector(s), {len(sims)} simulations")
         best, rows = tune(g, lid, sims, betas, 0x5EED0001, log=log)
         b = str(cells_bucket(W * H))
-        mine.setdefault(b, {})[kind] = {"schedule": best, "ms": rows[0][0],
-                                        "lattice": [W, H], "sims": n,
+        builtin_ms = next(ms for ms, s in rows if s.get("builtin"))
+        if best.get("builtin"):
+            # the built-in plan won: no class entry (it adapts to the batch)
+            mine.setdefault(b, {}).pop(kind, None)
+            log(f"{label}, {kind}: built-in plan kept ({builtin_ms:.3f} ms)")
+            g.free_landscape(lid)
+            continue
+        mine.setdefault(b, {})[kind] = {"schedule": best, "ms": rows[0][0], "lattice": [W, H],
+                                        "workload": label, "sims": len(sims),
+                                        "builtin_ms": builtin_ms,
                                         "runner_up": rows[1][1] if len(rows) > 1 else None,
                                         "runner_up_ms": rows[1][0] if len(rows) > 1 else None}
         g.free_landscape(lid)

@@ -86,11 +86,11 @@ struct fire_ctx {
   // fixed schedule (autotuner) or built-in choice
   bool sched_fixed = false;
   fire_schedule sched{};
-  // per size-class schedules (autotuner): (log2 bucket of max_cells, more
-  // than kWindowMaxParams parameter vectors) -> schedule
+  // per size-class schedules (autotuner): (log2 bucket of max_cells, batch
+  // kind: see batch_kind) -> schedule
   struct ClassSched {
     int bucket;
-    int many;
+    int kind;
     fire_schedule s;
   };
   std::vector<ClassSched> class_sched;
@@ -407,6 +407,15 @@ bool shape_launch(fire_ctx *c, fire_schedule &s, int bitset_words, bool dur, boo
   return true;
 }
 
+// Kind of batch for the class schedules: 0 at most kWindowMaxParams
+// parameter vectors (replicate batches), 1 more vectors with at least 8
+// simulations each (GA populations), 2 other batches (one or a few
+// simulations per vector: Monte Carlo draws, random-parameter batches).
+int batch_kind(int32_t n_params, int32_t n_sims) {
+  if (n_params <= kWindowMaxParams) return 0;
+  return (int64_t)n_sims >= 8 * (int64_t)n_params ? 1 : 2;
+}
+
 // Launch plan for simulations on landscapes of at most max_h rows of
 // max_stride bitset words (bitset_words = the largest H * stride) and
 // max_cells cells.
@@ -419,10 +428,13 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
   if (c->sched_fixed) {
     s = c->sched;
   } else {
+    // class schedules are timed on one-step burns; runs with turn-off
+    // times keep the built-in choice
     const int b = cells_bucket(max_cells);
-    const int many = n_params > kWindowMaxParams ? 1 : 0;
-    for (const auto &e : c->class_sched)
-      if (e.bucket == b && e.many == many) s = e.s;
+    const int kind = batch_kind(n_params, n_sims);
+    if (!dur)
+      for (const auto &e : c->class_sched)
+        if (e.bucket == b && e.kind == kind) s = e.s;
   }
   if (!table_allowed) s.table_mode = 0;
   fire_schedule full = s;
@@ -1478,12 +1490,11 @@ fire_status fire_run_dense(fire_ctx *c, const double *betas, int32_t n_params,
   return FIRE_OK;
 }
 
-fire_status fire_set_class_schedule(fire_ctx *c, int64_t max_cells, int32_t many_params,
+fire_status fire_set_class_schedule(fire_ctx *c, int64_t max_cells, int32_t kind,
                                     const fire_schedule *s) {
   if (!c) return FIRE_E_INVALID;
   if (max_cells < 1) return fail(c, FIRE_E_INVALID, "max_cells < 1");
-  if (many_params != 0 && many_params != 1)
-    return fail(c, FIRE_E_INVALID, "many_params must be 0 or 1");
+  if (kind < 0 || kind > 2) return fail(c, FIRE_E_INVALID, "batch kind must be 0, 1 or 2");
   const int b = cells_bucket(max_cells);
   if (s) {
     if (!valid_threads(s->threads))
@@ -1494,12 +1505,12 @@ fire_status fire_set_class_schedule(fire_ctx *c, int64_t max_cells, int32_t many
       return fail(c, FIRE_E_INVALID, "schedule field out of range");
   }
   for (size_t i = 0; i < c->class_sched.size(); ++i)
-    if (c->class_sched[i].bucket == b && c->class_sched[i].many == many_params) {
+    if (c->class_sched[i].bucket == b && c->class_sched[i].kind == kind) {
       if (s) c->class_sched[i].s = *s;
       else c->class_sched.erase(c->class_sched.begin() + i);
       return FIRE_OK;
     }
-  if (s) c->class_sched.push_back({b, many_params, *s});
+  if (s) c->class_sched.push_back({b, kind, *s});
   return FIRE_OK;
 }
 

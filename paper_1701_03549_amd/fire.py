@@ -330,11 +330,14 @@ class FireGPU:
                      int(wave))
         self._check(self.lib.fire_set_schedule(self.ctx, ctypes.byref(s)))
 
-    def set_class_schedule(self, max_cells: int, sched: dict | None, many_params=None):
-        """Schedule for runs on landscapes of the size class of ``max_cells``:
-        for batches of more than 8 parameter vectors (many_params=True), of
-        at most 8 (False), or both (None)."""
-        kinds = (0, 1) if many_params is None else (1 if many_params else 0,)
+    BATCH_KINDS = {"replicate": 0, "population": 1, "scattered": 2}
+
+    def set_class_schedule(self, max_cells: int, sched: dict | None, kind=None):
+        """Schedule for runs on landscapes of the size class of ``max_cells``
+        and batches of `kind`: "replicate" (at most 8 parameter vectors),
+        "population" (more, with at least 8 simulations each), "scattered"
+        (the rest), or every kind (None)."""
+        kinds = (0, 1, 2) if kind is None else (self.BATCH_KINDS[kind],)
         for k in kinds:
             if sched is None:
                 self._check(self.lib.fire_set_class_schedule(self.ctx, int(max_cells), k, None))

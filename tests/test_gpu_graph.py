@@ -88,7 +88,8 @@ def test_grouped_classes_match_single_launch_and_oracle(g):
         compare_with_oracle(ls, [oracle.thresholds(ls, betas[i])], r[i:i + 1], None, sd, SEED)
     # a class schedule changes nothing either
     g.set_class_schedule(128 * 128, {"threads": 512, "queue_cap": 1024, "table_mode": 0,
-                                     "wg_per_cu": 2})
+                                     "wg_per_cu": 2}, kind="scattered")
+    assert g.get_schedule(128 * 128, 60, 60)["threads"] == 512
     res2, _ = g.run(betas, sims, SEED)
     g.sync()
     assert torch.equal(res, res2)
