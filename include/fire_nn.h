@@ -11,8 +11,9 @@
  * fixed reference map, and (b) a burn-probability map on a 128x128 grid.
  * Every candidate it keeps is re-scored by exact simulation (fire.h).
  *
- * Network (all GEMMs are bf16 x bf16 -> fp32 on MFMA; master weights and
- * Adam state fp32):
+ * Network (every matrix product and every decoder convolution takes bf16
+ * operands -- activations, weights, back-propagated errors -- and
+ * accumulates in fp32 on MFMA; master weights and Adam state fp32):
  *   input  x = (b0/30, ..., b4/30, 2x/W - 1, 2y/H - 1), zero-padded to 16
  *   h1 = relu(x  W1 + c1)    W1 16x256  (rows 7..15 unused, kept zero)
  *   h2 = relu(h1 W2 + c2)    W2 256x256
@@ -22,7 +23,8 @@
  *   d1 = relu(U(d0) * K1)    3x3 conv, 8 -> 8, after 2x nearest upsampling (32x32)
  *   d2 = relu(U(d1) * K2)    8 -> 8 (64x64)
  *   z  = U(d2) * K3          8 -> 1 (128x128 logits); map = sigmoid(z)
- * Convolutions use zero padding and a per-output-channel bias.
+ * Convolutions use zero padding and a per-output-channel bias; their
+ * bias gradients are sums of the bf16 errors.
  * Loss per batch: mean((t - y_t)^2) + w_map * mean(BCE-with-logits(z, y_map)).
  *
  * Parameters are flattened (fp32) in this order: W1 [16][256], c1 [256],

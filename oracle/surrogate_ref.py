@@ -6,11 +6,12 @@ is the one fire_nn.h documents: a 7 -> 256 -> 256 -> 256 -> 1 MLP predicting
 log(1 + delta) of Eq. 2, and a dense + three (2x nearest upsample, 3x3 conv)
 decoder producing 128x128 burn-map logits.
 
-With ``bf16=True`` the inputs of every matrix product (activations and
-weights) are first rounded to bfloat16 (round-half-even), as the GPU's MFMA
-GEMMs consume them; everything else is binary64. With ``bf16=False`` the
-network is evaluated in plain binary64, which the finite-difference test uses
-to pin the analytic backward below.
+With ``bf16=True`` the inputs of every matrix product and every decoder
+convolution (activations, weights and back-propagated errors) are first
+rounded to bfloat16 (round-half-even), as the GPU's MFMA kernels consume
+them; everything else is binary64. With ``bf16=False`` the network is
+evaluated in plain binary64, which the finite-difference test uses to pin
+the analytic backward below.
 """
 from __future__ import annotations
 
@@ -111,11 +112,11 @@ def forward(params, x_raw, W, H_, bf16=True):
     B = c["d0"].shape[0]
     d0 = c["d0"].reshape(B, DEC_C, DEC_S, DEC_S)
     c["u0"] = upsample2(d0)
-    c["d1"] = np.maximum(conv3x3(c["u0"], P["K1"], P["k1"]), 0.0)
+    c["d1"] = np.maximum(conv3x3(r(c["u0"]), r(P["K1"]), P["k1"]), 0.0)
     c["u1"] = upsample2(c["d1"])
-    c["d2"] = np.maximum(conv3x3(c["u1"], P["K2"], P["k2"]), 0.0)
+    c["d2"] = np.maximum(conv3x3(r(c["u1"]), r(P["K2"]), P["k2"]), 0.0)
     c["u2"] = upsample2(c["d2"])
-    c["z"] = conv3x3(c["u2"], P["K3"], P["k3"])[:, 0]
+    c["z"] = conv3x3(r(c["u2"]), r(P["K3"]), P["k3"])[:, 0]
     return c
 
 
@@ -144,11 +145,13 @@ def loss_and_grads(params, x_raw, y_t, y_map, W, H_, w_map, bf16=True):
         n = z.size
         loss_map = float(np.mean(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))))
         dz = w_map * (1.0 / (1.0 + np.exp(-z)) - y) / n
-        du2, g["K3"], g["k3"] = conv3x3_backward(c["u2"], P["K3"], dz[:, None])
+        # each convolution's back-propagated error enters its two products
+        # (data and kernel gradients) and its bias gradient as bf16
+        du2, g["K3"], g["k3"] = conv3x3_backward(r(c["u2"]), r(P["K3"]), r(dz[:, None]))
         dd2 = downsample2_sum(du2) * (c["d2"] > 0)
-        du1, g["K2"], g["k2"] = conv3x3_backward(c["u1"], P["K2"], dd2)
+        du1, g["K2"], g["k2"] = conv3x3_backward(r(c["u1"]), r(P["K2"]), r(dd2))
         dd1 = downsample2_sum(du1) * (c["d1"] > 0)
-        du0, g["K1"], g["k1"] = conv3x3_backward(c["u0"], P["K1"], dd1)
+        du0, g["K1"], g["k1"] = conv3x3_backward(r(c["u0"]), r(P["K1"]), r(dd1))
         dd0 = (downsample2_sum(du0).reshape(B, DEC) * (c["d0"] > 0))
         dd0r = r(dd0)
         g["Wd"] = r(c["h3"]).T @ dd0r

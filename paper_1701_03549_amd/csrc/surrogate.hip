@@ -337,110 +337,238 @@ __global__ void sigmoid_kernel(const float *z, float *p, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Decoder layer: 2x nearest upsampling of in [B][Ci][S][S] followed by a 3x3
-// convolution with zero padding: out [B][Co][2S][2S].
+// Decoder convolutions on MFMA (v_mfma_f32_16x16x32_bf16: A 16x32 with lane
+// l holding row l%16 and k 8*(l/16)..+8; B 32x16 with lane l holding column
+// l%16 and the same k; D 16x16 with lane l holding column l%16 and rows
+// 4*(l/16)..+4). A layer is out = conv3x3(up2(in)) with zero padding, in
+// [Ci=8][S][S] and out [Co][2S][2S]; the products take bf16 operands
+// (activations, kernels, back-propagated errors) and accumulate in fp32.
+// One workgroup of 4 waves per sample stages that sample's planes in LDS.
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
+constexpr int kConvCi = 8, kConvTaps = 9, kConvK = kConvCi * kConvTaps;  // 72
+constexpr int kWgradCols = 80;  // 72 kernel taps, the bias column, padding
+constexpr int kWgradRows = 16;  // output channels, padded
+constexpr int kWgradParts = 512;
 
-__device__ __forceinline__ float up_at(const float *in, int b, int ci, int Ci, int S, int Y,
-                                       int X) {
-  if (Y < 0 || X < 0 || Y >= 2 * S || X >= 2 * S) return 0.0f;
-  return in[(((int64_t)b * Ci + ci) * S + (Y >> 1)) * S + (X >> 1)];
+__device__ __forceinline__ bf16x8_t as_bf16x8(u16x8_t v) { return __builtin_bit_cast(bf16x8_t, v); }
+
+// Stage n bf16 values (n a multiple of 8, 16-byte aligned) into LDS.
+__device__ __forceinline__ void stage_bf16(uint16_t *dst, const uint16_t *src, int n) {
+  for (int i = threadIdx.x; i < n / 8; i += blockDim.x)
+    reinterpret_cast<uint4 *>(dst)[i] = reinterpret_cast<const uint4 *>(src)[i];
 }
 
-__global__ void upconv_fwd_kernel(const float *in, const float *Kw, const float *kb, int B,
-                                  int Ci, int Co, int S, int relu, float *out) {
+// Forward (UP) or data gradient (!UP) of one layer, 16-pixel tiles of the
+// 2S x 2S grid:
+//   UP:  out[co][y][x] = bias[co] + sum_k A[p][k] B[k][co],
+//        A[p][k] = in[ci][(y+dy-1)/2][(x+dx-1)/2], B[k][co] = K[co][ci][dy][dx],
+//        k = ci*9 + dy*3 + dx; written fp32 (and bf16) after an optional ReLU;
+//  !UP:  dU[ci][u][v] = sum_k A[p][k] B[k][ci],
+//        A[p][k] = g[co][u-dy+1][v-dx+1], B[k][ci] = K[co][ci][dy][dx],
+//        k = co*9 + dy*3 + dx; the 2x2 blocks of dU are summed into
+//        din[ci][u/2][v/2], which is zeroed where act <= 0.
+// src: UP the layer input [8][S][S], !UP the error g [Co][2S][2S] (bf16).
+template <bool UP>
+__global__ __launch_bounds__(256) void upconv_mfma_kernel(const uint16_t *src, const uint16_t *Kb,
+                                                          const float *bias, int S, int Co,
+                                                          int relu, const float *act, float *out,
+                                                          uint16_t *out_b) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t plane[];
+  const int b = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int O = 2 * S;
-  const int64_t n = (int64_t)B * Co * O * O;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int x = (int)(i % O), y = (int)((i / O) % O);
-    const int co = (int)((i / ((int64_t)O * O)) % Co), b = (int)(i / ((int64_t)O * O * Co));
-    float acc = kb[co];
-    for (int ci = 0; ci < Ci; ++ci)
+  const int srcC = UP ? kConvCi : Co, srcR = UP ? S : O;
+  stage_bf16(plane, src + (int64_t)b * srcC * srcR * srcR, srcC * srcR * srcR);
+  const int col = lane & 15, kq = lane >> 4;
+  const int nk = UP ? kConvK : Co * kConvTaps;  // contraction length
+  const int ncols = UP ? Co : kConvCi;          // columns of the result
+  // B fragments of the (up to) three k-steps, and each A slot's tap
+  bf16x8_t bw[3];
+  int slot_c[3][8], slot_dy[3][8], slot_dx[3][8];
 #pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
+  for (int s = 0; s < 3; ++s) {
+    u16x8_t v;
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx)
-          acc += Kw[((co * Ci + ci) * 3 + dy) * 3 + dx] * up_at(in, b, ci, Ci, S, y + dy - 1, x + dx - 1);
-    out[i] = relu ? fmaxf(acc, 0.0f) : acc;
-  }
-}
-
-// d(in) for in [B][Ci][S][S], masked by (act > 0) when act is given
-__global__ void upconv_bwd_data_kernel(const float *dout, const float *Kw, const float *act,
-                                       int B, int Ci, int Co, int S, float *din) {
-  const int O = 2 * S;
-  const int64_t n = (int64_t)B * Ci * S * S;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int xi = (int)(i % S), yi = (int)((i / S) % S);
-    const int ci = (int)((i / ((int64_t)S * S)) % Ci), b = (int)(i / ((int64_t)S * S * Ci));
-    float acc = 0.0f;
-    for (int co = 0; co < Co; ++co) {
-      const float *dptr = dout + ((int64_t)b * Co + co) * O * O;
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          const float w = Kw[((co * Ci + ci) * 3 + dy) * 3 + dx];
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            const int y = 2 * yi + a - dy + 1;
-            if (y < 0 || y >= O) continue;
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              const int x = 2 * xi + c - dx + 1;
-              if (x < 0 || x >= O) continue;
-              acc += w * dptr[(int64_t)y * O + x];
-            }
-          }
-        }
+    for (int i = 0; i < 8; ++i) {
+      const int k = 32 * s + 8 * kq + i;
+      const int c = k / kConvTaps, t = k % kConvTaps;
+      // UP: column col is co; k runs over (ci, tap).  !UP: column col is
+      // ci; k runs over (co, tap)
+      const bool ok = k < nk && col < ncols;
+      const int widx = UP ? (col * kConvCi + c) * kConvTaps + t : (c * kConvCi + col) * kConvTaps + t;
+      v[i] = ok ? Kb[widx] : (uint16_t)0;
+      slot_c[s][i] = k < nk ? c : -1;
+      slot_dy[s][i] = t / 3;
+      slot_dx[s][i] = t % 3;
     }
-    din[i] = (act == nullptr || act[i] > 0.0f) ? acc : 0.0f;
+    bw[s] = as_bf16x8(v);
+  }
+  const int steps = (nk + 31) / 32;
+  const float bcol = (UP && col < ncols && bias) ? bias[col] : 0.0f;
+  __syncthreads();
+  // tile: 16 consecutive columns x0.. of one row; for !UP a wave takes the
+  // two rows of a 2x2 block together
+  const int per_row = O / 16;
+  const int rows_per_item = UP ? 1 : 2;
+  const int items = (O / rows_per_item) * per_row;
+  for (int it = wave; it < items; it += 4) {
+    const int y0 = (it / per_row) * rows_per_item, x0 = (it % per_row) * 16;
+    const int x = x0 + (lane & 15);
+    f32x4_t acc[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) acc[r] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (r >= rows_per_item) break;
+      const int y = y0 + r;
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        if (s >= steps) break;
+        u16x8_t a;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int c = slot_c[s][i];
+          int yy, xx;
+          if (UP) {
+            yy = y + slot_dy[s][i] - 1;
+            xx = x + slot_dx[s][i] - 1;
+          } else {
+            yy = y - slot_dy[s][i] + 1;
+            xx = x - slot_dx[s][i] + 1;
+          }
+          const bool in = c >= 0 && (unsigned)yy < (unsigned)O && (unsigned)xx < (unsigned)O;
+          const int sy = UP ? (yy >> 1) : yy, sx = UP ? (xx >> 1) : xx;
+          a[i] = in ? plane[(c * srcR + sy) * srcR + sx] : (uint16_t)0;
+        }
+        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), bw[s], acc[r], 0, 0, 0);
+      }
+    }
+    if (col >= ncols) continue;
+    if (UP) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float val = acc[0][v] + bcol;
+        if (relu) val = fmaxf(val, 0.0f);
+        const int64_t o = (((int64_t)b * Co + col) * O + y0) * O + x0 + 4 * kq + v;
+        out[o] = val;
+        if (out_b) out_b[o] = f2bf(val);
+      }
+    } else {
+      // lane holds dU[col][y0 + r][x0 + 4kq + v]: pairs of columns in the
+      // lane, the two rows in acc[0] and acc[1]
+      const int sy = y0 >> 1;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float sum = (acc[0][2 * h] + acc[0][2 * h + 1]) + (acc[1][2 * h] + acc[1][2 * h + 1]);
+        const int sx = (x0 >> 1) + 2 * kq + h;
+        const int64_t o = (((int64_t)b * kConvCi + col) * S + sy) * S + sx;
+        const float val = act[o] > 0.0f ? sum : 0.0f;
+        out[o] = val;
+        if (out_b) out_b[o] = f2bf(val);
+      }
+    }
   }
 }
 
-// partial weight and bias gradients: block (pair, part) sums over its slice of
-// the (b, y, x) positions; partial[(pair * parts + part) * 10 + tap]
-__global__ __launch_bounds__(256) void upconv_bwd_weight_kernel(const float *dout, const float *in,
-                                                                int B, int Ci, int Co, int S,
-                                                                int parts, float *partial) {
-  __shared__ float red[256];
-  const int pair = blockIdx.x / parts, part = blockIdx.x % parts;
-  const int co = pair / Ci, ci = pair % Ci;
+// Kernel and bias gradients of one layer: for every sample handled by this
+// workgroup (b = blockIdx.x, + gridDim.x, ...) the contraction over its
+// (2S)^2 pixels, 32 per MFMA step:
+//   P[co][k] += sum_p A[co][p] B[p][k],  A[co][p] = g[co][p] (bf16 error),
+//   B[p][k] = in[ci][(y+dy-1)/2][(x+dx-1)/2] for k = ci*9 + dy*3 + dx < 72,
+//   1 for k = 72 (the bias gradient), 0 beyond;
+// the four waves' sums are added in wave order and the workgroup writes its
+// partial [16][80] to part; wgrad_finish_kernel adds the partials.
+__global__ __launch_bounds__(256) void upconv_wgrad_mfma_kernel(const uint16_t *g_b,
+                                                                const uint16_t *in_b, int B, int S,
+                                                                int Co, float *part) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds16[];
+  __shared__ float red[4][kWgradRows * kWgradCols];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int O = 2 * S;
-  const int64_t n = (int64_t)B * O * O;
-  float acc[10];
+  uint16_t *gpl = lds16;                        // [Co][O][O]
+  uint16_t *ipl = lds16 + (Co * O * O + 7) / 8 * 8;  // [8][S][S]
+  const int row = lane & 15, kq = lane >> 4;
+  // each lane's B column per n-tile: k = 16 n + row
+  int bc[5], bdy[5], bdx[5];
 #pragma unroll
-  for (int t = 0; t < 10; ++t) acc[t] = 0.0f;
-  for (int64_t i = (int64_t)part * 256 + threadIdx.x; i < n; i += (int64_t)parts * 256) {
-    const int x = (int)(i % O), y = (int)((i / O) % O), b = (int)(i / ((int64_t)O * O));
-    const float g = dout[(((int64_t)b * Co + co) * O + y) * O + x];
-    if (g == 0.0f) continue;
-#pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) acc[dy * 3 + dx] += g * up_at(in, b, ci, Ci, S, y + dy - 1, x + dx - 1);
-    acc[9] += g;
+  for (int n = 0; n < 5; ++n) {
+    const int k = 16 * n + row;
+    bc[n] = k < kConvK ? k / kConvTaps : (k == kConvK ? -2 : -1);
+    bdy[n] = (k % kConvTaps) / 3;
+    bdx[n] = (k % kConvTaps) % 3;
   }
+  f32x4_t acc[5];
 #pragma unroll
-  for (int t = 0; t < 10; ++t) {
-    const float s = block_reduce(acc[t], red);
-    if (threadIdx.x == 0) partial[((int64_t)pair * parts + part) * 10 + t] = s;
+  for (int n = 0; n < 5; ++n) acc[n] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  const int chunks = O * O / 32;
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    __syncthreads();
+    stage_bf16(gpl, g_b + (int64_t)b * Co * O * O, Co * O * O);
+    stage_bf16(ipl, in_b + (int64_t)b * kConvCi * S * S, kConvCi * S * S);
+    __syncthreads();
+    for (int ch = wave; ch < chunks; ch += 4) {
+      const int p0 = ch * 32 + 8 * kq;  // this lane's 8 pixels (one row)
+      const int y = p0 / O, x0 = p0 % O;
+      u16x8_t a;
+      if (row < Co) {
+        a = *reinterpret_cast<const u16x8_t *>(&gpl[(row * O + y) * O + x0]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = 0;
+      }
+      const bf16x8_t av = as_bf16x8(a);
+#pragma unroll
+      for (int n = 0; n < 5; ++n) {
+        u16x8_t bv;
+        const int c = bc[n];
+        const int yy = y + bdy[n] - 1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int xx = x0 + i + bdx[n] - 1;
+          uint16_t v = 0;
+          if (c >= 0) {
+            if ((unsigned)yy < (unsigned)O && (unsigned)xx < (unsigned)O)
+              v = ipl[(c * S + (yy >> 1)) * S + (xx >> 1)];
+          } else if (c == -2) {
+            v = 0x3F80u;  // 1.0
+          }
+          bv[i] = v;
+        }
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, as_bf16x8(bv), acc[n], 0, 0, 0);
+      }
+    }
   }
+  // D layout: lane holds column (16 n + row) and rows (co) 4 kq + v
+#pragma unroll
+  for (int n = 0; n < 5; ++n)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][(4 * kq + v) * kWgradCols + 16 * n + row] = acc[n][v];
+  __syncthreads();
+  for (int i = threadIdx.x; i < kWgradRows * kWgradCols; i += blockDim.x)
+    part[(int64_t)blockIdx.x * kWgradRows * kWgradCols + i] =
+        ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
 
-__global__ void upconv_weight_finish_kernel(const float *partial, int Ci, int Co, int parts,
-                                            float *dK, float *dkb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Co * Ci * 10) return;
-  const int pair = i / 10, t = i % 10;
+// dK[co][ci][dy][dx] and dkb[co] from the partials of `parts` workgroups:
+// one workgroup per output; thread t adds partials t, t + 256, ... in
+// order, then a pairwise tree over the 256 threads.
+__global__ __launch_bounds__(256) void wgrad_finish_kernel(const float *part, int parts, int Co,
+                                                           float *dK, float *dkb) {
+  __shared__ float red[256];
+  const int o = blockIdx.x;  // co * 73 + k
+  const int co = o / (kConvK + 1), k = o % (kConvK + 1);
   float s = 0.0f;
-  for (int p = 0; p < parts; ++p) s += partial[((int64_t)pair * parts + p) * 10 + t];
-  const int co = pair / Ci, ci = pair % Ci;
-  if (t < 9) dK[(co * Ci + ci) * 9 + t] = s;
-  else if (ci == 0) {
-    // the bias gradient is the same sum for every ci; take ci == 0
-    dkb[co] = s;
+  for (int p = threadIdx.x; p < parts; p += 256)
+    s += part[(int64_t)p * kWgradRows * kWgradCols + co * kWgradCols + k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (k < kConvK) dK[co * kConvK + k] = red[0];
+    else dkb[co] = red[0];
   }
 }
 
@@ -586,7 +714,10 @@ struct fire_nn {
         *d2 = nullptr, *z = nullptr;
   float *gt = nullptr, *gd0 = nullptr, *gd1 = nullptr, *gd2 = nullptr, *gz = nullptr, *gh = nullptr;
   uint16_t *ghb = nullptr;
+  // bf16 copies the decoder's MFMA convolutions read
+  uint16_t *d1b = nullptr, *d2b = nullptr, *gzb = nullptr, *gd1b = nullptr, *gd2b = nullptr;
   float *partial = nullptr, *loss = nullptr;
+  float *wpart = nullptr;  // kernel-gradient partials [kWgradParts][16][80]
   std::vector<void *> allocs;
 };
 
@@ -615,7 +746,8 @@ hipError_t nn_alloc(fire_nn *nn, T **p, int64_t count) {
   return e;
 }
 
-constexpr int kWeightParts = 64;
+// dynamic LDS of a decoder convolution staging c planes of r x r bf16
+size_t conv_lds(int c, int r) { return sizeof(uint16_t) * (size_t)c * r * r; }
 
 hipError_t refresh_bf16(fire_nn *nn, hipStream_t s) {
   hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(nn->L.total)), dim3(256), 0, s, nn->w, nn->wb,
@@ -644,21 +776,27 @@ hipError_t forward(fire_nn *nn, const float *x, int B, hipStream_t s, bool want_
   if (!want_map) return hipSuccess;
   if ((e = gemm(B, kDec, kH, nn->h3b, kH, 1, wb + L.Wd.off, kDec, 1, nn->d0, kDec, w + L.cd.off,
                 1, 0, nn->d0b, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(upconv_fwd_kernel, dim3(blocks_for((int64_t)B * kD0C * 32 * 32)), dim3(256),
-                     0, s, nn->d0, w + L.K1.off, w + L.k1.off, B, kD0C, kD0C, 16, 1, nn->d1);
-  hipLaunchKernelGGL(upconv_fwd_kernel, dim3(blocks_for((int64_t)B * kD0C * 64 * 64)), dim3(256),
-                     0, s, nn->d1, w + L.K2.off, w + L.k2.off, B, kD0C, kD0C, 32, 1, nn->d2);
-  hipLaunchKernelGGL(upconv_fwd_kernel, dim3(blocks_for((int64_t)B * kP)), dim3(256), 0, s, nn->d2,
-                     w + L.K3.off, w + L.k3.off, B, kD0C, 1, 64, 0, nn->z);
+  // decoder: d0b (bf16 of d0, from the dense layer) -> d1 -> d2 -> z
+  hipLaunchKernelGGL((upconv_mfma_kernel<true>), dim3(B), dim3(256), conv_lds(kD0C, 16), s,
+                     nn->d0b, wb + L.K1.off, w + L.k1.off, 16, kD0C, 1, nullptr, nn->d1, nn->d1b);
+  hipLaunchKernelGGL((upconv_mfma_kernel<true>), dim3(B), dim3(256), conv_lds(kD0C, 32), s,
+                     nn->d1b, wb + L.K2.off, w + L.k2.off, 32, kD0C, 1, nullptr, nn->d2, nn->d2b);
+  hipLaunchKernelGGL((upconv_mfma_kernel<true>), dim3(B), dim3(256), conv_lds(kD0C, 64), s,
+                     nn->d2b, wb + L.K3.off, w + L.k3.off, 64, 1, 0, nullptr, nn->z, nullptr);
   return hipGetLastError();
 }
 
-hipError_t conv_weight_grad(fire_nn *nn, const float *dout, const float *in, int B, int Ci, int Co,
+// Kernel and bias gradients of one decoder layer: error g_b [B][Co][2S][2S]
+// and layer input in_b [B][8][S][S] (both bf16).
+hipError_t conv_weight_grad(fire_nn *nn, const uint16_t *g_b, const uint16_t *in_b, int B, int Co,
                             int S, float *dK, float *dkb, hipStream_t s) {
-  hipLaunchKernelGGL(upconv_bwd_weight_kernel, dim3(Co * Ci * kWeightParts), dim3(256), 0, s, dout,
-                     in, B, Ci, Co, S, kWeightParts, nn->partial);
-  hipLaunchKernelGGL(upconv_weight_finish_kernel, dim3(blocks_for((int64_t)Co * Ci * 10)),
-                     dim3(256), 0, s, nn->partial, Ci, Co, kWeightParts, dK, dkb);
+  const int parts = B < kWgradParts ? B : kWgradParts;
+  const int O = 2 * S;
+  const size_t lds = sizeof(uint16_t) * ((size_t)(Co * O * O + 7) / 8 * 8 + (size_t)kD0C * S * S);
+  hipLaunchKernelGGL(upconv_wgrad_mfma_kernel, dim3(parts), dim3(256), lds, s, g_b, in_b, B, S, Co,
+                     nn->wpart);
+  hipLaunchKernelGGL(wgrad_finish_kernel, dim3(Co * (kConvK + 1)), dim3(256), 0, s, nn->wpart,
+                     parts, Co, dK, dkb);
   return hipGetLastError();
 }
 
@@ -679,19 +817,22 @@ hipError_t backward(fire_nn *nn, const float *y_t, const uint8_t *y_map, int B, 
                        nn->cfg.w_map, nn->gz, nn->partial);
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, nn->partial, nb,
                        1.0f / (float)nz, nn->loss + 1);
-    // decoder backward
-    if ((e = conv_weight_grad(nn, nn->gz, nn->d2, B, kD0C, 1, 64, g + L.K3.off, g + L.k3.off, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(upconv_bwd_data_kernel, dim3(blocks_for((int64_t)B * kD0C * 64 * 64)),
-                       dim3(256), 0, s, nn->gz, w + L.K3.off, nn->d2, B, kD0C, 1, 64, nn->gd2);
-    if ((e = conv_weight_grad(nn, nn->gd2, nn->d1, B, kD0C, kD0C, 32, g + L.K2.off, g + L.k2.off, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(upconv_bwd_data_kernel, dim3(blocks_for((int64_t)B * kD0C * 32 * 32)),
-                       dim3(256), 0, s, nn->gd2, w + L.K2.off, nn->d1, B, kD0C, kD0C, 32, nn->gd1);
-    if ((e = conv_weight_grad(nn, nn->gd1, nn->d0, B, kD0C, kD0C, 16, g + L.K1.off, g + L.k1.off, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(upconv_bwd_data_kernel, dim3(blocks_for((int64_t)B * kDec)), dim3(256), 0,
-                       s, nn->gd1, w + L.K1.off, nn->d0, B, kD0C, kD0C, 16, nn->gd0);
+    // decoder backward: each layer's error enters its two MFMA products as
+    // bf16; the data gradient comes back summed over the 2x2 upsampling
+    // blocks and masked by the layer input's ReLU
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(nz)), dim3(256), 0, s, nn->gz, nn->gzb, nz);
+    if ((e = conv_weight_grad(nn, nn->gzb, nn->d2b, B, 1, 64, g + L.K3.off, g + L.k3.off, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL((upconv_mfma_kernel<false>), dim3(B), dim3(256), conv_lds(1, 128), s,
+                       nn->gzb, wb + L.K3.off, nullptr, 64, 1, 0, nn->d2, nn->gd2, nn->gd2b);
+    if ((e = conv_weight_grad(nn, nn->gd2b, nn->d1b, B, kD0C, 32, g + L.K2.off, g + L.k2.off, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL((upconv_mfma_kernel<false>), dim3(B), dim3(256), conv_lds(kD0C, 64), s,
+                       nn->gd2b, wb + L.K2.off, nullptr, 32, kD0C, 0, nn->d1, nn->gd1, nn->gd1b);
+    if ((e = conv_weight_grad(nn, nn->gd1b, nn->d0b, B, kD0C, 16, g + L.K1.off, g + L.k1.off, s)) != hipSuccess) return e;
+    // the last data gradient's bf16 copy replaces d0b, which the dense
+    // layer's gradient products read next
+    hipLaunchKernelGGL((upconv_mfma_kernel<false>), dim3(B), dim3(256), conv_lds(kD0C, 32), s,
+                       nn->gd1b, wb + L.K1.off, nullptr, 16, kD0C, 0, nn->d0, nn->gd0, nn->d0b);
     // dense decoder layer: gd0 already carries the ReLU mask of d0
-    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for((int64_t)B * kDec)), dim3(256), 0, s,
-                       nn->gd0, nn->d0b, (int64_t)B * kDec);
     if ((e = gemm(kH, kDec, B, nn->h3b, 1, kH, nn->d0b, kDec, 1, g + L.Wd.off, kDec, nullptr, 0,
                   0, nullptr, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(colsum_kernel, dim3(colsum_blocks(kDec)), dim3(256), 0, s, nn->gd0, B, kDec,
@@ -778,7 +919,23 @@ fire_status fire_nn_create(int device, const fire_nn_cfg *cfg, uint64_t seed, fi
   if (e == hipSuccess) e = nn_alloc(nn, &nn->gd2, Bm * kD0C * 64 * 64);
   if (e == hipSuccess) e = nn_alloc(nn, &nn->gz, Bm * kP);
   if (e == hipSuccess) e = nn_alloc(nn, &nn->gh, Bm * kH);
-  if (e == hipSuccess) e = nn_alloc(nn, &nn->partial, (int64_t)kD0C * kD0C * kWeightParts * 10 + 1024);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->partial, (int64_t)1024);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->wpart, (int64_t)kWgradParts * kWgradRows * kWgradCols);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->d1b, Bm * kD0C * 32 * 32);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->d2b, Bm * kD0C * 64 * 64);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->gzb, Bm * kP);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->gd1b, Bm * kD0C * 32 * 32);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->gd2b, Bm * kD0C * 64 * 64);
+  // the decoder kernels stage up to 96 KiB of planes in LDS
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&upconv_wgrad_mfma_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&upconv_mfma_kernel<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&upconv_mfma_kernel<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
   if (e == hipSuccess) e = nn_alloc(nn, &nn->loss, 2);
   if (e != hipSuccess) return fail_out(e);
   // initial parameters

@@ -17,7 +17,9 @@ GPU and reference is bounded per element by
   sides round identically unless the value sits within its fp32 error of a
   bf16 rounding midpoint, where they differ by one bf16 ulp (<= 2u |v|); a
   product of two such operands differs by at most (2u + 2u + 4u^2) |a||b|.
-  rho = 0 for fp32 operands (bias and convolution gradients).
+  rho = 2 u when one operand is such a bf16 value and the other is exact
+  (the bias gradients of the convolutions: sums of bf16 errors); rho = 0
+  for fp32 operands (the dense layers' bias gradients).
 * 8 sqrt(K) 2^-24: fp32 accumulation of K terms, the probabilistic bound of
   Higham and Mary (SIAM J. Sci. Comput. 41, 2019) at lambda = 8: it holds
   with probability >= 1 - 2K exp(-32), over 1 - 1e-8 for every sum here.
@@ -32,10 +34,9 @@ GPU and reference is bounded per element by
 A ReLU mask can differ between the two sides where the pre-activation lies
 within its own error of zero: the pre-activation v counts as near zero when
 |v| <= 8 sqrt(K) 2^-24 M_v + f, its own contraction's accumulation bound plus
-an allowance f for upstream rounding flips: for a layer with bf16 inputs
-each flip moves v by one ulp of one of its K terms, and f = 4u max_k|a_k w_k|
-allows two; for the convolutions (fp32 inputs that inherit such flips from
-the dense layer) f = (u/16) M_v. Where it is, the back-propagated value that the
+an allowance f for upstream rounding flips: every layer, dense or
+convolution, has bf16 inputs, each flip moves v by one ulp of one of its K
+terms, and f = 4u max_k|a_k w_k| allows two. Where it is, the back-propagated value that the
 mask gates may be |g| on one side and 0 on the other. Those possible jumps
 are carried downstream in absolute value, D (|.| of each later linear map
 applied to them, seeded only at the near-zero entries, so D stays sparse),
@@ -76,7 +77,19 @@ def _convT_abs(g, K):
     return S.conv3x3_backward(a, np.abs(K), np.abs(g))[0]
 
 
-C_MASK = 1.0 / 16.0
+def _max_term(u, K):
+    """For every output of conv3x3(u, K): its largest term |u| |K|."""
+    B, Ci, S_, _ = u.shape
+    p = np.zeros((B, Ci, S_ + 2, S_ + 2))
+    p[:, :, 1:-1, 1:-1] = np.abs(u)
+    out = np.zeros((B, K.shape[0], S_, S_))
+    for dy in range(3):
+        for dx in range(3):
+            for ci in range(Ci):
+                t = p[:, ci, dy:dy + S_, dx:dx + S_][:, None] * \
+                    np.abs(K[:, ci, dy, dx])[None, :, None, None]
+                np.maximum(out, t, out=out)
+    return out
 
 
 def _near_zero(pre, Mpre, k, flip):
@@ -107,9 +120,10 @@ def gradient_tolerances(params, x_raw, y_t, y_map, W, H, w_map):
         near[a] = _near_zero(pre, Mpre, inb.shape[1] + 2, 4 * U * maxterm)
         open_[a] = (pre > 0) | near[a]
     for a, u, Kn, kn in (("d1", c["u0"], "K1", "k1"), ("d2", c["u1"], "K2", "k2")):
-        pre = S.conv3x3(u, P[Kn], P[kn])
-        Mpre = S.conv3x3(np.abs(u), np.abs(P[Kn]), np.abs(P[kn]))
-        near[a] = _near_zero(pre, Mpre, 9 * u.shape[1] + 1, C_MASK * U * Mpre)
+        ub, Kb = r(u), r(P[Kn])
+        pre = S.conv3x3(ub, Kb, P[kn])
+        Mpre = S.conv3x3(np.abs(ub), np.abs(Kb), np.abs(P[kn]))
+        near[a] = _near_zero(pre, Mpre, 9 * u.shape[1] + 1, 4 * U * _max_term(ub, Kb))
         open_[a] = (pre > 0) | near[a]
     M = {name: np.zeros(shape) for name, shape in S.layout()}
     extra = {name: np.zeros(shape) for name, shape in S.layout()}
@@ -123,23 +137,31 @@ def gradient_tolerances(params, x_raw, y_t, y_map, W, H, w_map):
         z = c["z"]
         y = np.asarray(y_map, dtype=np.float64).reshape(z.shape)
         dz = w_map * (1.0 / (1.0 + np.exp(-z)) - y) / z.size
-        du2 = S.conv3x3_backward(c["u2"], P["K3"], dz[:, None])[0]
-        M["K3"], M["k3"] = _dK_abs(c["u2"], dz[:, None]), np.abs(dz).sum(axis=(0, 1, 2))[None]
+        # the convolutions take their inputs, kernels and errors as bf16
+        dzb = r(dz)[:, None]
+        du2 = S.conv3x3_backward(r(c["u2"]), r(P["K3"]), dzb)[0]
+        M["K3"], M["k3"] = _dK_abs(r(c["u2"]), dzb), np.abs(dzb).sum(axis=(0, 2, 3))
         g2 = S.downsample2_sum(du2)
         dd2 = g2 * (c["d2"] > 0)
         D2 = np.abs(g2) * near["d2"]
-        du1 = S.conv3x3_backward(c["u1"], P["K2"], dd2)[0]
-        M["K2"], M["k2"] = _dK_abs(c["u1"], np.abs(dd2) + D2), (np.abs(dd2) + D2).sum(axis=(0, 2, 3))
+        dd2b = r(dd2)
+        du1 = S.conv3x3_backward(r(c["u1"]), r(P["K2"]), dd2b)[0]
+        M["K2"] = _dK_abs(r(c["u1"]), np.abs(dd2b) + D2)
+        M["k2"] = (np.abs(dd2b) + D2).sum(axis=(0, 2, 3))
         g1 = S.downsample2_sum(du1)
         dd1 = g1 * (c["d1"] > 0)
-        D1 = (S.downsample2_sum(_convT_abs(D2, P["K2"])) * open_["d1"]) + np.abs(g1) * near["d1"]
-        du0 = S.conv3x3_backward(c["u0"], P["K1"], dd1)[0]
-        M["K1"], M["k1"] = _dK_abs(c["u0"], np.abs(dd1) + D1), (np.abs(dd1) + D1).sum(axis=(0, 2, 3))
+        D1 = (S.downsample2_sum(_convT_abs(D2, r(P["K2"]))) * open_["d1"]
+              + np.abs(g1) * near["d1"])
+        dd1b = r(dd1)
+        du0 = S.conv3x3_backward(r(c["u0"]), r(P["K1"]), dd1b)[0]
+        M["K1"] = _dK_abs(r(c["u0"]), np.abs(dd1b) + D1)
+        M["k1"] = (np.abs(dd1b) + D1).sum(axis=(0, 2, 3))
         for layer, side in ((1, 32), (2, 64), (3, 128)):
             K[f"K{layer}"] = K[f"k{layer}"] = B * side * side
+            rho[f"K{layer}"], rho[f"k{layer}"] = 4 * U, 2 * U
         g0 = S.downsample2_sum(du0).reshape(B, -1)
         dd0 = g0 * (c["d0"] > 0)
-        D0 = (S.downsample2_sum(_convT_abs(D1, P["K1"])).reshape(B, -1) * open_["d0"]
+        D0 = (S.downsample2_sum(_convT_abs(D1, r(P["K1"]))).reshape(B, -1) * open_["d0"]
               + np.abs(g0) * near["d0"])
         dd0b = r(dd0)
         M["Wd"], K["Wd"], rho["Wd"] = np.abs(h3b).T @ np.abs(dd0b), B, 4 * U
