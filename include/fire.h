@@ -178,10 +178,14 @@ typedef struct {
  *          map starts at out_maps + i*map_words
  *   map_words  words reserved per map; must be >= H*ceil(W/32) of every
  *          sim's landscape when out_maps != NULL
- * Simulations are grouped by landscape (by size when more than 8
- * landscapes are used) and each group runs as its own persistent launch
- * with LDS sized for it; groups run concurrently on internal streams
- * forked from and joined back to `stream`. Results do not depend on the
+ * With one parameter vector, simulations are grouped by landscape (by
+ * size when more than 8 landscapes are used) and each group runs as its
+ * own persistent launch with LDS sized for it, on internal streams forked
+ * from and joined back to `stream`. With several parameter vectors the
+ * batch runs as one persistent launch whose simulations start in
+ * decreasing order of expected fire size (burnable cells times the
+ * logistic of the parameters at the landscape's mean covariates), so that
+ * the longest fires do not start last. Results do not depend on the
  * schedule (threads, queue sizes, threshold mode), the grouping or the
  * order in which simulations run. Stream-ordered; calls on one context
  * must not overlap on different streams (they share staging and scratch

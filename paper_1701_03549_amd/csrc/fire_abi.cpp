@@ -33,6 +33,11 @@ struct LandscapeHost {
   // kWindowRetryMax)
   float win_frac = 0.f;
   int win_obs = 0;
+  // landscape means for ordering simulations by expected fire size: share
+  // of forest among burnable cells, mean psi, mean sigma of an edge, and
+  // the number of burnable cells
+  double mean_forest = 0.0, mean_psi = 0.0, mean_sigma = 0.0;
+  int64_t burnable = 0;
 };
 
 struct TargetHost {
@@ -120,6 +125,7 @@ struct fire_ctx {
 
 namespace {
 
+constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxClasses = 8;   // concurrent persistent launches per fire_run
 constexpr int kErrWord = 16;     // error flag word in d_work
 constexpr int kWorkWords = 32;
@@ -884,6 +890,24 @@ fire_status fire_landscape_load(fire_ctx *c, const fire_landscape_desc *d,
   LandscapeHost L;
   L.W = W; L.H = H; L.stride = stride;
   L.forest = d->forest_class ? d->forest_class : 1;
+  {
+    // about half of a cell's edges lead uphill, where sigma is slope/100
+    int64_t nb = 0, nf = 0;
+    double sp = 0.0, ss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      if (veg[i] == 0) continue;
+      ++nb;
+      nf += veg[i] == L.forest;
+      if (layers[1][i] > 5.0f) sp += std::cos(((double)layers[2][i] - 315.0) * kPi / 180.0);
+      ss += 0.5 * (double)layers[1][i] / 100.0;
+    }
+    L.burnable = nb;
+    if (nb > 0) {
+      L.mean_forest = (double)nf / (double)nb;
+      L.mean_psi = sp / (double)nb;
+      L.mean_sigma = ss / (double)nb;
+    }
+  }
   uint8_t *d_veg = nullptr;
   float *d_f = nullptr;
   hipError_t e = hipMalloc(&L.rec, sizeof(uint4) * n);
@@ -1157,6 +1181,15 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
                 "fire_run stages host descriptors through pinned memory, which a captured "
                 "graph would read at replay time; use fire_run_dev under stream capture");
 
+  // With several parameter vectors the simulations start in decreasing
+  // order of expected fire size (longest processing time first), so that
+  // the longest fires do not start last and set the launch's tail: expected
+  // size ~ burnable cells x the logistic of the parameters at the
+  // landscape's mean covariates (the wind term averages out over the eight
+  // directions). Such a batch on several landscapes runs as one launch
+  // (size classes would run one after another: each persistent launch
+  // fills the GPU). Results do not depend on the order.
+  const bool lpt = n_params > 1;
   // Size classes: simulations grouped by landscape (by size when there are
   // more landscapes than concurrent launches), each class run by its own
   // persistent launch with LDS sized for that class.
@@ -1169,7 +1202,8 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
     const int l = sims[i].landscape_id;
     if (cls_of_ls[l] < 0) { cls_of_ls[l] = -2; ls_ids.push_back(l); }
   }
-  if ((int)ls_ids.size() <= kMaxClasses) {
+  const bool per_ls = (int)ls_ids.size() <= kMaxClasses && !(lpt && ls_ids.size() > 1);
+  if (per_ls) {
     for (int l : ls_ids) {
       cls_of_ls[l] = (int)cls_cells.size();
       cls_cells.push_back((int64_t)c->ls[l].W * c->ls[l].H);
@@ -1197,6 +1231,23 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
   std::vector<std::vector<uint32_t>> members(n_cls);
   for (int32_t i = 0; i < n_sims; ++i)
     members[cls_of_ls[sims[i].landscape_id]].push_back((uint32_t)i);
+  if (lpt) {
+    std::vector<std::pair<double, uint32_t>> key;
+    for (auto &m : members) {
+      key.resize(m.size());
+      for (size_t j = 0; j < m.size(); ++j) {
+        const fire_sim &sd = sims[m[j]];
+        const LandscapeHost &L = c->ls[sd.landscape_id];
+        const double *b = betas + 5 * (size_t)sd.param_index;
+        const double x = b[0] + b[1] * L.mean_forest + b[2] * L.mean_psi + b[4] * L.mean_sigma;
+        key[j] = {-(double)L.burnable / (1.0 + std::exp(-x)), m[j]};
+      }
+      std::stable_sort(key.begin(), key.end(),
+                       [](const std::pair<double, uint32_t> &u,
+                          const std::pair<double, uint32_t> &v) { return u.first < v.first; });
+      for (size_t j = 0; j < m.size(); ++j) m[j] = key[j].second;
+    }
+  }
   std::vector<RunPlan> plans(n_cls);
   int64_t spill_total = 0;
   harvest_stats(c);
@@ -1205,7 +1256,7 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
   for (int l : ls_ids) {
     const int k = cls_of_ls[l];
     cls_frac[k] = std::max(cls_frac[k], c->ls[l].win_frac);
-    cls_lid[k] = (int)ls_ids.size() <= kMaxClasses ? l : -1;
+    cls_lid[k] = per_ls ? l : -1;
   }
   for (int k = 0; k < n_cls; ++k) {
     fire_status ps = plan_run(c, cls_words[k], cls_cells[k], cls_h[k], cls_stride[k], n_params,
@@ -1269,7 +1320,8 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
     if (tsx != FIRE_OK) return tsx;
   }
   if (n_cls == 1)
-    return launch_run(c, plans[0], d_betas, n_params, d_sims, nullptr, n_sims, seed, tables,
+    return launch_run(c, plans[0], d_betas, n_params, d_sims, lpt ? d_order : nullptr, n_sims,
+                      seed, tables,
                       tstride, tables ? one_ls : -1, out, out_maps, map_words, 0, c->d_ovf,
                       c->d_retry, st, cls_lid[0]);
 
