@@ -6,7 +6,9 @@
 //
 // Built with -ffp-contract=off: every binary64 + - * / below is a single
 // correctly rounded operation, so the only floating-point differences from
-// another IEEE implementation come from exp and cos.
+// another IEEE implementation come from cos and from the logistic function's
+// own exp and reciprocal (logistic_quantised), each within a few units in
+// the last place.
 
 #include <hip/hip_runtime.h>
 
@@ -67,15 +69,60 @@ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1,
 // (ps[2t], ps[2t+1]) and the eight omegas (omega[8t + d]) do not depend on
 // beta and are computed once per landscape.
 __device__ __forceinline__ uint32_t quantise(double p) {
-  if (!(p < 1.0)) return kSaturated;
-  if (!(p > 0.0)) return 0u;
+  // branch-free: p >= 1, NaN and values that round to 2^32 - 1 or above
+  // saturate, p <= 0 gives 0
   const double scaled = rint(p * 4294967296.0);
-  if (scaled >= 4294967295.0) return kSaturated;
-  return (uint32_t)scaled;
+  const double clamped = scaled > 0.0 ? (scaled < 4294967295.0 ? scaled : 0.0) : 0.0;
+  const uint32_t t = (uint32_t)clamped;
+  const bool sat = !(p < 1.0) || scaled >= 4294967295.0;
+  return sat ? kSaturated : t;
 }
 
 __device__ __forceinline__ double omega_of(float wind_deg, int d) {
   return cos(((double)wind_deg - 45.0 * (double)d) * kDegToRad);
+}
+
+// Eq. 1's probability 1 / (1 + e^(-x)), quantised. e^(-x) by Cody and
+// Waite's two-constant reduction, -x = n ln2 + r with |r| <= ln2 / 2 (the
+// upper part of ln 2 has 32 significant bits, so n times it is exact), and
+// the Taylor series of e^r to degree 12, whose truncation error is below
+// 2e-16 relative; the reciprocal of 1 + e^(-x) by the hardware estimate and
+// two Newton steps. The probability then lies within a few units in the
+// last place of the correctly rounded one, which moves a quantised
+// threshold by one unit for about one x in 10^7. Beyond |x| = 40 the
+// quantised value is 0 or saturated already, so x is clamped there; a NaN
+// saturates.
+__device__ __forceinline__ uint32_t logistic_quantised(double x) {
+  constexpr double kLog2e = 1.4426950408889634074;
+  constexpr double kLn2Hi = 6.93147180369123816490e-01;
+  constexpr double kLn2Lo = 1.90821492927058770002e-10;
+  const bool nan = x != x;
+  x = fmin(fmax(x, -40.0), 40.0);
+  const double n = rint(-x * kLog2e);
+  double r = fma(-n, kLn2Hi, -x);
+  r = fma(-n, kLn2Lo, r);
+  double e = 1.0 / 479001600.0;  // 1/12!
+  e = fma(e, r, 1.0 / 39916800.0);
+  e = fma(e, r, 1.0 / 3628800.0);
+  e = fma(e, r, 1.0 / 362880.0);
+  e = fma(e, r, 1.0 / 40320.0);
+  e = fma(e, r, 1.0 / 5040.0);
+  e = fma(e, r, 1.0 / 720.0);
+  e = fma(e, r, 1.0 / 120.0);
+  e = fma(e, r, 1.0 / 24.0);
+  e = fma(e, r, 1.0 / 6.0);
+  e = fma(e, r, 0.5);
+  e = fma(e, r, 1.0);
+  e = fma(e, r, 1.0);
+  const double d = 1.0 + __builtin_amdgcn_ldexp(e, (int)n);
+  double q = __builtin_amdgcn_rcp(d);
+  q = fma(q, fma(-d, q, 1.0), q);
+  q = fma(q, fma(-d, q, 1.0), q);
+  // q lies in (0, 1 + 2^-52]: rint(q 2^32) is in [0, 2^32], and a value
+  // at or above 2^32 - 1 saturates (as quantise does)
+  const double scaled = rint(q * 4294967296.0);
+  const uint32_t t = (uint32_t)fmin(scaled, 4294967295.0);
+  return nan || scaled >= 4294967295.0 ? kSaturated : t;
 }
 
 __device__ __forceinline__ uint32_t logistic_threshold(const double *beta, double i_f, double psi,
@@ -85,7 +132,7 @@ __device__ __forceinline__ uint32_t logistic_threshold(const double *beta, doubl
   x = x + beta[2] * psi;
   x = x + beta[3] * omega;
   x = x + beta[4] * sigma;
-  return quantise(1.0 / (1.0 + exp(-x)));
+  return logistic_quantised(x);
 }
 
 // The threshold from the landscape's precomputed covariates (F: pointer type
@@ -148,8 +195,8 @@ __global__ void preprocess_kernel(const uint8_t *veg, const float *elev,
 constexpr int kBetaPerThread = 16;
 
 __global__ void thresholds_kernel(const LandscapeDev *lsd, int W, int H,
-                                  const double *beta_dev, int n_beta, uint32_t forest,
-                                  uint32_t *out_base, int64_t out_stride) {
+                                  const double *__restrict__ beta_dev, int n_beta, uint32_t forest,
+                                  uint32_t *__restrict__ out_base, int64_t out_stride) {
   // parameter vectors b0 .. b0 + nb - 1; vector b's table at out_base + b * out_stride
   const LandscapeDev L = *lsd;
   const int b0 = blockIdx.y * kBetaPerThread;
@@ -177,23 +224,25 @@ __global__ void thresholds_kernel(const LandscapeDev *lsd, int W, int H,
       cs[d] = ((rec.w >> (8 + d)) & 1u) ? L.ps[2 * t + 1] : 0.0;
       co[d] = omega_of(__uint_as_float(rec.z), d);
     }
-    // one table at a time: 8 independent evaluations per vector
+    // one table at a time: the 8 evaluations of a vector are independent
+    // and branch-free (an edge that cannot burn is evaluated on zero
+    // covariates and its result discarded)
 #pragma unroll 1
     for (int b = 0; b < nb; ++b) {
-      const double *beta = beta_dev + 5 * (int64_t)(b0 + b);
+      const double *bp = beta_dev + 5 * (int64_t)(b0 + b);
+      double beta[5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) beta[i] = bp[i];
       uint4 *o = reinterpret_cast<uint4 *>(out_base + (int64_t)(b0 + b) * out_stride + s * 8);
+      uint32_t t[8];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        uint32_t t4[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int d = 4 * h + k;
-          t4[k] = ((ok >> d) & 1u)
-                      ? logistic_threshold(beta, ((fm >> d) & 1u) ? 1.0 : 0.0, cp[d], co[d], cs[d])
-                      : 0u;
-        }
-        o[h] = make_uint4(t4[0], t4[1], t4[2], t4[3]);
+      for (int d = 0; d < 8; ++d) {
+        const uint32_t v =
+            logistic_threshold(beta, ((fm >> d) & 1u) ? 1.0 : 0.0, cp[d], co[d], cs[d]);
+        t[d] = ((ok >> d) & 1u) ? v : 0u;
       }
+      o[0] = make_uint4(t[0], t[1], t[2], t[3]);
+      o[1] = make_uint4(t[4], t[5], t[6], t[7]);
     }
   }
 }

@@ -51,8 +51,10 @@ def test_thresholds_within_one_unit(g, W, H, seed):
 
 def test_thresholds_dev_equals_host_entry(g):
     """fire_thresholds_dev (device parameters, several tables in one launch)
-    writes the tables fire_thresholds writes; a NaN parameter saturates every
-    burnable edge."""
+    writes the tables fire_thresholds writes for one vector; a NaN parameter
+    saturates every burnable edge, alone or among other vectors (the host
+    entry rejects it, so the single NaN vector goes through the device
+    entry)."""
     import torch
     W, H = 100, 67
     ls = synth.make_landscape(W, H, 6)
@@ -67,6 +69,9 @@ def test_thresholds_dev_equals_host_entry(g):
     # calibration vector (its logit is at least -12.5)
     live = T[0] > 0
     assert np.all(T[4][live] == U32) and np.all(T[4][~live] == 0)
+    # one NaN vector alone
+    T1 = g.thresholds_dev(lid, torch.from_numpy(betas[4:5]).cuda()).cpu().numpy().view(np.uint32)
+    assert np.array_equal(T1[0], T[4])
     g.free_landscape(lid)
 
 
