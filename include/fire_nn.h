@@ -128,6 +128,40 @@ fire_status fire_nn_select(const double *cand, const float *score, int32_t n,
                            int32_t G, int32_t keep, int32_t k, double *out,
                            int32_t *out_idx, void *stream);
 
+/* Training rows from simulator runs (device pointers). Row i of out_x
+ * [n][7] fp32 is the network input of run i: parameter row i / reps of
+ * params [*][5] binary64 (rounded to nearest fp32), then the ignition
+ * (ign [n][2] fp32, or the constant pair ign_x, ign_y when ign is NULL);
+ * out_y [n] fp32 receives log(1 + delta) of results[i].fitness (Eq. 2,
+ * binary64 log1p rounded to fp32), the surrogate's fitness target;
+ * out_fit [n] binary64 the fitness itself. Any output may be NULL (params
+ * only when out_x is). n >= 0, reps >= 1. Stream-ordered. */
+fire_status fire_nn_rows_from_results(const double *params, int32_t reps,
+                                      const float *ign, float ign_x, float ign_y,
+                                      const fire_result *results, int32_t n,
+                                      float *out_x, float *out_y,
+                                      double *out_fit, void *stream);
+
+/* Row gather (device pointers): row k of dst [n][row_bytes] is row
+ * rows[k] of src; used for shuffled minibatches of training rows, targets
+ * and maps. row_bytes a positive multiple of 4; rows [n] int64 must index
+ * rows of src (not checked on the device); dst must not overlap src.
+ * n >= 0. Stream-ordered. */
+fire_status fire_gather_rows(const void *src, int64_t row_bytes,
+                             const int64_t *rows, int32_t n, void *dst,
+                             void *stream);
+
+/* Screening candidates from n_sets offspring sets drawn from one parent
+ * population (sets [n_sets][P][5] binary64, e.g. n_sets calls of
+ * fire_ga_step on copies of the population): cand receives all P rows of
+ * set 0, then rows E..P-1 of sets 1..n_sets-1 (their rows 0..E-1 are the
+ * same elites), P + (n_sets - 1)(P - E) rows of 5 values; x the matching
+ * network inputs [rows][7] fp32 (parameters rounded to nearest, then the
+ * constant ignition). n_sets >= 1, 0 <= E < P. Stream-ordered. */
+fire_status fire_nn_candidates(const double *sets, int32_t n_sets, int32_t P,
+                               int32_t E, float ign_x, float ign_y,
+                               double *cand, float *x, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -681,6 +681,71 @@ __global__ __launch_bounds__(1024) void select_kernel(const double *cand, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Training rows from simulation results: row i takes parameter row
+// i / reps (binary64 -> fp32, round to nearest), the ignition (a row of
+// `ign` or the constant pair) and the target log(1 + delta) of result i's
+// Eq. 2 fitness (binary64 log1p, then rounded to fp32); delta itself is
+// copied to out_fit. Any output may be NULL.
+__global__ void rows_from_results_kernel(const double *params, int reps, const float *ign,
+                                         float ign_x, float ign_y, const fire_result *res, int n,
+                                         float *out_x, float *out_y, double *out_fit) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double delta = res[i].fitness;
+    if (out_fit) out_fit[i] = delta;
+    if (out_y) out_y[i] = (float)log1p(delta);
+    if (out_x) {
+      const double *b = params + 5 * (int64_t)(i / reps);
+      float *x = out_x + 7 * (int64_t)i;
+      for (int k = 0; k < 5; ++k) x[k] = (float)b[k];
+      x[5] = ign ? ign[2 * (int64_t)i] : ign_x;
+      x[6] = ign ? ign[2 * (int64_t)i + 1] : ign_y;
+    }
+  }
+}
+
+// dst row k = src row rows[k]; rows of `words` 32-bit words, copied with
+// 16-byte moves when `vec` (rows and both bases 16-byte aligned).
+__global__ void gather_rows_kernel(const uint32_t *src, int64_t words, const int64_t *rows, int n,
+                                   uint32_t *dst, int vec) {
+  const int64_t per = vec ? words / 4 : words;
+  const int64_t total = (int64_t)n * per;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = t / per, w = t % per;
+    const int64_t r = rows[k];
+    if (vec) {
+      reinterpret_cast<uint4 *>(dst + k * words)[w] =
+          reinterpret_cast<const uint4 *>(src + r * words)[w];
+    } else {
+      dst[k * words + w] = src[r * words + w];
+    }
+  }
+}
+
+// Screening candidates from `n_sets` offspring sets [n_sets][P][5]: all of
+// set 0, then rows E..P-1 of every later set (its first E rows are the
+// elites again); binary64 rows to cand, fp32 network inputs (parameters,
+// then the constant ignition) to x.
+__global__ void candidates_kernel(const double *sets, int n_sets, int P, int E, float ign_x,
+                                  float ign_y, double *cand, float *x) {
+  const int n = P + (n_sets - 1) * (P - E);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int src = i;
+    if (i >= P) {
+      const int o = 1 + (i - P) / (P - E), j = E + (i - P) % (P - E);
+      src = o * P + j;
+    }
+    for (int k = 0; k < 5; ++k) {
+      const double v = sets[5 * (int64_t)src + k];
+      cand[5 * (int64_t)i + k] = v;
+      x[7 * (int64_t)i + k] = (float)v;
+    }
+    x[7 * (int64_t)i + 5] = ign_x;
+    x[7 * (int64_t)i + 6] = ign_y;
+  }
+}
+
 }  // namespace
 }  // namespace firenn
 
@@ -1104,6 +1169,41 @@ fire_status fire_nn_select(const double *cand, const float *score, int32_t n, in
     return FIRE_E_INVALID;
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, cand, score, n,
                      G, keep, k, out, out_idx);
+  return hipGetLastError() == hipSuccess ? FIRE_OK : FIRE_E_DEVICE;
+}
+
+fire_status fire_nn_rows_from_results(const double *params, int32_t reps, const float *ign,
+                                      float ign_x, float ign_y, const fire_result *results,
+                                      int32_t n, float *out_x, float *out_y, double *out_fit,
+                                      void *stream) {
+  if (n < 0 || !results || reps < 1 || (out_x && !params)) return FIRE_E_INVALID;
+  if (n == 0) return FIRE_OK;
+  hipLaunchKernelGGL(rows_from_results_kernel, dim3(blocks_for(n)), dim3(256), 0,
+                     (hipStream_t)stream, params, reps, ign, ign_x, ign_y, results, n, out_x,
+                     out_y, out_fit);
+  return hipGetLastError() == hipSuccess ? FIRE_OK : FIRE_E_DEVICE;
+}
+
+fire_status fire_gather_rows(const void *src, int64_t row_bytes, const int64_t *rows, int32_t n,
+                             void *dst, void *stream) {
+  if (n < 0 || row_bytes < 4 || row_bytes % 4 != 0 || (n > 0 && (!src || !rows || !dst)))
+    return FIRE_E_INVALID;
+  if (n == 0) return FIRE_OK;
+  const int vec = row_bytes % 16 == 0 && (uintptr_t)src % 16 == 0 && (uintptr_t)dst % 16 == 0;
+  const int64_t words = row_bytes / 4;
+  hipLaunchKernelGGL(gather_rows_kernel,
+                     dim3(blocks_for((int64_t)n * (vec ? words / 4 : words))), dim3(256), 0,
+                     (hipStream_t)stream, (const uint32_t *)src, words, rows, n, (uint32_t *)dst,
+                     vec);
+  return hipGetLastError() == hipSuccess ? FIRE_OK : FIRE_E_DEVICE;
+}
+
+fire_status fire_nn_candidates(const double *sets, int32_t n_sets, int32_t P, int32_t E,
+                               float ign_x, float ign_y, double *cand, float *x, void *stream) {
+  if (!sets || !cand || !x || n_sets < 1 || P < 1 || E < 0 || E >= P) return FIRE_E_INVALID;
+  const int n = P + (n_sets - 1) * (P - E);
+  hipLaunchKernelGGL(candidates_kernel, dim3(blocks_for(n)), dim3(256), 0,
+                     (hipStream_t)stream, sets, n_sets, P, E, ign_x, ign_y, cand, x);
   return hipGetLastError() == hipSuccess ? FIRE_OK : FIRE_E_DEVICE;
 }
 

@@ -53,10 +53,9 @@ def make_dataset(g: fire.FireGPU, lid: int, tid: int, n: int, seed: int, sim_see
         sims = fire.make_sims(e - s, lid, tid, ign[s:e], param_index=np.arange(e - s),
                               sim_index=np.arange(s, e, dtype=np.uint32))
         res, m = g.run(betas[s:e], sims, sim_seed, want_maps=maps)
-        delta = res.view(torch.float64).reshape(-1, 3)[:, 2]
-        y_t[s:e] = torch.log1p(delta).float()
-        X[s:e, :5] = torch.from_numpy(betas[s:e]).float().to(g.device)
-        X[s:e, 5:] = torch.from_numpy(ign[s:e]).float().to(g.device)
+        d_par = torch.from_numpy(np.ascontiguousarray(betas[s:e])).to(g.device)
+        d_ign = torch.from_numpy(ign[s:e].astype(np.float32)).to(g.device)
+        nn.rows_from_results(res, e - s, params=d_par, ign=d_ign, out_x=X[s:e], out_y=y_t[s:e])
         if maps:
             y_map[s:e] = nn.pool_maps(m, e - s, W, H, m.shape[1])
     g.sync()
@@ -64,19 +63,29 @@ def make_dataset(g: fire.FireGPU, lid: int, tid: int, n: int, seed: int, sim_see
 
 
 def train(net: nn.Surrogate, X, y_t, y_map, epochs=4, batch=512, lr=1e-3, seed=0, log=None):
+    """Adam over shuffled minibatches (a host-side permutation per epoch;
+    rows gathered on the device by fire_gather_rows); returns the mean
+    losses of every epoch."""
     n = X.shape[0]
-    gen = torch.Generator(device="cpu").manual_seed(seed)
+    dev = X.device
+    rng = np.random.default_rng(seed)
+    xb = torch.empty((batch, 7), dtype=torch.float32, device=dev)
+    yb = torch.empty(batch, dtype=torch.float32, device=dev)
+    mb = torch.empty((batch, nn.MAP, nn.MAP), dtype=torch.uint8, device=dev) \
+        if y_map is not None else None
+    steps = n // batch
+    losses = torch.empty((max(steps, 1), 2), dtype=torch.float32, device=dev)
     hist = []
     for ep in range(epochs):
-        perm = torch.randperm(n, generator=gen).to(X.device)
-        acc = torch.zeros(2, device=X.device)
-        k = 0
-        for s in range(0, n - batch + 1, batch):
-            idx = perm[s:s + batch]
-            xm = y_map[idx] if y_map is not None else None
-            acc += net.train_step(X[idx], y_t[idx], xm, lr=lr)
-            k += 1
-        ep_loss = (acc / max(k, 1)).cpu().numpy()
+        perm = torch.from_numpy(rng.permutation(n).astype(np.int64)).to(dev)
+        for k in range(steps):
+            idx = perm[k * batch:(k + 1) * batch]
+            nn.gather_rows(X, idx, xb)
+            nn.gather_rows(y_t, idx, yb)
+            if mb is not None:
+                nn.gather_rows(y_map, idx, mb)
+            net.train_step(xb, yb, mb, lr=lr, out_loss=losses[k])
+        ep_loss = losses[:steps].cpu().numpy().mean(axis=0) if steps else np.zeros(2)
         hist.append(ep_loss)
         if log:
             log(f"epoch {ep}: fitness loss {ep_loss[0]:.4f}, map loss {ep_loss[1]:.4f}")
@@ -123,6 +132,7 @@ def run_ga(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=
     dev = g.device
     screen = net is not None and oversample > 1
     pop_in = torch.from_numpy(np.ascontiguousarray(pop0, dtype=np.float64)).to(dev)
+    pop = torch.empty_like(pop_in)
     hist_pop = torch.empty((generations, P, 5), dtype=torch.float64, device=dev)
     hist_fit = torch.empty((generations, P, R), dtype=torch.float64, device=dev)
     res = torch.empty((P * R, 24), dtype=torch.uint8, device=dev)
@@ -130,24 +140,40 @@ def run_ga(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=
     sims = fire.make_sims(generations * P * R, lid, tid, ign,
                           param_index=np.tile(np.repeat(np.arange(P), R), generations))
     d_sims_all = torch.from_numpy(sims.view(np.uint8).copy()).to(dev).reshape(-1, 28)
-    bank_x = torch.empty((generations * P * R, 7), dtype=torch.float32, device=dev)
-    bank_y = torch.empty(generations * P * R, dtype=torch.float32, device=dev)
-    idx = []
-    if screen and online_steps > 0:
-        idx = [torch.from_numpy(a).to(dev)
+    ign_xy = (float(ign[0]), float(ign[1]))
+    online = screen and online_steps > 0
+    if online:
+        bank_x = torch.empty((generations * P * R, 7), dtype=torch.float32, device=dev)
+        bank_y = torch.empty(generations * P * R, dtype=torch.float32, device=dev)
+        xb = torch.empty((net.max_batch, 7), dtype=torch.float32, device=dev)
+        yb = torch.empty(net.max_batch, dtype=torch.float32, device=dev)
+        idx = [torch.from_numpy(a.astype(np.int64)).to(dev)
                for a in online_indices(generations, P, R, online_steps, net.max_batch, seed)]
+    if screen:
+        sets = torch.empty((oversample, P, 5), dtype=torch.float64, device=dev)
+        n_cand = P + (oversample - 1) * (P - E)
+        cand = torch.empty((n_cand, 5), dtype=torch.float64, device=dev)
+        x = torch.empty((n_cand, 7), dtype=torch.float32, device=dev)
+        score = torch.empty(n_cand, dtype=torch.float32, device=dev)
     keep = E + ((P - E) // 2 if unscreened is None else unscreened)
     timing = {"simulation_s": 0.0, "screening_s": 0.0}
 
     def body(stream, eager):
-        pop = pop_in.clone()
+        pop.copy_(pop_in)
         for gen in range(generations):
             d_sims = d_sims_all[gen * P * R:(gen + 1) * P * R]
+            fit = hist_fit[gen]
             hist_pop[gen].copy_(pop)
             t0 = time.perf_counter()
             g.run_dev(pop, d_sims, P * R, sim_seed, res, stream=stream)
-            fit = res.view(torch.float64).reshape(P * R, 3)[:, 2].reshape(P, R).contiguous()
-            hist_fit[gen].copy_(fit)
+            if online:
+                # the exact evaluations join the online training bank
+                k0 = gen * P * R
+                nn.rows_from_results(res, P * R, params=pop, reps=R, ign_xy=ign_xy,
+                                     out_x=bank_x[k0:k0 + P * R], out_y=bank_y[k0:k0 + P * R],
+                                     out_fit=fit, stream=stream)
+            else:
+                nn.rows_from_results(res, P * R, out_fit=fit, stream=stream)
             if eager:
                 torch.cuda.synchronize()
                 timing["simulation_s"] += time.perf_counter() - t0
@@ -155,27 +181,19 @@ def run_ga(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=
                 g.ga_step(pop, fit, cfg, gen, ga_seed, stream=stream)
                 continue
             t0 = time.perf_counter()
-            if online_steps > 0:
-                k0 = gen * P * R
-                bank_x[k0:k0 + P * R, :5] = pop.repeat_interleave(R, dim=0).float()
-                bank_x[k0:k0 + P * R, 5] = float(ign[0])
-                bank_x[k0:k0 + P * R, 6] = float(ign[1])
-                bank_y[k0:k0 + P * R] = torch.log1p(fit.reshape(-1)).float()
+            if online:
                 for s in range(online_steps):
                     rows = idx[gen][s]
-                    net.train_step(bank_x[rows], bank_y[rows], None, lr=online_lr, stream=stream)
-            sets = []
+                    nb = rows.shape[0]
+                    nn.gather_rows(bank_x, rows, xb, stream=stream)
+                    nn.gather_rows(bank_y, rows, yb, stream=stream)
+                    net.train_step(xb[:nb], yb[:nb], None, lr=online_lr, stream=stream)
             for o in range(oversample):
-                p = pop.clone()
-                g.ga_step(p, fit, cfg, gen, ga_seed + o * 0x9E3779B97F4A7C15, stream=stream)
-                sets.append(p if o == 0 else p[E:])
-            cand = torch.cat(sets).contiguous()
-            x = torch.empty((cand.shape[0], 7), dtype=torch.float32, device=dev)
-            x[:, :5] = cand.float()
-            x[:, 5] = float(ign[0])
-            x[:, 6] = float(ign[1])
-            score = net.predict(x, stream=stream)
-            pop, _ = nn.select(cand, score, keep=keep, k=P, stream=stream)
+                sets[o].copy_(pop)
+                g.ga_step(sets[o], fit, cfg, gen, ga_seed + o * 0x9E3779B97F4A7C15, stream=stream)
+            nn.candidates(sets, E, ign_xy, cand, x, stream=stream)
+            net.predict(x, out=score, stream=stream)
+            nn.select(cand, score, keep=keep, k=P, out=pop, stream=stream)
             if eager:
                 torch.cuda.synchronize()
                 timing["screening_s"] += time.perf_counter() - t0
@@ -215,14 +233,15 @@ def make_ignition_dataset(g: fire.FireGPU, lid: int, tid: int, beta, box, n: int
     X = torch.empty((n, 7), dtype=torch.float32, device=g.device)
     y_t = torch.empty(n, dtype=torch.float32, device=g.device)
     beta = np.asarray(beta, dtype=np.float64)
+    d_beta = torch.from_numpy(beta.reshape(1, 5).copy()).to(g.device)
     for s in range(0, n, chunk):
         e = min(n, s + chunk)
         sims = fire.make_sims(e - s, lid, tid, ign[s:e], param_index=0,
                               sim_index=np.arange(s, e, dtype=np.uint32))
         res, _ = g.run(beta[None, :], sims, sim_seed)
-        y_t[s:e] = torch.log1p(res.view(torch.float64).reshape(-1, 3)[:, 2]).float()
-        X[s:e, :5] = torch.from_numpy(np.tile(beta, (e - s, 1))).float().to(g.device)
-        X[s:e, 5:] = torch.from_numpy(ign[s:e] - np.array([x0, y0])).float().to(g.device)
+        d_ign = torch.from_numpy((ign[s:e] - np.array([x0, y0])).astype(np.float32)).to(g.device)
+        nn.rows_from_results(res, e - s, params=d_beta, reps=e - s, ign=d_ign, out_x=X[s:e],
+                             out_y=y_t[s:e])
     g.sync()
     return X, y_t
 
@@ -232,10 +251,10 @@ def screen_ignitions(net: nn.Surrogate, beta, cands, box, keep: int) -> np.ndarr
     fitness (a network trained by make_ignition_dataset on the same box)."""
     x0, y0 = box[0], box[1]
     c = np.asarray(cands, dtype=np.float64)
-    x = torch.empty((len(c), 7), dtype=torch.float32, device=net.device)
-    x[:, :5] = torch.tensor(np.asarray(beta, dtype=np.float32), device=net.device)
-    x[:, 5:] = torch.from_numpy((c - np.array([x0, y0])).astype(np.float32)).to(net.device)
-    score = net.predict(x).cpu().numpy()
+    xh = np.empty((len(c), 7), dtype=np.float32)
+    xh[:, :5] = np.asarray(beta, dtype=np.float64).astype(np.float32)
+    xh[:, 5:] = (c - np.array([x0, y0])).astype(np.float32)
+    score = net.predict(torch.from_numpy(xh).to(net.device)).cpu().numpy()
     return np.sort(np.argsort(score, kind="stable")[:keep])
 
 
@@ -253,4 +272,4 @@ def screened_scan(g: fire.FireGPU, net: nn.Surrogate, lid, tid, beta, cands, box
 
 def best_mean_fitness(hist_fit: torch.Tensor) -> float:
     """Lowest mean-over-replicates fitness of any evaluated individual."""
-    return float(hist_fit.mean(dim=2).min().item())
+    return float(hist_fit.cpu().numpy().mean(axis=2).min())

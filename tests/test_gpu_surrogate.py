@@ -10,7 +10,9 @@
   element by element, each within a tolerance derived from its own magnitude
   product (tests/surrogate_bounds.py);
 * the bias-gradient column sums in their fixed order, exactly;
-* Adam training on a fixed batch lowers the loss.
+* Adam training on a fixed batch lowers the loss;
+* the pipeline's data movers (rows from simulator results, row gathers,
+  screening candidates) against numpy.
 """
 import numpy as np
 import pytest
@@ -195,3 +197,86 @@ def test_training_lowers_loss():
     assert last[0] < 0.2 * first[0]
     assert last[1] < first[1]
     net.close()
+
+
+@pytest.mark.parametrize("n,reps,per_row_ign", [(1, 1, True), (777, 1, True), (1280, 20, False),
+                                                 (4096, 4096, True)])
+def test_rows_from_results(n, reps, per_row_ign):
+    """Network rows from simulator results against numpy: parameters of row
+    i // reps rounded to fp32, the ignition, log(1 + delta) (within one fp32
+    unit: the two libraries' binary64 log1p may differ in the last place)
+    and delta copied bit for bit; NaN fitness (no target) gives NaN."""
+    import torch
+    from paper_1701_03549_amd import fire, nn
+    rng = np.random.default_rng(n + reps)
+    n_par = (n + reps - 1) // reps
+    params = rng.uniform(-30, 30, (n_par, 5))
+    res = np.zeros(n, dtype=fire.RESULT_DTYPE)
+    res["fitness"] = rng.uniform(0, 3, n) ** 3
+    res["fitness"][:: 97] = np.nan
+    res["fitness"][1:: 89] = 0.0
+    ign = rng.integers(0, 1024, (n, 2)).astype(np.float32)
+    d_res = torch.from_numpy(res.view(np.uint8).copy()).cuda()
+    x = torch.full((n, 7), -1.0, dtype=torch.float32, device="cuda")
+    y = torch.full((n,), -1.0, dtype=torch.float32, device="cuda")
+    fit = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
+    say(f"rows from results n={n} reps={reps}")
+    nn.rows_from_results(d_res, n, params=torch.from_numpy(params).cuda(), reps=reps,
+                         ign=torch.from_numpy(ign).cuda() if per_row_ign else None,
+                         ign_xy=(17.0, 23.0), out_x=x, out_y=y, out_fit=fit)
+    xh, yh, fh = x.cpu().numpy(), y.cpu().numpy(), fit.cpu().numpy()
+    want_x = np.empty((n, 7), np.float32)
+    want_x[:, :5] = params[np.arange(n) // reps].astype(np.float32)
+    want_x[:, 5:] = ign if per_row_ign else np.array([17.0, 23.0], np.float32)
+    assert np.array_equal(xh, want_x)
+    assert np.array_equal(fh.view(np.uint64), res["fitness"].view(np.uint64))
+    want_y = np.log1p(res["fitness"]).astype(np.float32)
+    nan = np.isnan(want_y)
+    assert np.array_equal(np.isnan(yh), nan)
+    ulp = np.spacing(np.abs(want_y[~nan]))
+    assert np.all(np.abs(yh[~nan] - want_y[~nan]) <= ulp)
+    # outputs may be omitted
+    fit2 = torch.empty((n,), dtype=torch.float64, device="cuda")
+    nn.rows_from_results(d_res, n, out_fit=fit2)
+    assert np.array_equal(fit2.cpu().numpy().view(np.uint64), fh.view(np.uint64))
+
+
+@pytest.mark.parametrize("row_shape,dtype", [((7,), "float32"), ((1,), "float32"),
+                                             ((128, 128), "uint8"), ((4,), "float64")])
+def test_gather_rows(row_shape, dtype):
+    """Row gather against numpy fancy indexing: 28-byte rows (4-byte moves),
+    4-byte rows, 16 KiB map rows (16-byte moves), repeated and unordered row
+    indices, an empty gather."""
+    import torch
+    from paper_1701_03549_amd import nn
+    rng = np.random.default_rng(len(row_shape) * 7 + row_shape[0])
+    N = 3000
+    src = rng.integers(0, 255, (N,) + row_shape).astype(dtype)
+    rows = rng.integers(0, N, 1111).astype(np.int64)
+    rows[:5] = [0, N - 1, 7, 7, 0]
+    d_src = torch.from_numpy(src).cuda()
+    out = torch.zeros((len(rows),) + row_shape, dtype=d_src.dtype, device="cuda")
+    say(f"gather rows {row_shape} {dtype}")
+    nn.gather_rows(d_src, torch.from_numpy(rows).cuda(), out)
+    assert np.array_equal(out.cpu().numpy(), src[rows])
+    nn.gather_rows(d_src, torch.zeros(0, dtype=torch.int64, device="cuda"), out)
+    assert np.array_equal(out.cpu().numpy(), src[rows])
+
+
+@pytest.mark.parametrize("S,P,E", [(1, 64, 2), (8, 64, 2), (3, 5, 0), (4, 10, 9)])
+def test_candidates(S, P, E):
+    """Screening candidates against numpy: all of set 0, then rows E.. of
+    every later set, and their fp32 network inputs with the ignition."""
+    import torch
+    from paper_1701_03549_amd import nn
+    rng = np.random.default_rng(S * 100 + P + E)
+    sets = rng.normal(0, 5, (S, P, 5))
+    n = P + (S - 1) * (P - E)
+    cand = torch.zeros((n, 5), dtype=torch.float64, device="cuda")
+    x = torch.zeros((n, 7), dtype=torch.float32, device="cuda")
+    say(f"candidates S={S} P={P} E={E}")
+    nn.candidates(torch.from_numpy(sets).cuda(), E, (256.0, 259.0), cand, x)
+    want = np.concatenate([sets[0]] + [sets[o][E:] for o in range(1, S)])
+    assert np.array_equal(cand.cpu().numpy(), want)
+    want_x = np.column_stack([want.astype(np.float32), np.full((n, 2), [256.0, 259.0], np.float32)])
+    assert np.array_equal(x.cpu().numpy(), want_x)
