@@ -13,7 +13,11 @@
  *
  * Network (every matrix product and every decoder convolution takes bf16
  * operands -- activations, weights, back-propagated errors -- and
- * accumulates in fp32 on MFMA; master weights and Adam state fp32):
+ * accumulates in fp32, on MFMA except for the gradients of the last
+ * convolution, whose one output channel would fill one row of a 16-row
+ * MFMA tile: those are summed on VALU over the input's grid, the error
+ * first summed over the 2x2 blocks each tap reads; master weights and Adam
+ * state fp32):
  *   input  x = (b0/30, ..., b4/30, 2x/W - 1, 2y/H - 1), zero-padded to 16
  *   h1 = relu(x  W1 + c1)    W1 16x256  (rows 7..15 unused, kept zero)
  *   h2 = relu(h1 W2 + c2)    W2 256x256

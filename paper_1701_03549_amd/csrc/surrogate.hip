@@ -349,7 +349,7 @@ typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 constexpr int kConvCi = 8, kConvTaps = 9, kConvK = kConvCi * kConvTaps;  // 72
 constexpr int kWgradCols = 80;  // 72 kernel taps, the bias column, padding
 constexpr int kWgradRows = 16;  // output channels, padded
-constexpr int kWgradParts = 512;
+constexpr int kWgradParts = 2048;
 
 __device__ __forceinline__ bf16x8_t as_bf16x8(u16x8_t v) { return __builtin_bit_cast(bf16x8_t, v); }
 
@@ -372,8 +372,8 @@ __device__ __forceinline__ void stage_bf16(uint16_t *dst, const uint16_t *src, i
 // With 8 source channels (C8) the planes are staged channel-interleaved,
 // [row][col][channel], and k = tap * 8 + channel: a lane's 8 k-values of a
 // step are the 8 channels of one source cell, one 16-byte LDS read. With
-// one source channel (the last layer's error) k = tap and the values are
-// read one by one.
+// one source channel k = tap and the values are read one by one (the
+// network's one-channel data gradient runs in upconv_grads_co1_kernel).
 template <bool UP, bool C8>
 __global__ __launch_bounds__(256) void upconv_mfma_kernel(const uint16_t *src, const uint16_t *Kb,
                                                           const float *bias, int S, int Co,
@@ -563,6 +563,132 @@ __global__ __launch_bounds__(256) void upconv_wgrad_mfma_kernel(const uint16_t *
   for (int i = threadIdx.x; i < kWgradRows * kWgradCols; i += blockDim.x)
     part[(int64_t)blockIdx.x * kWgradRows * kWgradCols + i] =
         ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+}
+
+__device__ __forceinline__ float bf16_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Kernel, bias and data gradients of a layer with one output channel (the
+// last decoder layer), on the input's own grid. With nearest 2x upsampling,
+// tap (dy, dx) of output pixel (y, x) reads input cell
+// ((y + dy - 1) >> 1, (x + dx - 1) >> 1), so
+//   dK[c][dy][dx] = sum over input cells (Y, X) of in[c][Y][X] times the
+//                   sum of g over output rows {2Y+1-dy, 2Y+2-dy} and
+//                   columns {2X+1-dx, 2X+2-dx} (pixels outside the output
+//                   contribute nothing),
+// a quarter of the multiply-adds of the per-pixel form and no im2col; the
+// bias gradient is the sum of g over the 2x2 blocks {2Y, 2Y+1} x
+// {2X, 2X+1}. With one output channel an MFMA tile would use one of its 16
+// rows, so this runs on VALU. Thread item: one sample's input cells
+// (Y, 2j) and (Y, 2j + 1); their error windows, rows 2Y-1 .. 2Y+2 and
+// columns 4j-1 .. 4j+4, are three 8-byte loads per row, their inputs one
+// 4-byte load per channel. Items are spread over the grid; each thread
+// keeps 73 sums, reduced over the wave (a fixed shuffle tree) and then over
+// the four waves in order, so the result does not depend on timing.
+// Partials [gridDim.x][16][80] (row 0) as the MFMA form. S even, S <= 64.
+// The same box sums also give the layer's data gradient: the
+// error of input cell (Y, X), summed over its 2x2 upsampling block, is
+// sum over taps of K[c][dy][dx] times box (dy, dx); it is zeroed where the
+// layer input's activation act <= 0 and written to din (fp32) and din_b
+// (bf16), as the MFMA data-gradient kernel writes it.
+__global__ __launch_bounds__(256) void upconv_grads_co1_kernel(const uint16_t *g_b,
+                                                               const uint16_t *in_b, int B, int S,
+                                                               float *part, const uint16_t *Kb,
+                                                               const float *act, float *din,
+                                                               uint16_t *din_b) {
+  __shared__ float red[4][kConvK + 1];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int O = 2 * S, half = S / 2;
+  float acc[kConvK + 1];
+#pragma unroll
+  for (int k = 0; k <= kConvK; ++k) acc[k] = 0.0f;
+  float kw[kConvK];
+#pragma unroll
+  for (int k = 0; k < kConvK; ++k) kw[k] = bf16_f32(Kb[k]);
+  const int64_t items = (int64_t)B * S * half;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + t; it < items;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(it / (S * half)), pr = (int)(it % (S * half));
+    const int Y = pr / half, j = pr % half;
+    const uint16_t *gp = g_b + (int64_t)b * O * O;
+    // w[i][m]: error at row 2Y - 1 + i, column 4j - 1 + m (0 outside)
+    float w[4][6];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int y = 2 * Y - 1 + i;
+      uint2 q0 = make_uint2(0u, 0u), q1 = make_uint2(0u, 0u), q2 = make_uint2(0u, 0u);
+      if ((unsigned)y < (unsigned)O) {
+        const uint2 *row = reinterpret_cast<const uint2 *>(gp + (int64_t)y * O);
+        if (j > 0) q0 = row[j - 1];
+        q1 = row[j];
+        if (j + 1 < half) q2 = row[j + 1];
+      }
+      w[i][0] = __uint_as_float(q0.y & 0xFFFF0000u);
+      w[i][1] = __uint_as_float(q1.x << 16);
+      w[i][2] = __uint_as_float(q1.x & 0xFFFF0000u);
+      w[i][3] = __uint_as_float(q1.y << 16);
+      w[i][4] = __uint_as_float(q1.y & 0xFFFF0000u);
+      w[i][5] = __uint_as_float(q2.x << 16);
+    }
+    float v0[kConvCi], v1[kConvCi];
+#pragma unroll
+    for (int c = 0; c < kConvCi; ++c) {
+      const uint32_t pv =
+          *reinterpret_cast<const uint32_t *>(in_b + ((int64_t)(b * kConvCi + c) * S + Y) * S + 2 * j);
+      v0[c] = __uint_as_float(pv << 16);
+      v1[c] = __uint_as_float(pv & 0xFFFF0000u);
+    }
+    float dsum[2][kConvCi];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      // cell (Y, 2j + h): window columns 2h .. 2h + 3 of w
+      float cp[4][3];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) cp[i][dx] = w[i][2 * h + 2 - dx] + w[i][2 * h + 3 - dx];
+      float box[kConvTaps];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) box[3 * dy + dx] = cp[2 - dy][dx] + cp[3 - dy][dx];
+#pragma unroll
+      for (int c = 0; c < kConvCi; ++c) {
+        const float v = h ? v1[c] : v0[c];
+        float d = 0.0f;
+#pragma unroll
+        for (int tap = 0; tap < kConvTaps; ++tap) {
+          acc[c * kConvTaps + tap] = fmaf(box[tap], v, acc[c * kConvTaps + tap]);
+          d = fmaf(kw[c * kConvTaps + tap], box[tap], d);
+        }
+        dsum[h][c] = d;
+      }
+      acc[kConvK] += (w[1][2 * h + 1] + w[1][2 * h + 2]) + (w[2][2 * h + 1] + w[2][2 * h + 2]);
+    }
+#pragma unroll
+    for (int c = 0; c < kConvCi; ++c) {
+      const int64_t o = ((int64_t)(b * kConvCi + c) * S + Y) * S + 2 * j;
+      const float2 a = *reinterpret_cast<const float2 *>(act + o);
+      const float r0 = a.x > 0.0f ? dsum[0][c] : 0.0f, r1 = a.y > 0.0f ? dsum[1][c] : 0.0f;
+      *reinterpret_cast<float2 *>(din + o) = make_float2(r0, r1);
+      *reinterpret_cast<uint32_t *>(din_b + o) = (uint32_t)f2bf(r0) | ((uint32_t)f2bf(r1) << 16);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k <= kConvK; ++k) {
+    float v = acc[k];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off);
+    acc[k] = v;
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k <= kConvK; ++k) red[wave][k] = acc[k];
+  __syncthreads();
+  float *out = part + (int64_t)blockIdx.x * kWgradRows * kWgradCols;
+  for (int i = t; i < kWgradRows * kWgradCols; i += blockDim.x) {
+    const int r = i / kWgradCols, k = i % kWgradCols;
+    out[i] = (r == 0 && k <= kConvK) ? ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k] : 0.0f;
+  }
 }
 
 // dK[co][ci][dy][dx] and dkb[co] from the partials of `parts` workgroups:
@@ -871,7 +997,7 @@ hipError_t forward(fire_nn *nn, const float *x, int B, hipStream_t s, bool want_
 // and layer input in_b [B][8][S][S] (both bf16).
 hipError_t conv_weight_grad(fire_nn *nn, const uint16_t *g_b, const uint16_t *in_b, int B, int Co,
                             int S, float *dK, float *dkb, hipStream_t s) {
-  const int parts = B < kWgradParts ? B : kWgradParts;
+  const int parts = B < 512 ? B : 512;
   const int O = 2 * S;
   const size_t lds = sizeof(uint16_t) * ((size_t)(Co * O * O + 7) / 8 * 8 + (size_t)kD0C * S * S);
   hipLaunchKernelGGL(upconv_wgrad_mfma_kernel, dim3(parts), dim3(256), lds, s, g_b, in_b, B, S, Co,
@@ -902,9 +1028,16 @@ hipError_t backward(fire_nn *nn, const float *y_t, const uint8_t *y_map, int B, 
     // bf16; the data gradient comes back summed over the 2x2 upsampling
     // blocks and masked by the layer input's ReLU
     hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(nz)), dim3(256), 0, s, nn->gz, nn->gzb, nz);
-    if ((e = conv_weight_grad(nn, nn->gzb, nn->d2b, B, 1, 64, g + L.K3.off, g + L.k3.off, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((upconv_mfma_kernel<false, false>), dim3(B), dim3(256), conv_lds(1, 128), s,
-                       nn->gzb, wb + L.K3.off, nullptr, 64, 1, 0, nn->d2, nn->gd2, nn->gd2b);
+    // last layer (one output channel): kernel, bias and data gradients from
+    // the same 2x2 box sums of the error
+    {
+      const int64_t blocks = ((int64_t)B * 64 * 32 + 255) / 256;
+      const int parts = (int)(blocks < kWgradParts ? blocks : kWgradParts);
+      hipLaunchKernelGGL(upconv_grads_co1_kernel, dim3(parts), dim3(256), 0, s, nn->gzb,
+                         nn->d2b, B, 64, nn->wpart, wb + L.K3.off, nn->d2, nn->gd2, nn->gd2b);
+      hipLaunchKernelGGL(wgrad_finish_kernel, dim3(kConvK + 1), dim3(256), 0, s, nn->wpart, parts,
+                         1, g + L.K3.off, g + L.k3.off);
+    }
     if ((e = conv_weight_grad(nn, nn->gd2b, nn->d1b, B, kD0C, 32, g + L.K2.off, g + L.k2.off, s)) != hipSuccess) return e;
     hipLaunchKernelGGL((upconv_mfma_kernel<false, true>), dim3(B), dim3(256), conv_lds(kD0C, 64), s,
                        nn->gd2b, wb + L.K2.off, nullptr, 32, kD0C, 0, nn->d1, nn->gd1, nn->gd1b);

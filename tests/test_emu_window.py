@@ -16,7 +16,7 @@ barriers, wave operations as rendezvous, and sequentially consistent memory.
 
 The default case runs in about a minute. FIRE_EMU_FULL=1 also runs the case
 of the GPU failure: 512x512, a 128-cell window, 64 simulations and four
-workgroups, about half an hour.
+workgroups, about ten minutes.
 """
 import os
 import pathlib
@@ -94,7 +94,7 @@ def test_window_1024_threads_small(emu_binary, tmp_path):
     assert 0 < reruns < 8
 
 
-@pytest.mark.skipif(os.environ.get("FIRE_EMU_FULL") != "1", reason="about half an hour; FIRE_EMU_FULL=1")
+@pytest.mark.skipif(os.environ.get("FIRE_EMU_FULL") != "1", reason="about ten minutes; FIRE_EMU_FULL=1")
 def test_window_1024_threads_gpu_failure_case(emu_binary, tmp_path):
     """512x512 (landscape seed 102), 128-cell window, queues of 1024 entries,
     64 simulations at the calibration vector, four concurrent workgroups."""
