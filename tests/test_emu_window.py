@@ -14,7 +14,9 @@ never gives a 1024-thread schedule a window. This test shows that the kernel's
 logic at that size completes and is exact under the emulated semantics:
 barriers, wave operations as rendezvous, and sequentially consistent memory.
 
-The default case runs in about a minute. FIRE_EMU_FULL=1 also runs the case
+The same small case also runs on 256-thread workgroups, the size of the
+512x512 calibration schedule. The default cases run in about a minute.
+FIRE_EMU_FULL=1 also runs the case
 of the GPU failure: 512x512, a 128-cell window, 64 simulations and four
 workgroups, about ten minutes.
 """
@@ -44,21 +46,25 @@ def _compiler():
     pytest.skip("no clang++ for the host")
 
 
-@pytest.fixture(scope="module")
-def emu_binary(tmp_path_factory):
-    out = tmp_path_factory.mktemp("emu_build")
+def _build(out, block):
     sys.path.insert(0, str(EMU))
     try:
         import mkkernel
     finally:
         sys.path.pop(0)
     mkkernel.generate(out / "kernel.inc")
-    exe = out / "emu_wg"
+    exe = out / f"emu_wg_{block}"
     cmd = [_compiler(), "-std=c++20", "-O1", "-g", "-fsanitize=address", "-pthread",
-           f"-I{out}", f"-I{EMU}", f"-I{REPO / 'include'}", str(EMU / "emu_wg.cpp"), "-o", str(exe)]
+           f"-DEMU_BLOCK={block}", f"-I{out}", f"-I{EMU}", f"-I{REPO / 'include'}",
+           str(EMU / "emu_wg.cpp"), "-o", str(exe)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-4000:]
     return exe
+
+
+@pytest.fixture(scope="module")
+def emu_binary(tmp_path_factory):
+    return _build(tmp_path_factory.mktemp("emu_build"), 1024)
 
 
 def _run_case(exe, tmp, W, H, land_seed, n, window, qcap, groups):
@@ -91,6 +97,14 @@ def test_window_1024_threads_small(emu_binary, tmp_path):
     simulations on two concurrent workgroups: two fires outgrow the window
     and are run again on the whole lattice, six do not."""
     reruns = _run_case(emu_binary, tmp_path, 128, 128, 6, 8, 96, 256, 2)
+    assert 0 < reruns < 8
+
+
+def test_window_256_threads_small(tmp_path):
+    """The workgroup size of the 512x512 calibration schedule: the same case
+    on 256-thread workgroups, four at once."""
+    exe = _build(tmp_path, 256)
+    reruns = _run_case(exe, tmp_path, 128, 128, 6, 8, 96, 256, 4)
     assert 0 < reruns < 8
 
 
