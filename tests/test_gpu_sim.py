@@ -75,6 +75,39 @@ def test_thresholds_dev_equals_host_entry(g):
     g.free_landscape(lid)
 
 
+def test_logistic_quantisation_over_x(g):
+    """The quantised logistic of Eq. 1 over x, through one-edge tables: on a
+    2x1 lattice of non-forest flat cells with no wind term, the east edge of
+    cell 0 has logit x = b0 exactly, so 200,000 parameter vectors (x, 0, 0,
+    0, 0) in one launch give the kernel's own evaluation (exp by range
+    reduction and a polynomial, reciprocal by Newton steps, the clamp at
+    |x| = 40) for x uniform in [-45, 45], a dense band around the ends of the
+    quantisation range and special values. Every threshold is within one unit
+    of the oracle's libm evaluation and at most 1 in 10^4 differ at all."""
+    import torch
+    ls = {"veg": np.array([[2, 2]], np.uint8), "elev_m": np.zeros((1, 2), np.float32),
+          "slope_deg": np.zeros((1, 2), np.float32), "aspect_deg": np.zeros((1, 2), np.float32),
+          "wind_to_deg": np.zeros((1, 2), np.float32)}
+    lid = g.load_landscape(ls)
+    rng = np.random.default_rng(77)
+    special = [0.0, -0.0, 40.0, -40.0, 40.000001, -40.000001, 21.5, -22.87, 1e-300, -1e-300,
+               709.0, -709.0, 1e300, -1e300, np.inf, -np.inf, np.nan]
+    x = np.concatenate([rng.uniform(-45, 45, 200000), rng.uniform(21.0, 23.5, 20000),
+                        rng.uniform(-23.5, -21.0, 20000), special])
+    betas = np.zeros((len(x), 5))
+    betas[:, 0] = x
+    say(f"logistic over {len(x)} logits")
+    T = g.thresholds_dev(lid, torch.from_numpy(betas).cuda()).cpu().numpy().view(np.uint32)
+    got = T[:, 0, 0, 2].astype(np.int64)
+    want = np.array([oracle.quantise(oracle.spread_probability((v, 0, 0, 0, 0), 0.0, 0.0, 0.0, 0.0))
+                     for v in x], dtype=np.int64)
+    d = np.abs(got - want)
+    assert d.max() <= 1, x[np.argmax(d)]
+    assert np.count_nonzero(d) <= len(x) // 10000, np.count_nonzero(d)
+    assert np.array_equal(got[-len(special):], want[-len(special):])
+    g.free_landscape(lid)
+
+
 def test_tables_for_many_parameter_vectors(g):
     """Table mode with 13 parameter vectors: one threshold launch writes the
     13 tables, 8 vectors per thread and a partial last group; every
