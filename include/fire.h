@@ -356,6 +356,19 @@ fire_status fire_ga_step(fire_ctx *ctx, double *pop, const double *fit,
                          const fire_ga_cfg *cfg, uint32_t gen,
                          uint64_t ga_seed, void *stream);
 
+/* Offspring sets of one parent population (Appendix B operators, as
+ * fire_ga_step): set o of out_sets [n_sets][P][G] (device) is the
+ * population fire_ga_step would make from pop and fit at generation gen
+ * under seed ga_seed + o * seed_step (mod 2^64), with pop left unchanged;
+ * used to draw several candidate offspring sets for screening in one
+ * launch. out_sets must not overlap pop. 1 <= n_sets <= 1024; sizes and
+ * configuration as fire_ga_step. Stream-ordered. */
+fire_status fire_ga_offspring(fire_ctx *ctx, const double *pop, const double *fit,
+                              int32_t P, int32_t G, int32_t R,
+                              const fire_ga_cfg *cfg, uint32_t gen,
+                              uint64_t ga_seed, uint64_t seed_step,
+                              int32_t n_sets, double *out_sets, void *stream);
+
 /* fire_ga_step with a box and a mutation half-width per gene (host arrays
  * lo[G], hi[G], h[G]); used when genes have different ranges, e.g. the
  * ignition cell carried as genes 5 and 6 (Appendix B: 7 parameters when

@@ -1628,6 +1628,27 @@ fire_status fire_ga_step(fire_ctx *c, double *pop, const double *fit, double *me
   return FIRE_OK;
 }
 
+fire_status fire_ga_offspring(fire_ctx *c, const double *pop, const double *fit, int32_t P,
+                              int32_t G, int32_t R, const fire_ga_cfg *cfg, uint32_t gen,
+                              uint64_t ga_seed, uint64_t seed_step, int32_t n_sets,
+                              double *out_sets, void *stream) {
+  if (!c) return FIRE_E_INVALID;
+  if (!pop || !fit || !cfg || !out_sets) return fail(c, FIRE_E_INVALID, "null argument");
+  if (P < 1 || P > 1024 || G < 2 || G > 16 || R < 1 || cfg->elite < 0 || cfg->elite > P ||
+      cfg->generations < 1 || !(cfg->lo <= cfg->hi) || ga_step_lds(P, G) > c->max_lds ||
+      n_sets < 1 || n_sets > 1024)
+    return fail(c, FIRE_E_INVALID, "GA sizes, configuration or set count out of range");
+  const uintptr_t a0 = (uintptr_t)pop, a1 = a0 + sizeof(double) * (size_t)P * G;
+  const uintptr_t b0 = (uintptr_t)out_sets, b1 = b0 + sizeof(double) * (size_t)n_sets * P * G;
+  if (a0 < b1 && b0 < a1) return fail(c, FIRE_E_INVALID, "out_sets overlaps pop");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, launch_ga_offspring(pop, fit, P, G, R, cfg->elite, cfg->pm0,
+                                     uniform_box(cfg->lo, cfg->hi, cfg->mut_h), gen,
+                                     cfg->generations, ga_seed, seed_step, n_sets, out_sets,
+                                     (hipStream_t)stream));
+  return FIRE_OK;
+}
+
 fire_status fire_ga_step_genes(fire_ctx *c, double *pop, const double *fit, double *mean_fit,
                                int32_t P, int32_t G, int32_t R, int32_t elite, double pm0,
                                const double *lo, const double *hi, const double *h,

@@ -130,6 +130,10 @@ hipError_t launch_ga_step(double *pop, const double *fit, double *mean_fit,
                           const GeneBox &box, uint32_t gen,
                           uint32_t *gen_ptr, uint32_t generations,
                           uint32_t key0, uint32_t key1, hipStream_t s);
+hipError_t launch_ga_offspring(const double *pop, const double *fit, int P, int G, int R,
+                               int elite, double pm0, const GeneBox &box, uint32_t gen,
+                               uint32_t generations, uint64_t seed, uint64_t seed_step,
+                               int n_sets, double *out_sets, hipStream_t s);
 hipError_t launch_sims_from_pop(const double *pop, int P, int G, int R,
                                 int32_t landscape_id, int32_t target_id, int W,
                                 int H, uint32_t gen, const uint32_t *gen_ptr,

@@ -1309,11 +1309,17 @@ __global__ __launch_bounds__(kWave) void simw_kernel(SimArgs a) {
 // Genetic-algorithm generation (Appendix B): elitism, tournament of two,
 // one-point crossover of consecutive non-elite pairs, dynamic mutation.
 // One workgroup, thread i owns slot i. Only exact IEEE operations.
-__global__ void ga_step_kernel(double *pop, const double *fit,
+// Workgroup b reads the parents from src and writes its offspring set to
+// dst + b * dst_stride under key (k1:k0) + b * key_step (64-bit): one
+// workgroup with src == dst is the in-place generation step; several give
+// offspring sets of one parent population (gen_ptr is then NULL, and only
+// workgroup 0 writes mean_fit).
+__global__ void ga_step_kernel(const double *src, double *dst, int64_t dst_stride,
+                               uint64_t key_step, const double *fit,
                                double *mean_fit, int P, int G, int R,
                                int elite, double pm0, GeneBox box, uint32_t gen_arg,
                                uint32_t *gen_ptr, uint32_t generations,
-                               uint32_t k0, uint32_t k1) {
+                               uint32_t key0, uint32_t key1) {
   extern __shared__ double sh[];
   double *mean = sh;            // [P]
   double *oldp = sh + P;        // [P][G]
@@ -1321,12 +1327,15 @@ __global__ void ga_step_kernel(double *pop, const double *fit,
   int *order = reinterpret_cast<int *>(newp + P * G);  // [P]
   const uint32_t gen = gen_ptr ? *gen_ptr : gen_arg;
   const int i = threadIdx.x;
+  const uint64_t key = (((uint64_t)key1 << 32) | key0) + (uint64_t)blockIdx.x * key_step;
+  const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+  double *pop = dst + (int64_t)blockIdx.x * dst_stride;
 
   if (i < P) {
     double acc = 0.0;
     for (int r = 0; r < R; ++r) acc = acc + fit[(int64_t)i * R + r];
     mean[i] = acc / (double)R;
-    for (int j = 0; j < G; ++j) oldp[i * G + j] = pop[(int64_t)i * G + j];
+    for (int j = 0; j < G; ++j) oldp[i * G + j] = src[(int64_t)i * G + j];
   }
   __syncthreads();
   if (i < P) order[i] = i;
@@ -1386,7 +1395,7 @@ __global__ void ga_step_kernel(double *pop, const double *fit,
       }
     }
     for (int j = 0; j < G; ++j) pop[(int64_t)i * G + j] = newp[i * G + j];
-    if (mean_fit) mean_fit[i] = mean[i];
+    if (mean_fit && blockIdx.x == 0) mean_fit[i] = mean[i];
   }
   __syncthreads();
   if (gen_ptr && i == 0) *gen_ptr = gen + 1;
@@ -2016,9 +2025,21 @@ hipError_t launch_ga_step(double *pop, const double *fit, double *mean_fit,
                           uint32_t key0, uint32_t key1, hipStream_t s) {
   const int threads = ((P + 63) / 64) * 64;
   const size_t lds = ga_step_lds(P, G);
-  hipLaunchKernelGGL(ga_step_kernel, dim3(1), dim3(threads), lds, s, pop, fit,
-                     mean_fit, P, G, R, elite, pm0, box, gen, gen_ptr,
+  hipLaunchKernelGGL(ga_step_kernel, dim3(1), dim3(threads), lds, s, pop, pop, (int64_t)0,
+                     (uint64_t)0, fit, mean_fit, P, G, R, elite, pm0, box, gen, gen_ptr,
                      generations, key0, key1);
+  return hipGetLastError();
+}
+
+hipError_t launch_ga_offspring(const double *pop, const double *fit, int P, int G, int R,
+                               int elite, double pm0, const GeneBox &box, uint32_t gen,
+                               uint32_t generations, uint64_t seed, uint64_t seed_step,
+                               int n_sets, double *out_sets, hipStream_t s) {
+  const int threads = ((P + 63) / 64) * 64;
+  const size_t lds = ga_step_lds(P, G);
+  hipLaunchKernelGGL(ga_step_kernel, dim3(n_sets), dim3(threads), lds, s, pop, out_sets,
+                     (int64_t)P * G, seed_step, fit, nullptr, P, G, R, elite, pm0, box, gen,
+                     nullptr, generations, (uint32_t)seed, (uint32_t)(seed >> 32));
   return hipGetLastError();
 }
 

@@ -784,16 +784,21 @@ __global__ void pool_maps_kernel(const uint32_t *maps, int n, int W, int H, int6
 __global__ __launch_bounds__(1024) void select_kernel(const double *cand, const float *score,
                                                       int n, int G, int keep, int k, double *out,
                                                       int32_t *out_idx) {
+  // the scores are staged in LDS (n <= 4096): every thread reads all of
+  // them, the same one at a time (a broadcast)
+  __shared__ float sc[4096];
+  for (int i = threadIdx.x; i < n; i += 1024) sc[i] = score[i];
+  __syncthreads();
   for (int i = threadIdx.x; i < n; i += 1024) {
     int slot;
     if (i < keep) {
       slot = i;
     } else {
-      const float si = score[i];
+      const float si = sc[i];
       const bool fi = isfinite(si);
       int rank = 0;
       for (int j = keep; j < n; ++j) {
-        const float sj = score[j];
+        const float sj = sc[j];
         const bool fj = isfinite(sj);
         const bool before = (fj && !fi) || (fj == fi && ((fi && sj < si) || ((!fi || sj == si) && j < i)));
         rank += before ? 1 : 0;

