@@ -4,7 +4,7 @@
 // are a rendezvous of the wave's 64 threads, the lane-pair shuffle a
 // rendezvous of two, atomics take one global lock, and LDS is a per-workgroup
 // buffer. Memory is sequentially consistent between barriers; a watchdog in
-// the driver reports a barrier that never completes.
+// emu_wg.cpp reports a barrier that never completes.
 #pragma once
 #include <algorithm>
 #include <atomic>

@@ -51,7 +51,7 @@ def compare_with_oracle(ls, T_oracle, res, maps, sims, seed, ref_bits=None, idx=
 
 
 def oracle_threads():
-    """Worker threads for oracle batches (the GPU machine gives a run 16 CPU threads)."""
+    """Worker threads for oracle batches (at most 16 host threads)."""
     import os
     return max(1, min(16, os.cpu_count() or 1))
 
