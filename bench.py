@@ -542,7 +542,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only; simulations are independent, so N "
+        print("bench.py: the benchmark measures one GPU only; simulations are independent, so N "
               "GPUs would each run their own share of the batch (see the sharding design). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)

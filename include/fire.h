@@ -55,7 +55,7 @@ typedef enum {
   FIRE_E_INVALID = -1,     /* bad argument or unknown id                 */
   FIRE_E_OOM = -2,         /* device or host allocation failed           */
   FIRE_E_DEVICE = -3,      /* HIP runtime / kernel error                 */
-  FIRE_E_UNSUPPORTED = -4  /* valid request this build cannot serve      */
+  FIRE_E_UNSUPPORTED = -4  /* valid request the library cannot serve    */
 } fire_status;
 
 /* ---- context ---------------------------------------------------------- */

@@ -412,7 +412,7 @@ double oracle_fitness(int W, int H, const uint32_t *sim_bits,
 /* Genetic-algorithm generation (Appendix B). The paper states the operators
  * (elitism, tournament of two, one-point crossover, per-gene mutation whose
  * probability decreases with the generation, a small random gene change)
- * but not their constants or random draws; this build fixes them:
+ * but not their constants or random draws; the oracle fixes them:
  *   - fitness of individual i = mean over its R replicate deltas, summed in
  *     replicate order;
  *   - the `elite` best individuals (ordered by fitness, ties by index) are
