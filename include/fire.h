@@ -191,7 +191,12 @@ typedef struct {
  * must not overlap on different streams (they share staging and scratch
  * buffers). Not for stream capture: descriptors are staged through pinned
  * host memory that a graph would read at replay time, so under capture
- * this returns FIRE_E_UNSUPPORTED (use fire_run_dev). */
+ * this returns FIRE_E_UNSUPPORTED (use fire_run_dev).
+ * Size limit: a simulation runs in one workgroup whose LDS holds the
+ * whole-lattice burn bitset (H*ceil(W/32) words) and two frontier queues of
+ * at least 64 entries, so a run needs H*ceil(W/32) <= 40816 words with
+ * 160 KiB of LDS (gfx950), e.g. 1024 x 1275 or 4096 x 318 cells; a run on a
+ * larger lattice returns FIRE_E_UNSUPPORTED. */
 fire_status fire_run(fire_ctx *ctx, const double *betas, int32_t n_params,
                      const fire_sim *sims, int32_t n_sims, uint64_t seed,
                      const uint32_t *thresholds_override, fire_result *out,

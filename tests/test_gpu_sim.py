@@ -199,6 +199,63 @@ def test_ragged_and_degenerate_lattices(g, W, H):
     g.free_landscape(lid)
 
 
+@pytest.mark.parametrize("W,H", [(4096, 16), (8, 4096), (1024, 1275)])
+def test_largest_lattices(g, W, H):
+    """The largest lattices a run takes: 4096 cells wide or tall (the 12-bit
+    coordinates of frontier entries at their limit) and the largest area
+    whose whole-lattice bitset and two 64-entry queues fit one workgroup's
+    160 KiB of LDS (1024 x 1275: 40,800 words). Fires that reach the far
+    edges; every simulation and map against the oracle."""
+    from paper_1701_03549_amd import fire
+    say(f"largest lattice {W}x{H}")
+    ls = synth.random_small_landscape(W, H, seed=W + H, p_blocked=0.05)
+    beta = np.array([(1.5, 0.2, 0.3, 0.5, 0.5)])
+    T = [oracle.thresholds(ls, beta[0])]
+    lid = g.load_landscape(ls)
+    ign = [(W - 2, H - 2), (0, 0), (W // 2, H // 2), (W - 1, 0)]
+    ign = [synth.nearest_burnable(ls["veg"], x, y) for x, y in ign]
+    sims = np.concatenate([fire.make_sims(2, lid, -1, c) for c in ign])
+    sims["sim_index"] = np.arange(len(sims), dtype=np.uint32)
+    res, maps = g.run(beta, sims, SEED, want_maps=True)
+    g.sync()
+    r = _res(res)
+    assert r["burnt"].max() > (W * H) // 2  # fires cross the lattice
+    compare_with_oracle(ls, T, r, _np_maps(maps), sims, SEED)
+    g.free_landscape(lid)
+
+
+def test_lattice_limits_refused(g):
+    """A landscape side beyond 4096 is refused at load; a lattice whose
+    whole-lattice bitset exceeds a workgroup's LDS (2048 x 2048: 131,072
+    words) loads but a run on it returns FIRE_E_UNSUPPORTED, and the context
+    keeps working."""
+    from paper_1701_03549_amd import fire
+
+    def flat(W, H):
+        return {"veg": np.ones((H, W), np.uint8), "elev_m": np.zeros((H, W), np.float32),
+                "slope_deg": np.zeros((H, W), np.float32),
+                "aspect_deg": np.zeros((H, W), np.float32),
+                "wind_to_deg": np.zeros((H, W), np.float32)}
+    with pytest.raises(fire.FireError):
+        g.load_landscape(flat(4097, 4))
+    with pytest.raises(fire.FireError):
+        g.load_landscape(flat(4, 4097))
+    lid = g.load_landscape(flat(2048, 2048))
+    say("run on 2048x2048")
+    with pytest.raises(fire.FireError) as e:
+        g.run(np.array([(0.0, 0, 0, 0, 0)]), fire.make_sims(4, lid, -1, (10, 10)), SEED)
+        g.sync()
+    assert e.value.status == -4  # FIRE_E_UNSUPPORTED
+    g.free_landscape(lid)
+    small = synth.make_landscape(32, 32, 4)
+    lid = g.load_landscape(small)
+    res, _ = g.run(np.array([(0.5, 0, 0, 0, 0)]), fire.make_sims(4, lid, -1, (16, 16)), SEED)
+    g.sync()
+    T = [oracle.thresholds(small, (0.5, 0, 0, 0, 0))]
+    compare_with_oracle(small, T, _res(res), None, fire.make_sims(4, lid, -1, (16, 16)), SEED)
+    g.free_landscape(lid)
+
+
 def test_edge_cases(g):
     from paper_1701_03549_amd import fire
     W, H = 48, 40
