@@ -192,11 +192,13 @@ typedef struct {
  * buffers). Not for stream capture: descriptors are staged through pinned
  * host memory that a graph would read at replay time, so under capture
  * this returns FIRE_E_UNSUPPORTED (use fire_run_dev).
- * Size limit: a simulation runs in one workgroup whose LDS holds the
- * whole-lattice burn bitset (H*ceil(W/32) words) and two frontier queues of
- * at least 64 entries, so a run needs H*ceil(W/32) <= 40816 words with
- * 160 KiB of LDS (gfx950), e.g. 1024 x 1275 or 4096 x 318 cells; a run on a
- * larger lattice returns FIRE_E_UNSUPPORTED. */
+ * Burn state: a simulation runs in one workgroup, whose LDS holds its
+ * burn bitset (H*ceil(W/32) words, or a window of it) and two frontier
+ * queues. A lattice whose whole bitset does not fit LDS (more than 40816
+ * words with 160 KiB on gfx950, e.g. beyond 1024 x 1275 cells) keeps each
+ * workgroup's bitset in global memory instead (at most 1 GiB of such
+ * bitsets per launch, which bounds its resident simulations); results are
+ * the same. */
 fire_status fire_run(fire_ctx *ctx, const double *betas, int32_t n_params,
                      const fire_sim *sims, int32_t n_sims, uint64_t seed,
                      const uint32_t *thresholds_override, fire_result *out,
@@ -252,7 +254,8 @@ fire_status fire_run_dev(fire_ctx *ctx, const double *betas_dev,
  * are evaluated per trial (no context tables). The launch grids shrink so
  * that the spill area fits; a batch that cannot fit even one workgroup's
  * spill area (about 2 * W * H words for the largest loaded landscape, plus
- * n_sims + 65 words) is rejected with FIRE_E_INVALID before any device
+ * n_sims + 65 words), or whose lattice needs its burn bitsets in global
+ * memory (see fire_run), is rejected with FIRE_E_INVALID before any device
  * work. Every call on one GPU shares that GPU's array and leaves its
  * contents behind (counters are cleared by each call): calls that overlap
  * on one GPU, on any stream or context, race and must not be issued.

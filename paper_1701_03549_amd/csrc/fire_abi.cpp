@@ -76,7 +76,7 @@ struct fire_ctx {
   // workgroups of each simulation-kernel variant resident per CU as far as
   // registers allow ([threads 64..1024][table][turn-off times][window];
   // 0 = unknown)
-  int reg_blocks[5][2][2][2] = {};
+  int reg_blocks[5][2][2][3] = {};  // [threads][table][dur][whole LDS, window, global bitset]
   // resident workgroups per CU of (variant, dynamic LDS bytes), as the
   // runtime computes them (allocation granularity included)
   std::map<std::pair<int, size_t>, int> occ_cache;
@@ -271,6 +271,9 @@ int queue_cap_for(size_t bytes, int bitset_words, bool dur) {
 
 constexpr int kMaxPerCu = 16;  // built-in workgroups per compute unit, at most
 constexpr int64_t kTableBudget = (int64_t)2 << 30;  // bytes of threshold tables per run
+// bytes of global-memory burn bitsets per launch (caps the resident
+// simulations of a lattice whose bitset does not fit LDS)
+constexpr int64_t kGlobalBitsBudget = (int64_t)1 << 30;
 // LDS per workgroup left unused by the built-in queue sizing: with every
 // byte of an equal share taken, gfx950 kept one workgroup fewer resident
 // than the runtime's occupancy figure (measured: 5 x 32.4 KiB ran 4 per CU)
@@ -281,23 +284,25 @@ int threads_index(int t) { return t == 64 ? 0 : t == 128 ? 1 : t == 256 ? 2 : t 
 // Workgroups of a simulation-kernel variant resident per CU as far as its
 // registers allow (queried once per variant; LDS is accounted separately),
 // negated for a variant whose registers spill to scratch.
-int reg_blocks(fire_ctx *c, int threads, bool table, bool dur, bool win) {
-  int &v = c->reg_blocks[threads_index(threads)][table ? 1 : 0][dur ? 1 : 0][win ? 1 : 0];
+int reg_blocks(fire_ctx *c, int threads, bool table, bool dur, bool win, bool gb = false) {
+  int &v = c->reg_blocks[threads_index(threads)][table ? 1 : 0][dur ? 1 : 0][win ? 1 : gb ? 2 : 0];
   if (v == 0) {
-    v = sim_occupancy(threads, table, dur, win, 0);
+    v = sim_occupancy(threads, table, dur, win, 0, gb);
     if (v <= 0) v = 1;
     // a variant that spills registers to scratch is not a built-in choice
-    if (sim_scratch_bytes(threads, table, dur, win) > 0) v = -v;
+    if (sim_scratch_bytes(threads, table, dur, win, gb) > 0) v = -v;
   }
   return v;
 }
 
 // Workgroups of a variant resident per CU with `lds` bytes of dynamic LDS.
-int resident(fire_ctx *c, int threads, bool table, bool dur, bool win, size_t lds) {
-  const int key = threads_index(threads) * 8 + (table ? 4 : 0) + (dur ? 2 : 0) + (win ? 1 : 0);
+int resident(fire_ctx *c, int threads, bool table, bool dur, bool win, size_t lds,
+             bool gb = false) {
+  const int key = threads_index(threads) * 16 + (gb ? 8 : 0) + (table ? 4 : 0) + (dur ? 2 : 0) +
+                  (win ? 1 : 0);
   auto it = c->occ_cache.find({key, lds});
   if (it != c->occ_cache.end()) return it->second;
-  int v = sim_occupancy(threads, table, dur, win, lds);
+  int v = sim_occupancy(threads, table, dur, win, lds, gb);
   if (v < 0) v = 0;
   c->occ_cache[{key, lds}] = v;
   return v;
@@ -313,7 +318,8 @@ int resident(fire_ctx *c, int threads, bool table, bool dur, bool win, size_t ld
 // fronts in one pass).
 fire_schedule default_schedule(fire_ctx *c, int64_t max_cells,
                                int bitset_words, int32_t n_params, bool dur = false,
-                               int64_t n_sims = (int64_t)1 << 30, bool win = false) {
+                               int64_t n_sims = (int64_t)1 << 30, bool win = false,
+                               bool gb = false) {
   fire_schedule best{};
   int64_t best_conc = -1;
   // a table per parameter vector pays off once each serves a few
@@ -334,13 +340,13 @@ fire_schedule default_schedule(fire_ctx *c, int64_t max_cells,
     // the resident workgroups (no more than the batch fills) share the LDS;
     // queues take what is left (less a margin the hardware needs)
     const int64_t need = std::max<int64_t>(1, (n_sims + c->num_cu - 1) / c->num_cu);
-    const int rb = reg_blocks(c, threads, table, dur, win);
+    const int rb = reg_blocks(c, threads, table, dur, win, gb);
     if (rb < 0 && threads > 128) continue;  // spills; 128 threads is the fallback
     const int res = (int)std::min<int64_t>(std::min(per_cu, rb < 0 ? -rb : rb), need);
     int qcap = queue_cap_for(c->max_lds / res - kLdsMargin, bitset_words, dur);
     if (qcap > 16384) qcap = 16384;
     while (qcap > 64 &&
-           resident(c, threads, table, dur, win, lds_bytes_for(bitset_words, qcap, dur)) < res)
+           resident(c, threads, table, dur, win, lds_bytes_for(bitset_words, qcap, dur), gb) < res)
       qcap -= 64;
     if (qcap < 64) qcap = 64;
     const int64_t conc = std::min<int64_t>((int64_t)res * c->num_cu, n_sims);
@@ -361,6 +367,9 @@ struct RunPlan {
   fire_schedule s;
   bool wave;  // first launch: one simulation per wavefront (simw_kernel)
   bool dur;  // some landscape of the launch has turn-off times
+  // whole-lattice launches whose bitset does not fit LDS keep it in global
+  // memory (gb: the first launch, gb2: the re-run launch of a window plan)
+  bool gb = false, gb2 = false;
   int bitset_words;
   int64_t max_cells;
   size_t lds;
@@ -392,7 +401,7 @@ constexpr int kWaveQueue = 512;
 
 // LDS, queue and residency of one launch shape; false if it cannot fit.
 bool shape_launch(fire_ctx *c, fire_schedule &s, int bitset_words, bool dur, bool win,
-                  int32_t n_sims, size_t *lds_out, int *grid_out) {
+                  int32_t n_sims, size_t *lds_out, int *grid_out, bool gb = false) {
   if (dur && lds_bytes_for(bitset_words, s.queue_cap, true) > c->max_lds) {
     // a schedule tuned without life bytes: shrink the LDS queues to fit
     // (results do not depend on the queue capacity)
@@ -402,7 +411,7 @@ bool shape_launch(fire_ctx *c, fire_schedule &s, int bitset_words, bool dur, boo
   const size_t lds = lds_bytes_for(bitset_words, s.queue_cap, dur);
   if (lds > c->max_lds) return false;
   // workgroups that fit at once (registers, LDS and its granularity)
-  const int fit = resident(c, s.threads, s.table_mode != 0, dur, win, lds);
+  const int fit = resident(c, s.threads, s.table_mode != 0, dur, win, lds, gb);
   int per_cu = s.wg_per_cu < fit ? s.wg_per_cu : fit;
   if (per_cu < 1) per_cu = 1;
   int64_t grid = (int64_t)per_cu * c->num_cu;
@@ -446,17 +455,30 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
   fire_schedule full = s;
   size_t lds = 0;
   int grid = 0;
-  if (!shape_launch(c, full, bitset_words, dur, false, n_sims, &lds, &grid))
-    return fail(c, FIRE_E_UNSUPPORTED,
-                "LDS needed (%zu B: %d bitset words + 2x%d queue entries) "
-                "exceeds the device limit of %zu B",
-                lds_bytes_for(bitset_words, full.queue_cap, dur), bitset_words, full.queue_cap,
-                c->max_lds);
+  bool gb = false;
+  if (!shape_launch(c, full, bitset_words, dur, false, n_sims, &lds, &grid)) {
+    // the whole-lattice bitset does not fit LDS: each workgroup keeps its
+    // simulation's bitset in global memory and the LDS holds the queues
+    gb = true;
+    if (!c->sched_fixed) {
+      const int tm = full.table_mode;
+      full = default_schedule(c, max_cells, 0, n_params, dur, n_sims, false, true);
+      full.table_mode = tm;
+    }
+    if (!shape_launch(c, full, 0, dur, false, n_sims, &lds, &grid, true))
+      return fail(c, FIRE_E_UNSUPPORTED,
+                  "LDS needed (%zu B: 2x%d queue entries) exceeds the device limit of %zu B",
+                  lds_bytes_for(0, full.queue_cap, dur), full.queue_cap, c->max_lds);
+    const int64_t cap = std::max<int64_t>(1, kGlobalBitsBudget / (4 * (int64_t)bitset_words));
+    if (grid > cap) grid = (int)cap;
+  }
   full.window = 0;
   full.wave = 0;
   out->s = full;
   out->wave = false;
   out->dur = dur;
+  out->gb = gb;
+  out->gb2 = false;
   out->bitset_words = bitset_words;
   out->max_cells = max_cells;
   out->lds = lds;
@@ -533,6 +555,8 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
       ws.wg_per_cu = 1;
       ws.window = wside;
       ws.wave = 1;
+      out->gb = false;
+      out->gb2 = gb;
       out->s2 = full;
       out->bitset_words2 = bitset_words;
       out->lds2 = lds;
@@ -580,6 +604,8 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
   if (sim_scratch_bytes(ws.threads, ws.table_mode != 0, dur, true) > 0) return FIRE_OK;
   ws.window = win;
   ws.wave = 0;
+  out->gb = false;
+  out->gb2 = gb;
   out->s2 = full;
   out->bitset_words2 = bitset_words;
   out->lds2 = lds;
@@ -604,13 +630,25 @@ int64_t spill_words_one(int64_t max_cells, int queue_cap, int grid, bool dur) {
   return entries + (dur ? (entries + 3) / 4 : 0);
 }
 
-int64_t spill_words(const RunPlan &p) {
+int64_t spill_entry_words(const RunPlan &p) {
   // the wavefront kernel keeps its queues in LDS only
   int64_t w = p.wave ? 0 : spill_words_one(p.max_cells, p.s.queue_cap, p.grid, p.dur);
   if (p.win > 0 || p.wave)
     w = std::max(w, spill_words_one(p.max_cells, p.s2.queue_cap, p.grid2, p.dur));
   return w;
 }
+
+// Global-memory burn bitsets of the plan's launches (one per workgroup of a
+// launch whose whole-lattice bitset does not fit LDS), after the spill
+// entries; the two launches of a window plan run one after the other and
+// share the area.
+int64_t global_bits_words(const RunPlan &p) {
+  int64_t w = p.gb ? (int64_t)p.grid * p.bitset_words : 0;
+  if (p.gb2) w = std::max(w, (int64_t)p.grid2 * p.bitset_words2);
+  return w;
+}
+
+int64_t spill_words(const RunPlan &p) { return spill_entry_words(p) + global_bits_words(p); }
 
 // Retry lists of window runs: `words` words (waits for the device when it grows).
 fire_status ensure_retry(fire_ctx *c, int64_t words, hipStream_t st) {
@@ -709,6 +747,8 @@ fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
   uint32_t *const work2 = two ? wb + counter + kMaxClasses : nullptr;
   // the launches' work counters and the retry count, in one launch
   HIP_OR_FAIL(c, launch_zero_words(a.work, work2, two ? retry : nullptr, st));
+  uint32_t *const gbits = spill + spill_entry_words(p);
+  a.gbits = p.gb ? gbits : nullptr;
   if (two) {
     a.win = p.win;
     a.retry = retry;
@@ -722,6 +762,7 @@ fire_status launch_run(fire_ctx *c, const RunPlan &p, const double *betas_dev,
                          table_stride, table_ls, out, out_maps, map_words, p.max_cells,
                          p.s2.queue_cap, p.grid2, p.dur, p.bitset_words2, work2, spill);
     b.n_dev = retry;
+    b.gbits = p.gb2 ? gbits : nullptr;
     const int slot = stat_lid >= 0 ? stat_slot(c, st) : -1;
     if (slot >= 0) b.stat_out = c->h_stat + slot;
     HIP_OR_FAIL(c, launch_sim(b, p.s2.threads, tables != nullptr, p.dur, p.grid2, p.lds2, st));
@@ -1403,6 +1444,10 @@ static fire_status run_dev_impl(fire_ctx *c, const double *betas_dev, int32_t n_
                             frac);
   if (ps != FIRE_OK) return ps;
   uint32_t *spill = c->d_ovf, *retry = c->d_retry, *work = nullptr;
+  if (noalloc && (plan.gb || plan.gb2))
+    return fail(c, FIRE_E_INVALID,
+                "the no-allocation entry point keeps burn bitsets in LDS; a lattice of %d "
+                "bitset words needs them in global memory", bw);
   if (noalloc) {
     // scratch words: [0, 32) work counters, [64, 65 + n_sims) re-run list,
     // then the spill area of the launches, whose grids shrink to fit it

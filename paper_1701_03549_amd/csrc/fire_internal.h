@@ -56,7 +56,9 @@ struct SimArgs {
                            // remaining-life bytes of the spilled entries
   int64_t ovf_cap;
   int32_t queue_cap;       // frontier entries per queue held in LDS
-  int32_t bitset_words;    // LDS words reserved for the burn bitset
+  int32_t bitset_words;    // words of the burn bitset: in LDS, or per workgroup in gbits
+  uint32_t *gbits;         // NULL (bitset in LDS), or [gridDim][bitset_words] in global
+                           // memory for lattices whose bitset does not fit LDS (no window)
   int32_t win;             // 0, or the side (cells, multiple of 32) of the
                            // LDS window a simulation runs in
   uint32_t *retry;         // window runs: [0] count, [1..] simulations whose
@@ -101,9 +103,10 @@ int simw_occupancy(bool table, bool win, size_t lds_bytes);
 size_t simw_scratch_bytes(bool table, bool win);
 // workgroups of the simulation kernel resident per compute unit for this
 // launch shape (registers and LDS), 0 if unknown
-int sim_occupancy(int threads, bool table, bool dur, bool win, size_t lds_bytes);
+int sim_occupancy(int threads, bool table, bool dur, bool win, size_t lds_bytes,
+                  bool gb = false);
 // per-lane scratch (register spills) of a simulation-kernel variant, bytes
-size_t sim_scratch_bytes(int threads, bool table, bool dur, bool win);
+size_t sim_scratch_bytes(int threads, bool table, bool dur, bool win, bool gb = false);
 // per-cell (paper-style) ablation path
 hipError_t launch_dense_init(uint8_t *st, const LandscapeDev &L, int ix, int iy,
                              unsigned long long *counts, hipStream_t s);

@@ -350,13 +350,35 @@ enum CtlSlot { kSim = 0, kLen0 = 1, kTrials = 4, kNew = 5, kInter = 6, kAbort0 =
 // kRegRounds * BLOCK / 2 cells held in the LDS queue)
 constexpr int kRegRounds = 2;
 
-template <int BLOCK, bool TABLE, bool DUR, bool WIN>
+// GB (global bitset, never with WIN): the burn bitset of the workgroup's
+// simulation is its own a.bitset_words words of a.gbits in global memory
+// instead of LDS, for lattices whose bitset does not fit LDS. Its words are
+// read, written and ORed with agent-scope atomics, which are performed at
+// L2: the waves of the workgroup then never read a stale vector-L1 copy of
+// a word another wave has ORed, nor one left from the workgroup's previous
+// simulation, and the barriers order the phases as they do for LDS.
+template <int BLOCK, bool TABLE, bool DUR, bool WIN, bool GB = false>
 __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
+  static_assert(!(GB && WIN), "a global bitset covers the whole lattice");
   extern __shared__ uint32_t lds[];
   const int bw = a.bitset_words;
   const uint32_t cap = (uint32_t)a.queue_cap;
-  uint32_t *const bits = lds;
-  uint32_t *const ctl = lds + bw + 2 * cap;
+  uint32_t *const bits = GB ? a.gbits + (int64_t)blockIdx.x * bw : lds;
+  const int lbw = GB ? 0 : bw;  // bitset words in LDS
+  auto bload = [&](int w) -> uint32_t {
+    if constexpr (GB) return __hip_atomic_load(&bits[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return bits[w];
+  };
+  auto bstore = [&](int w, uint32_t v) {
+    if constexpr (GB) __hip_atomic_store(&bits[w], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else bits[w] = v;
+  };
+  auto bor = [&](int w, uint32_t v) -> uint32_t {
+    if constexpr (GB)
+      return __hip_atomic_fetch_or(&bits[w], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return atomicOr(&bits[w], v);
+  };
+  uint32_t *const ctl = lds + lbw + 2 * cap;
   gmem_u32 *const spill_base = (gmem_u32 *)(a.ovf + (int64_t)blockIdx.x * 2 * a.ovf_cap);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -375,11 +397,11 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
 
   // frontier queue q (0 or 1), entry i
   auto q_load = [&](uint32_t q, uint32_t i) -> uint32_t {
-    if (i < cap) return lds[bw + q * cap + i];
+    if (i < cap) return lds[lbw + q * cap + i];
     return spill_base[(int64_t)q * a.ovf_cap + (i - cap)];
   };
   auto q_store = [&](uint32_t q, uint32_t i, uint32_t v) {
-    if (i < cap) lds[bw + q * cap + i] = v;
+    if (i < cap) lds[lbw + q * cap + i] = v;
     else spill_base[(int64_t)q * a.ovf_cap + (i - cap)] = v;
   };
 
@@ -491,7 +513,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     const int wwords = wh * ws;
 
     // -- init: bitset = non-burnable map, ignition burnt -------------------
-    for (int w = tid; w < wwords; w += BLOCK) bits[w] = blocked[gw_of(w)];
+    for (int w = tid; w < wwords; w += BLOCK) bstore(w, blocked[gw_of(w)]);
     if (tid == 0) {
       ctl[kLen0 + 0] = 1; ctl[kLen0 + 1] = 0; ctl[kLen0 + 2] = 0;
       ctl[kTrials] = 0; ctl[kNew] = 0; ctl[kInter] = 0;
@@ -506,7 +528,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       return (rec_word(L.rec, (int64_t)y * W + x) >> 16) & 0xFFu;
     };
     if (tid == 0) {
-      bits[bw_of(ix, iy)] |= 1u << (ix & 31);
+      bor(bw_of(ix, iy), 1u << (ix & 31));
       q_store(0, 0, (uint32_t)ix | ((uint32_t)iy << 12));
       if (DUR) l_store(0, 0, life_of(ix, iy));
     }
@@ -604,7 +626,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       for (int k = 0; k < 4; ++k) {
         const int w = in[k] ? q.wk[k] : base;
         const int b = in[k] ? q.bk[k] : xb;
-        elig |= ((bits[w] >> b) & 1u) == 0 ? (1u << k) : 0u;
+        elig |= ((bload(w) >> b) & 1u) == 0 ? (1u << k) : 0u;
       }
       n_tried = __popc(elig);
       // not gated on elig: the rounds then overlap the bitset and table reads
@@ -678,7 +700,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         const bool h = (hit >> k) & 1u;
         const int w = h ? q.wk[k] : base;
         bitv[k] = h ? 1u << q.bk[k] : 0u;
-        old[k] = atomicOr(&bits[w], bitv[k]);
+        old[k] = bor(w, bitv[k]);
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -709,7 +731,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
         const int tx = x + (k == 0 ? 0 : sg), ty = y + (k == 2 ? 0 : (k == 3 ? sg : -sg));
         const uint32_t v = (uint32_t)tx | ((uint32_t)ty << 12);
         if (direct) {
-          lds[bw + (cq ^ 1u) * cap + idx] = v;
+          lds[lbw + (cq ^ 1u) * cap + idx] = v;
           if (DUR) life_lds[(cq ^ 1u) * cap + idx] = 0u;
         } else {
           q_store(cq ^ 1u, idx, v);
@@ -723,7 +745,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
     for (;; ++step) {
       // the frontier length and this lane's first entry are read together
       const uint32_t n_cur = ctl[kLen0 + slot];
-      const uint32_t e_first = lds[bw + cq * cap + min((uint32_t)tid >> 1, cap - 1)];
+      const uint32_t e_first = lds[lbw + cq * cap + min((uint32_t)tid >> 1, cap - 1)];
       aborted = WIN && ctl[kAbort0 + slot] != 0u;
       if (n_cur == 0 || step >= max_steps || aborted) break;
       const int nslot = slot == 2 ? 0 : slot + 1;
@@ -745,7 +767,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
           ent[rr] = 0;
           const uint32_t j = (uint32_t)(tid + rr * BLOCK);
           if (rr * BLOCK < (int)n_units && j < n_units) {
-            const uint32_t e = rr == 0 ? e_first : lds[bw + cq * cap + (j >> 1)];
+            const uint32_t e = rr == 0 ? e_first : lds[lbw + cq * cap + (j >> 1)];
             ent[rr] = e;
             if ((j & 1u) == 0) resolve_life(e, j >> 1);
             uint32_t nt;
@@ -839,7 +861,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       uint32_t inter = 0;
       for (int w = tid; w < wwords; w += BLOCK) {
         const int gw = gw_of(w);
-        inter += __popc(bits[w] & ~blocked[gw] & ref[gw]);
+        inter += __popc(bload(w) & ~blocked[gw] & ref[gw]);
       }
       if (inter) atomicAdd(&ctl[kInter], inter);
       __syncthreads();
@@ -864,7 +886,7 @@ __global__ __launch_bounds__(BLOCK) void sim_kernel(SimArgs a) {
       for (int w = tid; w < words; w += BLOCK) {
         const int y = w / stride, xw = w % stride;
         const bool in = y >= wy0 && y < wy0 + wh && xw >= wx0w && xw < wx0w + ws;
-        m[w] = in ? bits[(y - wy0) * ws + (xw - wx0w)] & ~blocked[w] : 0u;
+        m[w] = in ? bload((y - wy0) * ws + (xw - wx0w)) & ~blocked[w] : 0u;
       }
     }
     __syncthreads();
@@ -1867,6 +1889,9 @@ template <int BLOCK, bool TABLE, bool DUR>
 static void launch_one(const SimArgs &a, bool win, int grid, size_t lds, hipStream_t s) {
   if (win)
     hipLaunchKernelGGL((sim_kernel<BLOCK, TABLE, DUR, true>), dim3(grid), dim3(BLOCK), lds, s, a);
+  else if (a.gbits)
+    hipLaunchKernelGGL((sim_kernel<BLOCK, TABLE, DUR, false, true>), dim3(grid), dim3(BLOCK), lds,
+                       s, a);
   else
     hipLaunchKernelGGL((sim_kernel<BLOCK, TABLE, DUR, false>), dim3(grid), dim3(BLOCK), lds, s, a);
 }
@@ -1886,12 +1911,14 @@ static hipError_t launch_sim_block(const SimArgs &a, bool table, bool dur, int g
 }
 
 template <int BLOCK, bool TABLE, bool DUR>
-static int occupancy_one(size_t lds, bool win) {
+static int occupancy_one(size_t lds, bool win, bool gb) {
   int n = 0;
-  hipError_t e = win ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &n, sim_kernel<BLOCK, TABLE, DUR, true>, BLOCK, lds)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &n, sim_kernel<BLOCK, TABLE, DUR, false>, BLOCK, lds);
+  hipError_t e = win  ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &n, sim_kernel<BLOCK, TABLE, DUR, true>, BLOCK, lds)
+                 : gb ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &n, sim_kernel<BLOCK, TABLE, DUR, false, true>, BLOCK, lds)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &n, sim_kernel<BLOCK, TABLE, DUR, false>, BLOCK, lds);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;
@@ -1900,20 +1927,21 @@ static int occupancy_one(size_t lds, bool win) {
 }
 
 template <int BLOCK>
-static int occupancy_block(bool table, bool dur, bool win, size_t lds) {
-  if (dur) return table ? occupancy_one<BLOCK, true, true>(lds, win)
-                        : occupancy_one<BLOCK, false, true>(lds, win);
-  return table ? occupancy_one<BLOCK, true, false>(lds, win)
-               : occupancy_one<BLOCK, false, false>(lds, win);
+static int occupancy_block(bool table, bool dur, bool win, bool gb, size_t lds) {
+  if (dur) return table ? occupancy_one<BLOCK, true, true>(lds, win, gb)
+                        : occupancy_one<BLOCK, false, true>(lds, win, gb);
+  return table ? occupancy_one<BLOCK, true, false>(lds, win, gb)
+               : occupancy_one<BLOCK, false, false>(lds, win, gb);
 }
 
 template <int BLOCK, bool TABLE, bool DUR>
-static size_t scratch_one(bool win) {
+static size_t scratch_one(bool win, bool gb) {
   hipFuncAttributes at{};
-  hipError_t e = win ? hipFuncGetAttributes(
-                           &at, reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, true>))
-                     : hipFuncGetAttributes(
-                           &at, reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, false>));
+  const void *f =
+      win  ? reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, true>)
+      : gb ? reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, false, true>)
+           : reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, false>);
+  hipError_t e = hipFuncGetAttributes(&at, f);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;
@@ -1922,29 +1950,30 @@ static size_t scratch_one(bool win) {
 }
 
 template <int BLOCK>
-static size_t scratch_block(bool table, bool dur, bool win) {
-  if (dur) return table ? scratch_one<BLOCK, true, true>(win) : scratch_one<BLOCK, false, true>(win);
-  return table ? scratch_one<BLOCK, true, false>(win) : scratch_one<BLOCK, false, false>(win);
+static size_t scratch_block(bool table, bool dur, bool win, bool gb) {
+  if (dur) return table ? scratch_one<BLOCK, true, true>(win, gb)
+                        : scratch_one<BLOCK, false, true>(win, gb);
+  return table ? scratch_one<BLOCK, true, false>(win, gb) : scratch_one<BLOCK, false, false>(win, gb);
 }
 
-size_t sim_scratch_bytes(int threads, bool table, bool dur, bool win) {
+size_t sim_scratch_bytes(int threads, bool table, bool dur, bool win, bool gb) {
   switch (threads) {
-    case 64: return scratch_block<64>(table, dur, win);
-    case 128: return scratch_block<128>(table, dur, win);
-    case 256: return scratch_block<256>(table, dur, win);
-    case 512: return scratch_block<512>(table, dur, win);
-    case 1024: return scratch_block<1024>(table, dur, win);
+    case 64: return scratch_block<64>(table, dur, win, gb);
+    case 128: return scratch_block<128>(table, dur, win, gb);
+    case 256: return scratch_block<256>(table, dur, win, gb);
+    case 512: return scratch_block<512>(table, dur, win, gb);
+    case 1024: return scratch_block<1024>(table, dur, win, gb);
     default: return 0;
   }
 }
 
-int sim_occupancy(int threads, bool table, bool dur, bool win, size_t lds_bytes) {
+int sim_occupancy(int threads, bool table, bool dur, bool win, size_t lds_bytes, bool gb) {
   switch (threads) {
-    case 64: return occupancy_block<64>(table, dur, win, lds_bytes);
-    case 128: return occupancy_block<128>(table, dur, win, lds_bytes);
-    case 256: return occupancy_block<256>(table, dur, win, lds_bytes);
-    case 512: return occupancy_block<512>(table, dur, win, lds_bytes);
-    case 1024: return occupancy_block<1024>(table, dur, win, lds_bytes);
+    case 64: return occupancy_block<64>(table, dur, win, gb, lds_bytes);
+    case 128: return occupancy_block<128>(table, dur, win, gb, lds_bytes);
+    case 256: return occupancy_block<256>(table, dur, win, gb, lds_bytes);
+    case 512: return occupancy_block<512>(table, dur, win, gb, lds_bytes);
+    case 1024: return occupancy_block<1024>(table, dur, win, gb, lds_bytes);
     default: return 0;
   }
 }
@@ -1968,6 +1997,9 @@ static hipError_t set_limit_one(size_t bytes) {
   hipError_t e = hipFuncSetAttribute(
       reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, false>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, false, true>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void *>(&sim_kernel<BLOCK, TABLE, DUR, true>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

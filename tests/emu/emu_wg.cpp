@@ -6,7 +6,10 @@
 // watchdog reports a barrier that never completes with the line every thread
 // waits at.
 //
-// usage: emu_wg CASE_DIR W H WINDOW QUEUE_CAP WORKGROUPS SEED
+// usage: emu_wg CASE_DIR W H WINDOW QUEUE_CAP WORKGROUPS SEED [global]
+// With `global`, the re-run launch keeps each workgroup's whole-lattice
+// bitset in global memory (the form for lattices whose bitset does not fit
+// LDS) and its LDS holds the queues only.
 // CASE_DIR holds the landscape layers veg.bin (uint8), elev.bin, slope.bin,
 // aspect.bin, wind.bin (float32, row-major H x W), which the kernel source's
 // own preprocess_kernel turns into cell records, table.bin (an Eq. 1 table,
@@ -40,7 +43,7 @@ template <class T> std::vector<T> load(const std::string &path) {
   return v;
 }
 
-template <bool WIN>
+template <bool WIN, bool GB = false>
 void run_workgroup(const SimArgs &a, int b, size_t lds_words) {
   std::vector<uint32_t> lds(lds_words, 0xDEADBEEFu);
   WgCtx ctx;
@@ -73,7 +76,7 @@ void run_workgroup(const SimArgs &a, int b, size_t lds_words) {
       g_wg = &ctx;
       g_lds = lds.data();
       g_where = &where[t];
-      sim_kernel<BLOCK, true, false, WIN>(a);
+      sim_kernel<BLOCK, true, false, WIN, GB>(a);
       where[t] = 999999;
       block.arrive_and_drop();
     });
@@ -85,7 +88,11 @@ void run_workgroup(const SimArgs &a, int b, size_t lds_words) {
 }
 
 int main(int argc, char **argv) {
-  if (argc != 8) { fprintf(stderr, "usage: emu_wg CASE_DIR W H WINDOW QUEUE_CAP WORKGROUPS SEED\n"); return 2; }
+  if (argc != 8 && argc != 9) {
+    fprintf(stderr, "usage: emu_wg CASE_DIR W H WINDOW QUEUE_CAP WORKGROUPS SEED [global]\n");
+    return 2;
+  }
+  const bool global_bits = argc == 9 && std::string(argv[8]) == "global";
   const std::string d = argv[1];
   const int W = atoi(argv[2]), H = atoi(argv[3]), win = atoi(argv[4]), cap = atoi(argv[5]);
   const int groups = atoi(argv[6]);
@@ -148,10 +155,15 @@ int main(int argc, char **argv) {
   SimArgs b2 = a;
   b2.work = &work[1]; b2.order = retry.data() + 1; b2.n_dev = retry.data(); b2.win = 0;
   b2.bitset_words = H * stride;
+  std::vector<uint32_t> gbits(global_bits ? (size_t)groups * H * stride : 0, 0xDEADBEEFu);
+  b2.gbits = global_bits ? gbits.data() : nullptr;
   {
     std::vector<std::thread> wgs;
     for (int b = 0; b < groups; ++b)
-      wgs.emplace_back([&, b] { run_workgroup<false>(b2, b, (size_t)H * stride + 2 * cap + 16); });
+      wgs.emplace_back([&, b] {
+        if (global_bits) run_workgroup<false, true>(b2, b, (size_t)2 * cap + 16);
+        else run_workgroup<false>(b2, b, (size_t)H * stride + 2 * cap + 16);
+      });
     for (auto &x : wgs) x.join();
   }
   std::ofstream o(d + "/emu_results.bin", std::ios::binary);

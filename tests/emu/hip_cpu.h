@@ -125,6 +125,10 @@ inline uint32_t mbcnt_hi(uint32_t m, uint32_t acc) {
 #define __builtin_amdgcn_mbcnt_hi(m, a) mbcnt_hi((m), (a))
 #define __popc(x) __builtin_popcount((uint32_t)(x))
 #define __popcll(x) __builtin_popcountll((uint64_t)(x))
+// __hip_atomic_load / store / fetch_or are clang builtins on the host too
+#ifndef __HIP_MEMORY_SCOPE_AGENT
+#define __HIP_MEMORY_SCOPE_AGENT 3
+#endif
 template <class T> T atomicAdd(T *p, T v) { std::lock_guard<std::mutex> g(g_atomic_mu); T o = *p; *p = o + v; return o; }
 template <class T> T atomicOr(T *p, T v) { std::lock_guard<std::mutex> g(g_atomic_mu); T o = *p; *p = o | v; return o; }
 inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }

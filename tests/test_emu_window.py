@@ -67,7 +67,7 @@ def emu_binary(tmp_path_factory):
     return _build(tmp_path_factory.mktemp("emu_build"), 1024)
 
 
-def _run_case(exe, tmp, W, H, land_seed, n, window, qcap, groups):
+def _run_case(exe, tmp, W, H, land_seed, n, window, qcap, groups, global_bits=False):
     from paper_1701_03549_amd import fire
     ls = synth.make_landscape(W, H, land_seed)
     ign = synth.ignition_site(ls)
@@ -80,8 +80,9 @@ def _run_case(exe, tmp, W, H, land_seed, n, window, qcap, groups):
     sims = fire.make_sims(n, 0, -1, ign)
     np.ascontiguousarray(sims).view(np.uint8).tofile(tmp / "sims.bin")
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
-    r = subprocess.run([str(exe), str(tmp), str(W), str(H), str(window), str(qcap), str(groups),
-                        hex(SEED)], capture_output=True, text=True, env=env, timeout=3600)
+    cmd = [str(exe), str(tmp), str(W), str(H), str(window), str(qcap), str(groups), hex(SEED)]
+    r = subprocess.run(cmd + (["global"] if global_bits else []), capture_output=True, text=True,
+                       env=env, timeout=3600)
     assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
     got = np.fromfile(tmp / "emu_results.bin", np.uint8).view(fire.RESULT_DTYPE)
     reruns = int(r.stdout.split("re-runs ")[1].split(" ")[0])
@@ -105,6 +106,16 @@ def test_window_256_threads_small(tmp_path):
     on 256-thread workgroups, four at once."""
     exe = _build(tmp_path, 256)
     reruns = _run_case(exe, tmp_path, 128, 128, 6, 8, 96, 256, 4)
+    assert 0 < reruns < 8
+
+
+def test_global_bitset_reruns_256_threads(tmp_path):
+    """The re-run launch with each workgroup's whole-lattice bitset in global
+    memory (the form for lattices whose bitset does not fit LDS): the window
+    runs that abort are repeated that way, and every result equals the
+    oracle's."""
+    exe = _build(tmp_path, 256)
+    reruns = _run_case(exe, tmp_path, 128, 128, 6, 8, 96, 256, 4, global_bits=True)
     assert 0 < reruns < 8
 
 

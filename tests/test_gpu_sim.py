@@ -199,22 +199,24 @@ def test_ragged_and_degenerate_lattices(g, W, H):
     g.free_landscape(lid)
 
 
-@pytest.mark.parametrize("W,H", [(4096, 16), (8, 4096), (1024, 1275)])
-def test_largest_lattices(g, W, H):
-    """The largest lattices a run takes: 4096 cells wide or tall (the 12-bit
-    coordinates of frontier entries at their limit) and the largest area
-    whose whole-lattice bitset and two 64-entry queues fit one workgroup's
-    160 KiB of LDS (1024 x 1275: 40,800 words). Fires that reach the far
-    edges; every simulation and map against the oracle."""
+@pytest.mark.parametrize("W,H,n", [(4096, 16, 8), (8, 4096, 8), (1024, 1275, 8), (1280, 1024, 8),
+                                   (2048, 2048, 4), (4096, 4096, 2)])
+def test_largest_lattices(g, W, H, n):
+    """Large lattices: 4096 cells wide or tall (the 12-bit coordinates of
+    frontier entries at their limit); 1024 x 1275, the largest area whose
+    whole-lattice bitset and two 64-entry queues fit one workgroup's 160 KiB
+    of LDS; and beyond it (1280 x 1024, 2048^2, 4096^2) the bitset in global
+    memory. Fires that cross the lattice; every simulation and map against
+    the oracle."""
     from paper_1701_03549_amd import fire
-    say(f"largest lattice {W}x{H}")
+    say(f"large lattice {W}x{H}")
     ls = synth.random_small_landscape(W, H, seed=W + H, p_blocked=0.05)
     beta = np.array([(1.5, 0.2, 0.3, 0.5, 0.5)])
     T = [oracle.thresholds(ls, beta[0])]
     lid = g.load_landscape(ls)
-    ign = [(W - 2, H - 2), (0, 0), (W // 2, H // 2), (W - 1, 0)]
+    ign = [(W - 2, H - 2), (0, 0), (W // 2, H // 2), (W - 1, 0)][:max(1, n // 2)]
     ign = [synth.nearest_burnable(ls["veg"], x, y) for x, y in ign]
-    sims = np.concatenate([fire.make_sims(2, lid, -1, c) for c in ign])
+    sims = np.concatenate([fire.make_sims(2, lid, -1, c) for c in ign])[:n]
     sims["sim_index"] = np.arange(len(sims), dtype=np.uint32)
     res, maps = g.run(beta, sims, SEED, want_maps=True)
     g.sync()
@@ -224,11 +226,52 @@ def test_largest_lattices(g, W, H):
     g.free_landscape(lid)
 
 
+def test_global_bitset_reruns_and_turn_off(g):
+    """1600 x 1600 (the paper's lattice-size study): an explicit 256-cell
+    window schedule, so that fires outgrowing their window run again over
+    the whole lattice with the bitset in global memory; then turn-off times
+    (2 steps for vegetation 1, 3 otherwise) on the whole lattice in global
+    memory, per-trial thresholds. Every simulation and map against the
+    oracle."""
+    from paper_1701_03549_amd import fire
+    W = H = 1600
+    say("1600x1600 windows with global-bitset re-runs")
+    ls = synth.random_small_landscape(W, H, seed=16, p_blocked=0.05)
+    beta = np.array([(0.2, 0.1, 0.3, 0.5, 0.5), (-1.2, 0.0, 0.2, 0.3, 0.3)])
+    T = [oracle.thresholds(ls, b) for b in beta]
+    lid = g.load_landscape(ls)
+    c = synth.nearest_burnable(ls["veg"], W // 2, H // 2)
+    sims = fire.make_sims(8, lid, -1, c, param_index=np.arange(8) % 2)
+    g.set_schedule(256, 1024, 1, 4, window=256)
+    try:
+        res, maps = g.run(beta, sims, SEED, want_maps=True)
+        g.sync()
+    finally:
+        g.set_schedule(reset=True)
+    r = _res(res)
+    assert r["burnt"].max() > 256 * 256  # some fires outgrew the window
+    compare_with_oracle(ls, T, r, _np_maps(maps), sims, SEED)
+    say("1600x1600 turn-off times, global bitset")
+    bs = np.full(256, 3, dtype=np.uint8)
+    bs[1] = 2
+    g.set_burn_steps(lid, bs)
+    g.set_schedule(256, 1024, 0, 4, window=0)
+    try:
+        res, maps = g.run(beta, sims, SEED, want_maps=True)
+        g.sync()
+    finally:
+        g.set_schedule(reset=True)
+        g.set_burn_steps(lid, None)
+    compare_with_oracle(ls, T, _res(res), _np_maps(maps), sims, SEED, burn_steps=bs)
+    g.free_landscape(lid)
+
+
 def test_lattice_limits_refused(g):
-    """A landscape side beyond 4096 is refused at load; a lattice whose
-    whole-lattice bitset exceeds a workgroup's LDS (2048 x 2048: 131,072
-    words) loads but a run on it returns FIRE_E_UNSUPPORTED, and the context
-    keeps working."""
+    """A landscape side beyond 4096 is refused at load; the no-allocation
+    entry point, whose scratch holds no global bitsets, refuses a lattice
+    whose bitset does not fit LDS (2048 x 2048), and the context keeps
+    working."""
+    import torch
     from paper_1701_03549_amd import fire
 
     def flat(W, H):
@@ -241,11 +284,15 @@ def test_lattice_limits_refused(g):
     with pytest.raises(fire.FireError):
         g.load_landscape(flat(4, 4097))
     lid = g.load_landscape(flat(2048, 2048))
-    say("run on 2048x2048")
+    say("no-allocation run on 2048x2048")
+    sims = fire.make_sims(4, lid, -1, (10, 10))
+    d_sims = torch.from_numpy(sims.view(np.uint8).copy()).cuda()
+    d_beta = torch.tensor([(0.0, 0, 0, 0, 0)], dtype=torch.float64, device="cuda")
+    out = torch.empty((4, 24), dtype=torch.uint8, device="cuda")
     with pytest.raises(fire.FireError) as e:
-        g.run(np.array([(0.0, 0, 0, 0, 0)]), fire.make_sims(4, lid, -1, (10, 10)), SEED)
+        g.run_dev_noalloc(d_beta, d_sims, 4, SEED, out)
         g.sync()
-    assert e.value.status == -4  # FIRE_E_UNSUPPORTED
+    assert e.value.status == -1  # FIRE_E_INVALID
     g.free_landscape(lid)
     small = synth.make_landscape(32, 32, 4)
     lid = g.load_landscape(small)
