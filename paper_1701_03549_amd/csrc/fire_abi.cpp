@@ -579,7 +579,9 @@ fire_status plan_run(fire_ctx *c, int bitset_words, int64_t max_cells, int max_h
     // whose LDS queues keep kMinAutoQueue entries (fronts then stay in LDS),
     // else the one with the longest queues
     const int top = std::max(max_h, 32 * max_stride);
-    int best_conc = grid;  // a window has to beat whole-lattice bitsets
+    // a window has to beat whole-lattice bitsets in LDS; global-memory
+    // bitsets (L2 atomics every step) lose to any window that fits
+    int best_conc = gb ? 0 : grid;
     int best_q = 0;
     for (int side = 64; side < top; side += 32) {
       fire_schedule ws;
