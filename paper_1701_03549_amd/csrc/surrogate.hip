@@ -368,13 +368,13 @@ __device__ __forceinline__ void stage_bf16(uint16_t *dst, const uint16_t *src, i
 //        A[p][k] = g[co][u-dy+1][v-dx+1], B[k][ci] = K[co][ci][dy][dx];
 //        the 2x2 blocks of dU are summed into din[ci][u/2][v/2], which is
 //        zeroed where act <= 0.
-// src: UP the layer input [8][S][S], !UP the error g [C][2S][2S] (bf16).
-// With 8 source channels (C8) the planes are staged channel-interleaved,
-// [row][col][channel], and k = tap * 8 + channel: a lane's 8 k-values of a
-// step are the 8 channels of one source cell, one 16-byte LDS read. With
-// one source channel k = tap and the values are read one by one (the
-// network's one-channel data gradient runs in upconv_grads_co1_kernel).
-template <bool UP, bool C8>
+// src: UP the layer input [8][S][S], !UP the error g [8][2S][2S] (bf16;
+// the one-channel data gradient of the last layer runs in
+// upconv_grads_co1_kernel). The 8 source planes are staged
+// channel-interleaved, [row][col][channel], and k = tap * 8 + channel: a
+// lane's 8 k-values of a step are the 8 channels of one source cell, one
+// 16-byte LDS read.
+template <bool UP>
 __global__ __launch_bounds__(256) void upconv_mfma_kernel(const uint16_t *src, const uint16_t *Kb,
                                                           const float *bias, int S, int Co,
                                                           int relu, const float *act, float *out,
@@ -382,18 +382,16 @@ __global__ __launch_bounds__(256) void upconv_mfma_kernel(const uint16_t *src, c
   extern __shared__ __attribute__((aligned(16))) uint16_t plane[];
   const int b = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int O = 2 * S;
-  const int srcC = C8 ? kConvCi : 1, srcR = UP ? S : O;
-  const uint16_t *sp = src + (int64_t)b * srcC * srcR * srcR;
-  if (C8) {
+  const int srcR = UP ? S : O;
+  const uint16_t *sp = src + (int64_t)b * kConvCi * srcR * srcR;
+  {
     const int n = srcR * srcR;
     for (int i = threadIdx.x; i < kConvCi * n; i += blockDim.x)
       plane[(i % n) * kConvCi + i / n] = sp[i];
-  } else {
-    stage_bf16(plane, sp, srcR * srcR);
   }
   const int col = lane & 15, kq = lane >> 4;
   const int ncols = UP ? Co : kConvCi;  // columns of the result
-  const int nk = C8 ? kConvTaps * kConvCi : kConvTaps;
+  const int nk = kConvTaps * kConvCi;
   const int steps = (nk + 31) / 32;
   // B fragments of the (up to) three k-steps
   bf16x8_t bw[3];
@@ -403,7 +401,7 @@ __global__ __launch_bounds__(256) void upconv_mfma_kernel(const uint16_t *src, c
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int k = 32 * s + 8 * kq + i;
-      const int t = C8 ? k / kConvCi : k, c = C8 ? k % kConvCi : 0;
+      const int t = k / kConvCi, c = k % kConvCi;
       // UP: column col is co, k runs over (tap, ci). !UP: column col is ci,
       // k runs over (tap, co)
       const bool ok = k < nk && col < ncols;
@@ -434,27 +432,16 @@ __global__ __launch_bounds__(256) void upconv_mfma_kernel(const uint16_t *src, c
       for (int s = 0; s < 3; ++s) {
         if (s >= steps) break;
         u16x8_t a;
-        if (C8) {
-          // tap 4 s + kq, the 8 channels of one source cell
-          const int t = 4 * s + kq;
-          const int yy = y + sgn * (t / 3 - 1), xx = x + sgn * (t % 3 - 1);
-          const bool in = t < kConvTaps && (unsigned)yy < (unsigned)O && (unsigned)xx < (unsigned)O;
-          const int sy = UP ? (yy >> 1) : yy, sx = UP ? (xx >> 1) : xx;
-          if (in) {
-            a = *reinterpret_cast<const u16x8_t *>(&plane[(sy * srcR + sx) * kConvCi]);
-          } else {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) a[i] = 0;
-          }
+        // tap 4 s + kq, the 8 channels of one source cell
+        const int t = 4 * s + kq;
+        const int yy = y + sgn * (t / 3 - 1), xx = x + sgn * (t % 3 - 1);
+        const bool in = t < kConvTaps && (unsigned)yy < (unsigned)O && (unsigned)xx < (unsigned)O;
+        const int sy = UP ? (yy >> 1) : yy, sx = UP ? (xx >> 1) : xx;
+        if (in) {
+          a = *reinterpret_cast<const u16x8_t *>(&plane[(sy * srcR + sx) * kConvCi]);
         } else {
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const int t = 32 * s + 8 * kq + i;
-            const int yy = y + sgn * (t / 3 - 1), xx = x + sgn * (t % 3 - 1);
-            const bool in = t < kConvTaps && (unsigned)yy < (unsigned)O && (unsigned)xx < (unsigned)O;
-            const int sy = UP ? (yy >> 1) : yy, sx = UP ? (xx >> 1) : xx;
-            a[i] = in ? plane[sy * srcR + sx] : (uint16_t)0;
-          }
+          for (int i = 0; i < 8; ++i) a[i] = 0;
         }
         acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), bw[s], acc[r], 0, 0, 0);
       }
@@ -989,11 +976,11 @@ hipError_t forward(fire_nn *nn, const float *x, int B, hipStream_t s, bool want_
   if ((e = gemm(B, kDec, kH, nn->h3b, kH, 1, wb + L.Wd.off, kDec, 1, nn->d0, kDec, w + L.cd.off,
                 1, 0, nn->d0b, s)) != hipSuccess) return e;
   // decoder: d0b (bf16 of d0, from the dense layer) -> d1 -> d2 -> z
-  hipLaunchKernelGGL((upconv_mfma_kernel<true, true>), dim3(B), dim3(256), conv_lds(kD0C, 16), s,
+  hipLaunchKernelGGL((upconv_mfma_kernel<true>), dim3(B), dim3(256), conv_lds(kD0C, 16), s,
                      nn->d0b, wb + L.K1.off, w + L.k1.off, 16, kD0C, 1, nullptr, nn->d1, nn->d1b);
-  hipLaunchKernelGGL((upconv_mfma_kernel<true, true>), dim3(B), dim3(256), conv_lds(kD0C, 32), s,
+  hipLaunchKernelGGL((upconv_mfma_kernel<true>), dim3(B), dim3(256), conv_lds(kD0C, 32), s,
                      nn->d1b, wb + L.K2.off, w + L.k2.off, 32, kD0C, 1, nullptr, nn->d2, nn->d2b);
-  hipLaunchKernelGGL((upconv_mfma_kernel<true, true>), dim3(B), dim3(256), conv_lds(kD0C, 64), s,
+  hipLaunchKernelGGL((upconv_mfma_kernel<true>), dim3(B), dim3(256), conv_lds(kD0C, 64), s,
                      nn->d2b, wb + L.K3.off, w + L.k3.off, 64, 1, 0, nullptr, nn->z, nullptr);
   return hipGetLastError();
 }
@@ -1044,12 +1031,12 @@ hipError_t backward(fire_nn *nn, const float *y_t, const uint8_t *y_map, int B, 
                          1, g + L.K3.off, g + L.k3.off);
     }
     if ((e = conv_weight_grad(nn, nn->gd2b, nn->d1b, B, kD0C, 32, g + L.K2.off, g + L.k2.off, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((upconv_mfma_kernel<false, true>), dim3(B), dim3(256), conv_lds(kD0C, 64), s,
+    hipLaunchKernelGGL((upconv_mfma_kernel<false>), dim3(B), dim3(256), conv_lds(kD0C, 64), s,
                        nn->gd2b, wb + L.K2.off, nullptr, 32, kD0C, 0, nn->d1, nn->gd1, nn->gd1b);
     if ((e = conv_weight_grad(nn, nn->gd1b, nn->d0b, B, kD0C, 16, g + L.K1.off, g + L.k1.off, s)) != hipSuccess) return e;
     // the last data gradient's bf16 copy replaces d0b, which the dense
     // layer's gradient products read next
-    hipLaunchKernelGGL((upconv_mfma_kernel<false, true>), dim3(B), dim3(256), conv_lds(kD0C, 32), s,
+    hipLaunchKernelGGL((upconv_mfma_kernel<false>), dim3(B), dim3(256), conv_lds(kD0C, 32), s,
                        nn->gd1b, wb + L.K1.off, nullptr, 16, kD0C, 0, nn->d0, nn->gd0, nn->d0b);
     // dense decoder layer: gd0 already carries the ReLU mask of d0
     if ((e = gemm(kH, kDec, B, nn->h3b, 1, kH, nn->d0b, kDec, 1, g + L.Wd.off, kDec, nullptr, 0,
@@ -1150,13 +1137,10 @@ fire_status fire_nn_create(int device, const fire_nn_cfg *cfg, uint64_t seed, fi
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&upconv_wgrad_mfma_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&upconv_mfma_kernel<true, true>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&upconv_mfma_kernel<true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&upconv_mfma_kernel<false, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&upconv_mfma_kernel<false, false>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&upconv_mfma_kernel<false>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
   if (e == hipSuccess) e = nn_alloc(nn, &nn->loss, 2);
   if (e != hipSuccess) return fail_out(e);
