@@ -121,8 +121,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const ui
                                                    int64_t sam, int64_t sak, const uint16_t *B,
                                                    int64_t sbk, int64_t sbn, float *C,
                                                    int64_t ldc, const float *bias, int relu,
-                                                   int accumulate, uint16_t *Cb,
-                                                   const float *mask) {
+                                                   int accumulate, uint16_t *Cb) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2][kTM * kLdt];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kTN * kLdt];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -171,8 +170,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const ui
       if (bias) val += bias[n];
       if (accumulate) val += C[(int64_t)m * ldc + n];
       if (relu) val = fmaxf(val, 0.0f);
-      // backward through a ReLU: zero where the forward activation is not positive
-      if (mask && !(mask[(int64_t)m * ldc + n] > 0.0f)) val = 0.0f;
       C[(int64_t)m * ldc + n] = val;
       if (Cb) Cb[(int64_t)m * ldc + n] = f2bf(val);
     }
@@ -190,36 +187,32 @@ int load_mode(const uint16_t *p, int64_t sr, int64_t sk) {
 template <int AM>
 hipError_t gemm_b(int bm, dim3 grid, hipStream_t s, int M, int N, int K, const uint16_t *A,
                   int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk, int64_t sbn, float *C,
-                  int64_t ldc, const float *bias, int relu, int accumulate, uint16_t *Cb,
-                  const float *mask) {
+                  int64_t ldc, const float *bias, int relu, int accumulate, uint16_t *Cb) {
   if (bm == kAlongK)
     hipLaunchKernelGGL((gemm_kernel<AM, kAlongK>), grid, dim3(256), 0, s, M, N, K, A, sam, sak,
-                       B, sbk, sbn, C, ldc, bias, relu, accumulate, Cb, mask);
+                       B, sbk, sbn, C, ldc, bias, relu, accumulate, Cb);
   else if (bm == kAlongRows)
     hipLaunchKernelGGL((gemm_kernel<AM, kAlongRows>), grid, dim3(256), 0, s, M, N, K, A, sam,
-                       sak, B, sbk, sbn, C, ldc, bias, relu, accumulate, Cb, mask);
+                       sak, B, sbk, sbn, C, ldc, bias, relu, accumulate, Cb);
   else
     hipLaunchKernelGGL((gemm_kernel<AM, kElementwise>), grid, dim3(256), 0, s, M, N, K, A, sam,
-                       sak, B, sbk, sbn, C, ldc, bias, relu, accumulate, Cb, mask);
+                       sak, B, sbk, sbn, C, ldc, bias, relu, accumulate, Cb);
   return hipGetLastError();
 }
 
-// mask: NULL, or [M][ldc] activations; the result (and its bf16 copy) is
-// zeroed where the activation is not positive (backward through a ReLU)
 hipError_t gemm(int M, int N, int K, const uint16_t *A, int64_t sam, int64_t sak,
                 const uint16_t *B, int64_t sbk, int64_t sbn, float *C, int64_t ldc,
-                const float *bias, int relu, int accumulate, uint16_t *Cb, hipStream_t s,
-                const float *mask = nullptr) {
+                const float *bias, int relu, int accumulate, uint16_t *Cb, hipStream_t s) {
   dim3 grid((N + kTN - 1) / kTN, (M + kTM - 1) / kTM);
   const int am = load_mode(A, sam, sak), bm = load_mode(B, sbn, sbk);
   if (am == kAlongK)
     return gemm_b<kAlongK>(bm, grid, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, relu,
-                           accumulate, Cb, mask);
+                           accumulate, Cb);
   if (am == kAlongRows)
     return gemm_b<kAlongRows>(bm, grid, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, relu,
-                              accumulate, Cb, mask);
+                              accumulate, Cb);
   return gemm_b<kElementwise>(bm, grid, s, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc, bias, relu,
-                              accumulate, Cb, mask);
+                              accumulate, Cb);
 }
 
 // ---------------------------------------------------------------------------
@@ -241,6 +234,16 @@ __global__ void prep_input_kernel(const float *x, int B, float inv_w, float inv_
   else if (k == 5) v = 2.0f * x[b * 7 + 5] * inv_w - 1.0f;
   else if (k == 6) v = 2.0f * x[b * 7 + 6] * inv_h - 1.0f;
   xb[i] = f2bf(v);
+}
+
+// g <- g * (h > 0) (ReLU backward, in place) and its bf16 copy
+__global__ void relu_bwd_kernel(float *g, const float *h, uint16_t *gb, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = h[i] > 0.0f ? g[i] : 0.0f;
+    g[i] = v;
+    gb[i] = f2bf(v);
+  }
 }
 
 // column sums of d [M][N] (bias gradients) in a fixed order: a workgroup of
@@ -912,7 +915,7 @@ struct fire_nn {
   float *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *t = nullptr, *d0 = nullptr, *d1 = nullptr,
         *d2 = nullptr, *z = nullptr;
   float *gt = nullptr, *gd0 = nullptr, *gd1 = nullptr, *gd2 = nullptr, *gz = nullptr, *gh = nullptr;
-  uint16_t *ghb[2] = {nullptr, nullptr};  // bf16 hidden-layer errors, alternating per layer
+  uint16_t *ghb = nullptr;
   // bf16 copies the decoder's MFMA convolutions read
   uint16_t *d1b = nullptr, *d2b = nullptr, *gzb = nullptr, *gd1b = nullptr, *gd2b = nullptr;
   float *partial = nullptr, *loss = nullptr;
@@ -1052,32 +1055,28 @@ hipError_t backward(fire_nn *nn, const float *y_t, const uint8_t *y_map, int B, 
   if ((e = gemm(kH, 1, B, nn->h3b, 1, kH, nn->dtb, 1, 1, g + L.Wf.off, 1, nullptr, 0, 0, nullptr,
                 s)) != hipSuccess) return e;
   hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, nn->gt, B, 1, g + L.cf.off);
-  // the error at each hidden layer's pre-activation is its GEMM's result
-  // masked by that layer's ReLU (the GEMM epilogue applies the mask and
-  // writes the bf16 copy); the copies alternate between two buffers so a
-  // GEMM never overwrites the operand it reads
+  // dh3 = dt Wf^T (+ dd0 Wd^T)
+  if ((e = gemm(B, kH, 1, nn->dtb, 1, 1, wb + L.Wf.off, 1, 1, nn->gh, kH, nullptr, 0, 0, nullptr,
+                s)) != hipSuccess) return e;
+  if (use_map)
+    if ((e = gemm(B, kH, kDec, nn->d0b, kDec, 1, wb + L.Wd.off, 1, kDec, nn->gh, kH, nullptr, 0, 1,
+                  nullptr, s)) != hipSuccess) return e;
+  // through the three hidden layers
   struct Lay { const uint16_t *in_b; const float *act; const Seg *W; const Seg *c; int kin; };
   const Lay lays[3] = {{nn->h2b, nn->h3, &L.W3, &L.c3, kH},
                        {nn->h1b, nn->h2, &L.W2, &L.c2, kH},
                        {nn->xb, nn->h1, &L.W1, &L.c1, kIn}};
-  // dh3 = dt Wf^T (+ dd0 Wd^T), through the ReLU of h3
-  if ((e = gemm(B, kH, 1, nn->dtb, 1, 1, wb + L.Wf.off, 1, 1, nn->gh, kH, nullptr, 0, 0,
-                use_map ? nullptr : nn->ghb[0], s, use_map ? nullptr : nn->h3)) != hipSuccess)
-    return e;
-  if (use_map)
-    if ((e = gemm(B, kH, kDec, nn->d0b, kDec, 1, wb + L.Wd.off, 1, kDec, nn->gh, kH, nullptr, 0, 1,
-                  nn->ghb[0], s, nn->h3)) != hipSuccess) return e;
-  // through the three hidden layers
   for (int li = 0; li < 3; ++li) {
     const Lay &ly = lays[li];
-    const uint16_t *ge = nn->ghb[li & 1];
-    if ((e = gemm(ly.kin, kH, B, ly.in_b, 1, ly.kin, ge, kH, 1, g + ly.W->off, kH, nullptr, 0,
+    hipLaunchKernelGGL(relu_bwd_kernel, dim3(blocks_for((int64_t)B * kH)), dim3(256), 0, s, nn->gh,
+                       ly.act, nn->ghb, (int64_t)B * kH);
+    if ((e = gemm(ly.kin, kH, B, ly.in_b, 1, ly.kin, nn->ghb, kH, 1, g + ly.W->off, kH, nullptr, 0,
                   0, nullptr, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(colsum_kernel, dim3(colsum_blocks(kH)), dim3(256), 0, s, nn->gh, B, kH,
                        g + ly.c->off);
     if (li < 2)
-      if ((e = gemm(B, kH, kH, ge, kH, 1, wb + ly.W->off, 1, kH, nn->gh, kH, nullptr, 0, 0,
-                    nn->ghb[(li + 1) & 1], s, lays[li + 1].act)) != hipSuccess) return e;
+      if ((e = gemm(B, kH, kH, nn->ghb, kH, 1, wb + ly.W->off, 1, kH, nn->gh, kH, nullptr, 0, 0,
+                    nullptr, s)) != hipSuccess) return e;
   }
   return hipGetLastError();
 }
@@ -1113,8 +1112,7 @@ fire_status fire_nn_create(int device, const fire_nn_cfg *cfg, uint64_t seed, fi
   if (e == hipSuccess) e = nn_alloc(nn, &nn->h3b, Bm * kH);
   if (e == hipSuccess) e = nn_alloc(nn, &nn->d0b, Bm * kDec);
   if (e == hipSuccess) e = nn_alloc(nn, &nn->dtb, Bm);
-  if (e == hipSuccess) e = nn_alloc(nn, &nn->ghb[0], Bm * kH);
-  if (e == hipSuccess) e = nn_alloc(nn, &nn->ghb[1], Bm * kH);
+  if (e == hipSuccess) e = nn_alloc(nn, &nn->ghb, Bm * kH);
   if (e == hipSuccess) e = nn_alloc(nn, &nn->h1, Bm * kH);
   if (e == hipSuccess) e = nn_alloc(nn, &nn->h2, Bm * kH);
   if (e == hipSuccess) e = nn_alloc(nn, &nn->h3, Bm * kH);
