@@ -183,8 +183,9 @@ typedef struct {
  * own persistent launch with LDS sized for it, on internal streams forked
  * from and joined back to `stream`. With several parameter vectors the
  * batch runs as one persistent launch whose simulations start in
- * decreasing order of expected fire size (burnable cells times the
- * logistic of the parameters at the landscape's mean covariates), so that
+ * decreasing order of expected fire size (burnable cells times the Eq. 1
+ * probability averaged over the landscape's forest and other burnable
+ * cells, each at the landscape's mean aspect and slope terms), so that
  * the longest fires do not start last. Results do not depend on the
  * schedule (threads, queue sizes, threshold mode), the grouping or the
  * order in which simulations run. Stream-ordered; calls on one context

@@ -1227,11 +1227,14 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
   // With several parameter vectors the simulations start in decreasing
   // order of expected fire size (longest processing time first), so that
   // the longest fires do not start last and set the launch's tail: expected
-  // size ~ burnable cells x the logistic of the parameters at the
-  // landscape's mean covariates (the wind term averages out over the eight
-  // directions). Such a batch on several landscapes runs as one launch
-  // (size classes would run one after another: each persistent launch
-  // fills the GPU). Results do not depend on the order.
+  // size ~ burnable cells x the edge ignition probability averaged over the
+  // landscape's two vegetation classes (forest and the rest), each at the
+  // landscape's mean aspect and slope terms (the wind term averages out over
+  // the eight directions). Averaging the logistic per class, not taking it
+  // at the mean covariates, keeps fires that spread through forest alone
+  // ranked with the large fires. Such a batch on several landscapes runs as
+  // one launch (size classes would run one after another: each persistent
+  // launch fills the GPU). Results do not depend on the order.
   const bool lpt = n_params > 1;
   // Size classes: simulations grouped by landscape (by size when there are
   // more landscapes than concurrent launches), each class run by its own
@@ -1282,8 +1285,10 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
         const fire_sim &sd = sims[m[j]];
         const LandscapeHost &L = c->ls[sd.landscape_id];
         const double *b = betas + 5 * (size_t)sd.param_index;
-        const double x = b[0] + b[1] * L.mean_forest + b[2] * L.mean_psi + b[4] * L.mean_sigma;
-        key[j] = {-(double)L.burnable / (1.0 + std::exp(-x)), m[j]};
+        const double x = b[0] + b[2] * L.mean_psi + b[4] * L.mean_sigma;
+        const double p = L.mean_forest / (1.0 + std::exp(-(x + b[1]))) +
+                         (1.0 - L.mean_forest) / (1.0 + std::exp(-x));
+        key[j] = {-(double)L.burnable * p, m[j]};
       }
       std::stable_sort(key.begin(), key.end(),
                        [](const std::pair<double, uint32_t> &u,
