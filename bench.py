@@ -410,6 +410,27 @@ def run_uneven(log_fn):
         tr.append(time.perf_counter() - t0)
     same_graph = bool(torch.equal(out_g, out))
     del graph
+    # the same capture over descriptors uploaded longest-expected-first
+    # (fire_order_sims, the order fire_run starts such a batch in)
+    order = g.order_sims(betas, sims)
+    d_sims_o = torch.from_numpy(sims[order].view(np.uint8).copy()).cuda()
+    out_o = torch.empty_like(out)
+    g.run_dev(d_beta, d_sims_o, 2000, SIM_SEED, out_o)
+    g.sync()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.run_dev(d_beta, d_sims_o, 2000, SIM_SEED, out_o, stream=torch.cuda.current_stream())
+    tro = []
+    for _ in range(3):
+        out_o.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        tro.append(time.perf_counter() - t0)
+    idx = torch.from_numpy(order.astype(np.int64)).cuda()
+    same_ordered = bool(torch.equal(out_o, out[idx]))
+    del graph
     # load balance of each form, from the per-simulation device clocks
     from paper_1701_03549_amd.timing import load_balance
     clocks = torch.zeros((2000, 2), dtype=torch.int64, device="cuda")
@@ -426,10 +447,13 @@ def run_uneven(log_fn):
     trials = int(r["trials"].sum())
     g.close()
     dt_g, dt_s, dt_r = float(np.median(tg)), float(np.median(ts)), float(np.median(tr))
+    dt_ro = float(np.median(tro))
     log_fn(f"uneven: grouped {dt_g * 1e3:.1f} ms, single launch {dt_s * 1e3:.1f} ms, graph replay "
-           f"{dt_r * 1e3:.1f} ms; load balance single {lb_single}, grouped {lb_grouped}")
+           f"{dt_r * 1e3:.1f} ms, ordered graph replay {dt_ro * 1e3:.1f} ms; load balance single "
+           f"{lb_single}, grouped {lb_grouped}")
     return {"sims": 2000, "lattices": [[w, h] for w, h, _ in sizes],
             "grouped_ms": dt_g * 1e3, "single_launch_ms": dt_s * 1e3, "graph_replay_ms": dt_r * 1e3,
+            "ordered_graph_replay_ms": dt_ro * 1e3, "ordered_graph_identical": same_ordered,
             "grouped_sims_per_s": 2000 / dt_g, "grouped_trials_per_s": trials / dt_g,
             "identical_results": same, "graph_identical": same_graph,
             "load_balance_single": lb_single, "load_balance_grouped": lb_grouped,

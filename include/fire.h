@@ -205,6 +205,20 @@ fire_status fire_run(fire_ctx *ctx, const double *betas, int32_t n_params,
                      const uint32_t *thresholds_override, fire_result *out,
                      uint32_t *out_maps, int64_t map_words, void *stream);
 
+/* Longest-expected-first order of a batch (host pointers, no device work):
+ * out_order [n_sims] receives the indices of sims [n_sims] sorted by
+ * decreasing expected fire size, the order fire_run starts a batch with
+ * several parameter vectors in (burnable cells times the Eq. 1 probability
+ * averaged over the landscape's forest and other burnable cells, each at
+ * the landscape's mean aspect and slope terms; ties keep input order).
+ * For fire_run_dev callers, e.g. a batch captured into a graph: upload the
+ * descriptors in this order and row k of the results belongs to
+ * sims[out_order[k]]. Results of a simulation do not depend on its place
+ * in the batch. Descriptors are checked as by fire_run (FIRE_E_INVALID);
+ * betas [n_params][5] must be finite. */
+fire_status fire_order_sims(fire_ctx *ctx, const double *betas, int32_t n_params,
+                            const fire_sim *sims, int32_t n_sims, int32_t *out_order);
+
 /* Per-cell form of the simulation, after the paper's own kernel, kept as
  * an ablation and paper-style baseline of fire_run (CUDA-implementation
  * section; Methods, propagation rules): one thread per cell sweeps the

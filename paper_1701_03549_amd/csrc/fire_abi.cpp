@@ -1198,6 +1198,42 @@ static fire_status build_tables(fire_ctx *c, int lid, const double *betas_dev,
   return FIRE_OK;
 }
 
+// Expected fire size of a simulation on landscape L under parameters b, the
+// key of the longest-expected-first order: burnable cells x the Eq. 1
+// probability averaged over the forest and the other burnable cells, each
+// at the landscape's mean aspect and slope terms (the wind term averages out
+// over the eight directions).
+static double expected_size(const LandscapeHost &L, const double *b) {
+  const double x = b[0] + b[2] * L.mean_psi + b[4] * L.mean_sigma;
+  const double p = L.mean_forest / (1.0 + std::exp(-(x + b[1]))) +
+                   (1.0 - L.mean_forest) / (1.0 + std::exp(-x));
+  return (double)L.burnable * p;
+}
+
+fire_status fire_order_sims(fire_ctx *c, const double *betas, int32_t n_params,
+                            const fire_sim *sims, int32_t n_sims, int32_t *out_order) {
+  if (!c) return FIRE_E_INVALID;
+  if (n_sims < 0 || n_params < 1 || !betas || (n_sims > 0 && (!sims || !out_order)))
+    return fail(c, FIRE_E_INVALID, "bad sizes or null pointers");
+  for (int64_t i = 0; i < (int64_t)n_params * 5; ++i)
+    if (!std::isfinite(betas[i])) return fail(c, FIRE_E_INVALID, "non-finite beta %lld", (long long)i);
+  if (n_sims == 0) return FIRE_OK;
+  int bw = 0, one_ls = -1;
+  int64_t mc = 1;
+  fire_status st0 = check_sims_host(c, sims, n_sims, n_params, &bw, &mc, &one_ls, 0, false);
+  if (st0 != FIRE_OK) return st0;
+  std::vector<std::pair<double, int32_t>> key(n_sims);
+  for (int32_t i = 0; i < n_sims; ++i)
+    key[i] = {-expected_size(c->ls[sims[i].landscape_id], betas + 5 * (size_t)sims[i].param_index),
+              i};
+  std::stable_sort(key.begin(), key.end(),
+                   [](const std::pair<double, int32_t> &u, const std::pair<double, int32_t> &v) {
+                     return u.first < v.first;
+                   });
+  for (int32_t i = 0; i < n_sims; ++i) out_order[i] = key[i].second;
+  return FIRE_OK;
+}
+
 fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
                      const fire_sim *sims, int32_t n_sims, uint64_t seed,
                      const uint32_t *override_T, fire_result *out,
@@ -1226,13 +1262,10 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
 
   // With several parameter vectors the simulations start in decreasing
   // order of expected fire size (longest processing time first), so that
-  // the longest fires do not start last and set the launch's tail: expected
-  // size ~ burnable cells x the edge ignition probability averaged over the
-  // landscape's two vegetation classes (forest and the rest), each at the
-  // landscape's mean aspect and slope terms (the wind term averages out over
-  // the eight directions). Averaging the logistic per class, not taking it
-  // at the mean covariates, keeps fires that spread through forest alone
-  // ranked with the large fires. Such a batch on several landscapes runs as
+  // the longest fires do not start last and set the launch's tail
+  // (expected_size; averaging the logistic per vegetation class, not taking
+  // it at the mean covariates, keeps fires that spread through forest alone
+  // ranked with the large fires). Such a batch on several landscapes runs as
   // one launch (size classes would run one after another: each persistent
   // launch fills the GPU). Results do not depend on the order.
   const bool lpt = n_params > 1;
@@ -1283,12 +1316,8 @@ fire_status fire_run(fire_ctx *c, const double *betas, int32_t n_params,
       key.resize(m.size());
       for (size_t j = 0; j < m.size(); ++j) {
         const fire_sim &sd = sims[m[j]];
-        const LandscapeHost &L = c->ls[sd.landscape_id];
-        const double *b = betas + 5 * (size_t)sd.param_index;
-        const double x = b[0] + b[2] * L.mean_psi + b[4] * L.mean_sigma;
-        const double p = L.mean_forest / (1.0 + std::exp(-(x + b[1]))) +
-                         (1.0 - L.mean_forest) / (1.0 + std::exp(-x));
-        key[j] = {-(double)L.burnable * p, m[j]};
+        key[j] = {-expected_size(c->ls[sd.landscape_id], betas + 5 * (size_t)sd.param_index),
+                  m[j]};
       }
       std::stable_sort(key.begin(), key.end(),
                        [](const std::pair<double, uint32_t> &u,

@@ -29,7 +29,7 @@ STATUS = {0: "FIRE_OK", -1: "FIRE_E_INVALID", -2: "FIRE_E_OOM", -3: "FIRE_E_DEVI
 EXPORTS = ["fire_ctx_create", "fire_ctx_destroy", "fire_last_error", "fire_sync", "fire_version",
            "fire_landscape_load", "fire_landscape_free", "fire_landscape_set_burn_steps",
            "fire_target_load", "fire_target_free",
-           "fire_thresholds", "fire_thresholds_dev", "fire_run", "fire_run_dev", "fire_run_dev_noalloc", "fire_run_dense",
+           "fire_thresholds", "fire_thresholds_dev", "fire_run", "fire_order_sims", "fire_run_dev", "fire_run_dev_noalloc", "fire_run_dense",
            "fire_set_sim_timing",
            "fire_set_schedule",
            "fire_get_schedule", "fire_set_class_schedule", "fire_ga_step", "fire_ga_offspring", "fire_ga_step_genes",
@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "fire_thresholds": (i32, [vp, i32, vp, vp, vp]),
         "fire_thresholds_dev": (i32, [vp, i32, vp, i32, vp, vp]),
         "fire_run": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
+        "fire_order_sims": (i32, [vp, vp, i32, vp, i32, vp]),
         "fire_run_dev": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_run_dev_noalloc": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, vp, i64, vp]),
         "fire_run_dense": (i32, [vp, vp, i32, vp, i32, u64, vp, vp, i64, vp]),
@@ -270,6 +271,15 @@ class FireGPU:
                                       int(seed) & (2 ** 64 - 1), _ptr(override), _ptr(res),
                                       _ptr(maps), mw, _stream(stream)))
         return res[:n], maps
+
+    def order_sims(self, betas, sims: np.ndarray) -> np.ndarray:
+        """fire_order_sims: the longest-expected-first permutation of host descriptors."""
+        b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64).reshape(-1, 5))
+        s = np.ascontiguousarray(sims, dtype=SIM_DTYPE)
+        order = np.empty(max(len(s), 1), dtype=np.int32)
+        self._check(self.lib.fire_order_sims(self.ctx, b.ctypes.data, len(b), s.ctypes.data,
+                                             len(s), order.ctypes.data))
+        return order[:len(s)]
 
     def run_dense(self, betas, sims: np.ndarray, seed: int, want_maps: bool = False,
                   stream=None):

@@ -195,3 +195,61 @@ def test_sim_timing_clocks(g):
         g.set_sim_timing(torch.zeros(8, dtype=torch.int64, device="cuda"))
     for lid in lids:
         g.free_landscape(lid)
+
+
+def test_ordered_descriptors_captured_match_fire_run(g):
+    """fire_order_sims gives the longest-expected-first permutation fire_run
+    uses (checked against its documented key); a captured fire_run_dev over
+    descriptors uploaded in that order reproduces fire_run's rows."""
+    import torch
+    lss, lids, betas, which, sims = _mixed(g, n=60)
+    n = len(sims)
+    say("order_sims")
+    order = g.order_sims(betas, sims)
+    assert sorted(order.tolist()) == list(range(n))
+    # the documented key: burnable cells x the Eq. 1 probability averaged
+    # over forest and other burnable cells at the mean aspect and slope terms
+    sig = lambda v: 1.0 / (1.0 + np.exp(-v))
+    key = np.empty(n)
+    for i in range(n):
+        ls = lss[which[i]]
+        veg = ls["veg"].ravel()
+        m = veg != 0
+        sl = ls["slope_deg"].ravel()[m].astype(np.float64)
+        asp = ls["aspect_deg"].ravel()[m].astype(np.float64)
+        nb = m.sum()
+        mf = (veg[m] == 1).sum() / nb
+        psi = np.where(sl > 5.0, np.cos((asp - 315.0) * np.pi / 180.0), 0.0).sum() / nb
+        sgm = (0.5 * sl / 100.0).sum() / nb
+        b = betas[sims[i]["param_index"]]
+        x = b[0] + b[2] * psi + b[4] * sgm
+        key[i] = nb * (mf * sig(x + b[1]) + (1.0 - mf) * sig(x))
+    k = key[order]
+    assert np.all(k[1:] <= k[:-1] * (1 + 1e-9) + 1e-9)
+    res, _ = g.run(betas, sims, SEED)
+    g.sync()
+    d_sims = torch.from_numpy(sims[order].view(np.uint8).copy()).cuda()
+    d_beta = torch.from_numpy(betas.copy()).cuda()
+    out = torch.empty((n, 24), dtype=torch.uint8, device="cuda")
+    g.run_dev(d_beta, d_sims, n, SEED, out)
+    g.sync()
+    idx = torch.from_numpy(order.astype(np.int64)).cuda()
+    assert torch.equal(out, res[idx])
+    out_g = torch.empty_like(out)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.run_dev(d_beta, d_sims, n, SEED, out_g, stream=torch.cuda.current_stream())
+    for _ in range(2):
+        out_g.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out_g, res[idx])
+    del graph
+    bad = sims.copy()
+    bad[3]["landscape_id"] = 999
+    with pytest.raises(Exception):
+        g.order_sims(betas, bad)
+    assert len(g.order_sims(betas, sims[:0])) == 0
+    for lid in lids:
+        g.free_landscape(lid)
